@@ -1,0 +1,224 @@
+"""Benchmark: per-TF rebuild + 1080p render on the 512^3 float32 noise volume.
+
+Workload (one step): bind the volume (brick min/max), set the next TF of a
+100-TF sequence and rebuild the macrocell grid, the LBVH and the binned k-d
+tree, then render 1920x1080 with each of the three.  The camera orbits 3.6
+degrees per TF.  Inputs are synthetic (seeded fractal value noise, ~5 %
+non-empty voxels, 16^3 bricks) and resident in HBM before timing starts.
+
+Prints one JSON line.  ``value`` = rays rendered per second over the whole
+step (Mrays/s, all three renders, rebuilds and the min/max pass included).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+W, H = 1920, 1080
+DIMS = (512, 512, 512)
+BRICK = 16
+KD = dict(halting=1, max_leaf=32, bins=4)
+ACCELS = ("grid", "lbvh", "kd")
+# algorithmic FP32 operations per composited sample (counted from the
+# formulas: lattice t 3, point 6, trilinear 30, normalise 5, TF lerp 13,
+# opacity correction 5, compositing 9)
+FLOP_PER_SAMPLE = 71
+PEAK_FP32_TFLOPS = 157.3
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    i = min(len(xs) - 1, max(0, int(round(q / 100.0 * (len(xs) - 1)))))
+    return xs[i]
+
+
+def cpu_baseline(vol, tfs, stride=4):
+    """The CPU oracle on this host: one step of the same workload, with every
+    `stride`-th pixel of each 1080p frame rendered (full march, FP64)."""
+    import numpy as np
+
+    import oracle
+    import synth
+
+    threads = oracle.lib().orc_threads()
+    tf = tfs[0]
+    cam = synth.c2_camera(0)
+    t0 = time.perf_counter()
+    mn, mx = oracle.brick_minmax(vol, BRICK)
+    flags = oracle.classify(mn, mx, vol.dtype, tf)
+    ids = oracle.compact(flags)
+    nb = oracle.brick_grid(DIMS, BRICK)
+    k, i = oracle.sort_pairs(oracle.morton_keys(ids, nb[0], nb[1]), ids)
+    oracle.lbvh(k, i, BRICK, DIMS)
+    oracle.kd(flags, BRICK, DIMS, KD["halting"], KD["max_leaf"], KD["bins"])
+    idx = np.arange(0, W * H, stride)
+    pix = np.stack([idx % W, idx // W], 1).astype(np.int32)
+    rays = 0
+    for _ in ACCELS:
+        oracle.render(vol, tf, cam, W, H, 0.5, 1.0, pixels=pix)
+        rays += pix.shape[0]
+    dt = time.perf_counter() - t0
+    return {"value": rays / dt / 1e6, "unit": "Mrays/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"one step (min/max, classify, LBVH, k-d, 3 full-march renders of every "
+                      f"{stride}th pixel of the 1920x1080 frame = {rays} rays) in {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-stride", type=int, default=4)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1912_09596_amd as esk
+    import synth
+
+    log("generating 512^3 noise volume and 100 TFs")
+    vol = synth.fractal_noise(DIMS, seed=2)
+    tfs = synth.c2_tfs(100)
+    dev = torch.device("cuda", 0)
+    dvol = torch.from_numpy(vol).to(dev)
+    dtfs = [torch.from_numpy(t).to(dev) for t in tfs]
+    cams = [synth.c2_camera(i) for i in range(100)]
+    ctx = esk.Context(0)
+    ws = torch.empty(esk.workspace_bytes(DIMS, esk.F32, BRICK, 256), dtype=torch.uint8, device=dev)
+    outs = {a: torch.empty((H, W, 4), dtype=torch.float32, device=dev) for a in ACCELS}
+    kd = esk.Kd(**KD)
+    stream = torch.cuda.current_stream()
+
+    def step(i, ev=None):
+        j = i % 100
+        ctx.set_volume(dvol, BRICK, (0.0, 1.0), max_tf=256, workspace=ws)
+        ctx.set_tf(dtfs[j], build=ACCELS, kd=kd)
+        for a in ACCELS:
+            if ev is not None:
+                ev[a][0].record(stream)
+            ctx.render(cams[j], W, H, accel=a, step=0.5, ref=1.0, out=outs[a])
+            if ev is not None:
+                ev[a][1].record(stream)
+
+    log(f"warmup {args.warmup}")
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+
+    events = [{a: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for a in ACCELS} for _ in range(args.steps)]
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(args.warmup + i, events[i])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    render_ms = {a: [events[i][a][0].elapsed_time(events[i][a][1]) for i in range(args.steps)]
+                 for a in ACCELS}
+    rays = len(ACCELS) * W * H * args.steps
+    value = rays / elapsed / 1e6
+
+    # per-phase breakdown (outside the timed region)
+    log("phase breakdown")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    sv = []
+    for _ in range(5):
+        e0.record(stream)
+        ctx.set_volume(dvol, BRICK, (0.0, 1.0), max_tf=256, workspace=ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sv.append(e0.elapsed_time(e1))
+    rebuild = {}
+    for a in ACCELS:
+        times = []
+        for i in range(min(args.steps, 100)):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            ctx.set_tf(dtfs[i % 100], build=(a,), kd=kd)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t) * 1e3)
+        rebuild[a] = {"median_ms": statistics.median(times), "p99_ms": percentile(times, 99)}
+    # samples per frame (composited) for the dominant-kernel roofline
+    j = (args.warmup + args.steps - 1) % 100
+    ctx.set_tf(dtfs[j], build=ACCELS, kd=kd)
+    samples = {}
+    cnt = torch.empty((H, W), dtype=torch.int32, device=dev)
+    for a in ACCELS + ("none",):
+        ctx.render(cams[j], W, H, accel=a, out=outs.get(a, outs["lbvh"]), counts=cnt)
+        samples[a] = int(cnt.sum().item())
+    naive = []
+    for _ in range(3):
+        e0.record(stream)
+        ctx.render(cams[j], W, H, accel="none", out=outs["lbvh"])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        naive.append(e0.elapsed_time(e1))
+    st = ctx.stats()
+
+    mean_ms = {a: statistics.mean(render_ms[a]) for a in ACCELS}
+    dominant = max(ACCELS, key=lambda a: mean_ms[a])
+    # the same frame's sample count stands in for every step (same TF sequence position)
+    flops = samples[dominant] * FLOP_PER_SAMPLE
+    achieved = flops / (statistics.median(render_ms[dominant]) * 1e-3) / 1e12
+    result = {
+        "metric": "Mrays/s at 1080p + rebuild ms per TF change; batched vs plain, RGBA err≤1e-3",
+        "value": round(value, 2),
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "512^3 float32 fractal-noise volume (~5% non-empty), 16^3 bricks, "
+                               "100-TF sequence, 1920x1080 perspective, grid + LBVH + binned k-d "
+                               "(deep, MLS 32) rebuilt and rendered per TF",
+                   "image": [W, H], "brick": BRICK, "step_voxels": 0.5, "path": "plain"},
+        "phases": {
+            "set_volume_ms": round(statistics.median(sv), 4),
+            "rebuild": {a: {k: round(v, 4) for k, v in rebuild[a].items()} for a in ACCELS},
+            "render_ms": {a: round(statistics.median(render_ms[a]), 4) for a in ACCELS},
+            "render_mrays_per_s": {a: round(W * H / statistics.median(render_ms[a]) / 1e3, 1)
+                                   for a in ACCELS},
+            "naive_render_ms": round(statistics.median(naive), 4),
+            "naive_mrays_per_s": round(W * H / statistics.median(naive) / 1e3, 1),
+            "samples_per_frame": samples,
+            "bricks_nonempty": st["n_nonempty"], "lbvh_nodes": st["lbvh_nodes"],
+            "lbvh_height": st["lbvh_height"], "kd_nodes": st["kd_nodes"], "kd_height": st["kd_height"],
+        },
+        "roofline": {"kernel": f"k_render<{dominant}>", "bound": "alu", "achieved": round(achieved, 3),
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP32_TFLOPS, 5), "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        result["cpu_baseline"] = cpu_baseline(vol, tfs, args.cpu_stride)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

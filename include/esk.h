@@ -1,0 +1,195 @@
+/*
+ * esk.h -- C ABI of the MI355X empty-space-skipping library.
+ *
+ * Implements the data-parallel hot path studied in "Comparing Hierarchical
+ * Data Structures for Sparse Volume Rendering with Empty Space Skipping"
+ * (Zellmann et al., arXiv 1912.09596): whenever the transfer function (TF)
+ * changes, rebuild an empty-space-skipping hierarchy over a uniform scalar
+ * volume (Sec. 1: the amount and arrangement of empty space change with the
+ * alpha TF), then ray-march the volume, traversing the hierarchy to skip the
+ * empty regions (Sec. 3, Sec. 4.1).
+ *
+ * Conventions
+ *  - Voxel (x,y,z) of an nx*ny*nz volume lives at x + nx*(y + ny*z).
+ *  - Bricks have edge B (a power of two, 4..32); brick (bx,by,bz) covers the
+ *    voxels [B*b, min(B*b+B, n)) on each axis; its linear id is
+ *    bx + nbx*(by + nby*bz) with nbx = ceil(nx/B) (likewise y, z).  At most 1024 bricks per
+ *    axis (10 bits per axis of the 30-bit Morton code, Sec. 3.1).
+ *  - Transfer functions are N x RGBA float32, N in [2, 4096]; entry i sits at
+ *    the normalised value i/(N-1).  Normalised value s(v): v/255 (u8),
+ *    v/65535 (u16), clamp((v-lo)/(hi-lo), 0, 1) (f16, f32).
+ *  - Images are H x W x RGBA float32, row 0 at the top, premultiplied colour.
+ *  - Device pointers are HIP device addresses on the context's device.  All
+ *    device memory is owned by the caller; the library borrows it and never
+ *    allocates device memory.  Host pointers are plain host memory.
+ *
+ * Errors: every entry point returns an esk_status.  Arguments are validated on
+ * the host before any device work is enqueued; a rejected call changes no
+ * state.  Enqueued work is asynchronous on the context's stream; a device
+ * fault surfaces as ESK_EDEVICE at the next call that synchronises
+ * (esk_sync, esk_get_stats, esk_export, or a k-d rebuild).  esk_last_error
+ * returns a human-readable reason for the last failure on a context.
+ *
+ * Threading: a context is used by one host thread at a time.
+ */
+#ifndef ESK_H
+#define ESK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct esk_ctx esk_ctx;
+
+typedef enum {
+    ESK_OK = 0,
+    ESK_EINVAL = -1,    /* bad argument */
+    ESK_ENOSPC = -2,    /* workspace smaller than esk_workspace_bytes() */
+    ESK_ELIMIT = -3,    /* size beyond a documented limit (bricks/axis, TF entries) */
+    ESK_EDEVICE = -4,   /* HIP runtime error or device fault */
+    ESK_ESTATE = -5,    /* call out of order (no volume / no TF / accel not built) */
+    ESK_EINTERNAL = -6
+} esk_status;
+
+typedef enum { ESK_U8 = 0, ESK_U16 = 1, ESK_F16 = 2, ESK_F32 = 3 } esk_dtype;
+
+/* Acceleration structures.  Values are bits so a rebuild can build several. */
+typedef enum {
+    ESK_ACCEL_NONE = 0, /* full march, no skipping (the paper's "naive" column) */
+    ESK_ACCEL_GRID = 1, /* uniform macrocell grid, macrocell = brick (Sec. 1) */
+    ESK_ACCEL_LBVH = 2, /* LBVH over non-empty bricks (Sec. 3.1) */
+    ESK_ACCEL_KD = 4    /* binned k-d tree over brick occupancy (Sec. 3.2.2, 4.3) */
+} esk_accel;
+
+/* k-d build parameters (Sec. 4.3).
+ *  halting:  0 = shallow: split only while 10*V(node) > V(root);
+ *            1 = deep:    split only while V(node) > 8^3 voxels.
+ *  max_leaf: 0 = off; else when the cost function says "leaf" and
+ *            V(node) > max_leaf^3, split at the middle of the axis with the
+ *            largest extent (the maximum-leaf-size rule).
+ *  bins:     candidate planes lie on the bin boundaries lo + floor(j*e/bins),
+ *            j = 1..bins-1, of the node's brick extent e on each axis
+ *            (Sec. 3.2.2 uses 4); 2..16. */
+typedef struct {
+    int32_t halting;
+    int32_t max_leaf;
+    int32_t bins;
+} esk_kd_params;
+
+/* Camera basis, precomputed by the caller in FP32.  Pixel (x, y) has
+ *   perspective:  origin eye,                    direction dir00 + (x+.5) du + (y+.5) dv
+ *   orthographic: origin eye + (x+.5) du + (y+.5) dv, direction dir00
+ * and the direction is normalised (Sec. 4.1 renders orthographic views; the
+ * perspective form is the other common case). */
+typedef struct {
+    int32_t ortho;
+    float eye[3];
+    float dir00[3];
+    float du[3];
+    float dv[3];
+} esk_camera;
+
+typedef struct {
+    int64_t n_bricks;    /* nbx*nby*nbz */
+    int64_t n_nonempty;  /* bricks flagged by the last rebuild */
+    int64_t lbvh_nodes;  /* 2N-1 (0 if N = 0), if the LBVH was built */
+    int64_t kd_nodes;    /* k-d node count, if the k-d tree was built */
+    int32_t lbvh_height; /* levels; a single leaf has height 1 */
+    int32_t kd_height;
+    int32_t nb[3];
+    int32_t built;       /* esk_accel bits built by the last rebuild */
+} esk_stats;
+
+/* What esk_export copies out (all little-endian host arrays). */
+typedef enum {
+    ESK_X_MINMAX = 0,     /* 2*nb values in the volume dtype: all minima, then all maxima */
+    ESK_X_TF_PREFIX = 1,  /* int32[N+1]: P[i] = #{j < i : alpha_j > 0} */
+    ESK_X_FLAGS = 2,      /* uint8[nb]: 1 = brick may hold a visible sample */
+    ESK_X_IDS = 3,        /* uint32[N]: non-empty brick ids, ascending */
+    ESK_X_KEYS = 4,       /* uint32[N]: Morton keys of ESK_X_IDS, same order */
+    ESK_X_SORTED_KEYS = 5,/* uint32[N]: keys ascending */
+    ESK_X_SORTED_IDS = 6, /* uint32[N]: brick ids in sorted-key order (LBVH leaves) */
+    ESK_X_LBVH_LEFT = 7,  /* uint32[N-1]: left child; bit 31 set = leaf index */
+    ESK_X_LBVH_RIGHT = 8, /* uint32[N-1] */
+    ESK_X_LBVH_AXIS = 9,  /* int32[N-1]: axis of the highest differing key bit */
+    ESK_X_LBVH_LO = 10,   /* int32[N-1][3]: internal node AABB min, voxels */
+    ESK_X_LBVH_HI = 11,   /* int32[N-1][3]: internal node AABB max (exclusive) */
+    ESK_X_KD_LO = 12,     /* int32[M][3]: k-d node tight box min, bricks, BFS order */
+    ESK_X_KD_HI = 13,     /* int32[M][3]: max (exclusive) */
+    ESK_X_KD_AXIS = 14,   /* int32[M]: split axis, -1 = leaf */
+    ESK_X_KD_PLANE = 15,  /* int32[M]: split plane in bricks (0 for leaves) */
+    ESK_X_KD_FIRST = 16,  /* int32[M]: index of the left child (right = +1), -1 for leaves */
+    ESK_X_GRID = 17       /* uint32[ceil(nb/32)]: bit (i%32) of word i/32 = flag of brick i */
+} esk_export_what;
+
+/* Creates a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  device = -1 creates a
+ * validation-only context that checks arguments exactly as a device context
+ * does and then returns ESK_ESTATE instead of touching any device.  The
+ * context allocates pinned host memory for small read-backs only. */
+esk_status esk_create(int device, void *hip_stream, esk_ctx **out);
+esk_status esk_destroy(esk_ctx *ctx);
+
+/* Pure host: bytes of device workspace esk_set_volume needs for this shape,
+ * brick size and largest TF the caller will set. */
+esk_status esk_workspace_bytes(int nx, int ny, int nz, int dtype, int brick, int max_tf_entries,
+                               size_t *out);
+
+/* Binds a volume and computes the per-brick min/max of raw values over each
+ * brick plus a one-voxel apron (the trilinear footprint of the samples the
+ * brick owns): the TF-independent half of classification (Sec. 2 min-max
+ * range queries; Sec. 3.1 bricks).  d_vox: nx*ny*nz voxels of `dtype`;
+ * value_lo < value_hi map f16/f32 values to [0,1] (ignored for u8/u16).
+ * d_ws: caller-owned workspace of ws_bytes >= esk_workspace_bytes(...).
+ * Both must stay alive (in stream order) until the next esk_set_volume or
+ * esk_destroy.  Invalidates any previous TF/hierarchy. */
+esk_status esk_set_volume(esk_ctx *ctx, const void *d_vox, int dtype, int nx, int ny, int nz,
+                          float value_lo, float value_hi, int brick, int max_tf_entries,
+                          void *d_ws, size_t ws_bytes);
+
+/* Sets the TF and rebuilds (Sec. 3.1, 3.2.2): TF prefix count -> brick
+ * classification -> grid bitmask -> compaction -> Morton codes -> radix sort
+ * -> Karras hierarchy -> AABB refit (if ESK_ACCEL_LBVH in build_mask), and the
+ * 3-D occupancy prefix count -> level-synchronous binned k-d build (if
+ * ESK_ACCEL_KD).  d_rgba: N x RGBA float32 on the device, copied into the
+ * workspace (the caller may reuse it once the stream reaches this point).
+ * kd may be NULL when ESK_ACCEL_KD is not requested.  Asynchronous, except
+ * that a k-d build reads its level counts back to the host. */
+esk_status esk_set_transfer_function(esk_ctx *ctx, const float *d_rgba, int n_entries,
+                                     int build_mask, const esk_kd_params *kd);
+
+/* Renders W x H pixels with `accel` (ESK_ACCEL_NONE, or one structure built by
+ * the last rebuild): emission-absorption ray marching with post-classification
+ * and no early ray termination or shading (Sec. 4.1).  Samples lie at
+ * t_k = t0 + (k+1/2)*step along each ray, t0 = max(0, volume entry); a sample
+ * at p counts iff p is in [0,n)^3; its value is the cell-centred trilinear
+ * interpolation (clamp to edge), looked up in the TF with linear
+ * interpolation; alpha is corrected to 1-(1-a)^(step/opacity_ref_step)
+ * (opacity_ref_step = 0: no correction) and composited front to back.
+ * Skipping never changes the image: skipped samples have alpha exactly 0.
+ * d_rgba_out: H*W*4 float32.  d_count_out (nullable): H*W int32, the number of
+ * samples composited per pixel. */
+esk_status esk_render(esk_ctx *ctx, int accel, const esk_camera *cam, int width, int height,
+                      float step, float opacity_ref_step, float *d_rgba_out, int32_t *d_count_out);
+
+/* Waits for the context's stream; reports device faults. */
+esk_status esk_sync(esk_ctx *ctx);
+
+/* Synchronises and fills *out. */
+esk_status esk_get_stats(esk_ctx *ctx, esk_stats *out);
+
+/* Synchronises and copies one array of the current state into `host`
+ * (capacity cap bytes); *used receives the byte count (also when cap is too
+ * small, which returns ESK_ENOSPC). */
+esk_status esk_export(esk_ctx *ctx, int what, void *host, size_t cap, size_t *used);
+
+const char *esk_strerror(esk_status s);
+const char *esk_last_error(const esk_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ESK_H */

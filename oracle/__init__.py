@@ -81,6 +81,7 @@ def lib():
                                     P, i64, P, P]
         _lib.orc_ray.argtypes = [ctypes.POINTER(Camera), i32, i32, P, P]
         _lib.orc_sample.argtypes = [P, i32, i32, i32, i32, f32, f32, P, i32, P, i64, P]
+        _lib.orc_threads.argtypes = []
     return _lib
 
 

@@ -131,9 +131,13 @@ static int64_t tf_floor_index(double v, int dtype, float lo, float hi, int N)
 
 /* ------------------------------------------------------------------------ */
 /* a3: brick classification.  A brick is non-empty iff some entry in         */
-/* [floor(x(min))-1, floor(x(max))+1] clamped to [0,N-1] has alpha > 0.      */
+/* [floor(x(min))-1, floor(x(max))+2] clamped to [0,N-1] has alpha > 0.      */
 /* Sec. 3.1: bricks are classified visible/invisible under the current       */
-/* transfer function whenever it changes.                                    */
+/* transfer function whenever it changes.  The window is every entry a       */
+/* sample owned by the brick can read with a non-zero lerp weight: a value   */
+/* in [min, max] reads entries floor(x) and ceil(x) <= floor(x(max)) + 1,   */
+/* and one more entry on each side absorbs rounding of the interpolated     */
+/* value (ceil of a value rounded just past an integer).                     */
 /* ------------------------------------------------------------------------ */
 int64_t orc_classify(const double *mn, const double *mx, int64_t nb, int dtype, float lo,
                      float hi, const float *tf, int N, uint8_t *flags)
@@ -145,7 +149,7 @@ int64_t orc_classify(const double *mn, const double *mx, int64_t nb, int dtype, 
     int64_t count = 0;
     for (int64_t b = 0; b < nb; ++b) {
         int64_t a = tf_floor_index(mn[b], dtype, lo, hi, N) - 1;
-        int64_t c = tf_floor_index(mx[b], dtype, lo, hi, N) + 1;
+        int64_t c = tf_floor_index(mx[b], dtype, lo, hi, N) + 2;
         if (a < 0) a = 0;
         if (c > N - 1) c = N - 1;
         flags[b] = (P[c + 1] - P[a]) > 0 ? 1 : 0;
@@ -649,4 +653,17 @@ int orc_sample(const void *vol, int dtype, int nx, int ny, int nz, float vlo, fl
         }
     }
     return 0;
+}
+
+/* threads the OpenMP loops of this library use (for reporting) */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -1,0 +1,253 @@
+"""MI355X-native empty-space skipping for volume ray marching.
+
+Thin ctypes binding over ``libesk.so`` (C ABI in ``include/esk.h``): argument
+marshalling only.  Every step of the hot path -- brick min/max, TF prefix
+count, classification, compaction, Morton codes, radix sort, Karras LBVH,
+AABB refit, binned k-d build, macrocell grid and the ray marcher -- runs in
+the library's HIP kernels.  PyTorch provides device memory and the stream.
+
+There is no fallback: if ``libesk.so`` is missing or cannot be loaded, every
+entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libesk.so")
+
+OK, EINVAL, ENOSPC, ELIMIT, EDEVICE, ESTATE, EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+U8, U16, F16, F32 = 0, 1, 2, 3
+NONE, GRID, LBVH, KD = 0, 1, 2, 4
+ACCEL = {"none": NONE, "grid": GRID, "lbvh": LBVH, "kd": KD}
+LEAF = 0x80000000
+
+EXPORTS = {
+    "minmax": 0, "tf_prefix": 1, "flags": 2, "ids": 3, "keys": 4, "sorted_keys": 5, "sorted_ids": 6,
+    "lbvh_left": 7, "lbvh_right": 8, "lbvh_axis": 9, "lbvh_lo": 10, "lbvh_hi": 11,
+    "kd_lo": 12, "kd_hi": 13, "kd_axis": 14, "kd_plane": 15, "kd_first": 16, "grid": 17,
+}
+_EXPORT_DTYPE = {
+    "tf_prefix": (np.int32, 1), "flags": (np.uint8, 1), "ids": (np.uint32, 1), "keys": (np.uint32, 1),
+    "sorted_keys": (np.uint32, 1), "sorted_ids": (np.uint32, 1), "lbvh_left": (np.uint32, 1),
+    "lbvh_right": (np.uint32, 1), "lbvh_axis": (np.int32, 1), "lbvh_lo": (np.int32, 3),
+    "lbvh_hi": (np.int32, 3), "kd_lo": (np.int32, 3), "kd_hi": (np.int32, 3), "kd_axis": (np.int32, 1),
+    "kd_plane": (np.int32, 1), "kd_first": (np.int32, 1), "grid": (np.uint32, 1),
+}
+
+
+class EskError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"esk status {status}: {msg}")
+        self.status = status
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("ortho", ctypes.c_int32), ("eye", ctypes.c_float * 3),
+                ("dir00", ctypes.c_float * 3), ("du", ctypes.c_float * 3),
+                ("dv", ctypes.c_float * 3)]
+
+
+class KdParams(ctypes.Structure):
+    _fields_ = [("halting", ctypes.c_int32), ("max_leaf", ctypes.c_int32), ("bins", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_bricks", ctypes.c_int64), ("n_nonempty", ctypes.c_int64),
+                ("lbvh_nodes", ctypes.c_int64), ("kd_nodes", ctypes.c_int64),
+                ("lbvh_height", ctypes.c_int32), ("kd_height", ctypes.c_int32),
+                ("nb", ctypes.c_int32 * 3), ("built", ctypes.c_int32)]
+
+
+@dataclass
+class Kd:
+    """k-d build parameters: halting 0 = shallow (10 % of root), 1 = deep
+    (8^3); max_leaf 0 = off, else the maximum-leaf-size edge; bins per axis."""
+    halting: int = 1
+    max_leaf: int = 0
+    bins: int = 4
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Loads libesk.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -c 'import __graft_entry__ as g; g.build()'`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, f32, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_size_t
+    L.esk_create.argtypes = [i32, P, ctypes.POINTER(P)]
+    L.esk_destroy.argtypes = [P]
+    L.esk_workspace_bytes.argtypes = [i32, i32, i32, i32, i32, i32, ctypes.POINTER(sz)]
+    L.esk_set_volume.argtypes = [P, P, i32, i32, i32, i32, f32, f32, i32, i32, P, sz]
+    L.esk_set_transfer_function.argtypes = [P, P, i32, i32, ctypes.POINTER(KdParams)]
+    L.esk_render.argtypes = [P, i32, ctypes.POINTER(Camera), i32, i32, f32, f32, P, P]
+    L.esk_sync.argtypes = [P]
+    L.esk_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
+    L.esk_export.argtypes = [P, i32, P, sz, ctypes.POINTER(sz)]
+    L.esk_strerror.argtypes = [i32]
+    L.esk_strerror.restype = ctypes.c_char_p
+    L.esk_last_error.argtypes = [P]
+    L.esk_last_error.restype = ctypes.c_char_p
+    for name in ("esk_create", "esk_destroy", "esk_workspace_bytes", "esk_set_volume",
+                 "esk_set_transfer_function", "esk_render", "esk_sync", "esk_get_stats", "esk_export"):
+        getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+def _dtype_code(t) -> int:
+    import torch
+    codes = {torch.uint8: U8, torch.uint16: U16, torch.float16: F16, torch.float32: F32}
+    if t.dtype not in codes:
+        raise TypeError(f"unsupported volume dtype {t.dtype}")
+    return codes[t.dtype]
+
+
+def workspace_bytes(dims_xyz, dtype_code: int, brick: int, max_tf: int = 4096) -> int:
+    out = ctypes.c_size_t()
+    st = lib().esk_workspace_bytes(int(dims_xyz[0]), int(dims_xyz[1]), int(dims_xyz[2]),
+                                   dtype_code, brick, max_tf, ctypes.byref(out))
+    if st != OK:
+        raise EskError(st, lib().esk_strerror(st).decode())
+    return out.value
+
+
+def camera_struct(cam: dict) -> Camera:
+    c = Camera()
+    c.ortho = int(cam["ortho"])
+    for name in ("eye", "dir00", "du", "dv"):
+        v = np.asarray(cam[name], dtype=np.float32)
+        getattr(c, name)[:] = [float(x) for x in v]
+    return c
+
+
+class Context:
+    """One rendering context: a bound volume, its workspace, the current TF
+    and the hierarchies built for it.  device=-1 gives a validation-only
+    context (no GPU needed) that checks arguments and then reports ESTATE."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self._lib = lib()
+        self._ctx = ctypes.c_void_p()
+        self.device = device
+        if device >= 0:
+            import torch
+            if stream is None:
+                stream = torch.cuda.current_stream(device)
+            handle = ctypes.c_void_p(stream.cuda_stream)
+        else:
+            handle = ctypes.c_void_p(0)
+        self.stream = stream
+        self._check(self._lib.esk_create(device, handle, ctypes.byref(self._ctx)))
+        self._keep = {}
+
+    def _check(self, st):
+        if st != OK:
+            msg = self._lib.esk_last_error(self._ctx).decode() if self._ctx else ""
+            raise EskError(st, msg or self._lib.esk_strerror(st).decode())
+        return st
+
+    def close(self):
+        if self._ctx:
+            self._lib.esk_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- calls ---------------------------------------------------------------
+    def set_volume(self, vol, brick: int, value_range=(0.0, 1.0), max_tf: int = 1024, workspace=None):
+        """vol: contiguous [nz, ny, nx] device tensor (u8/u16/f16/f32)."""
+        import torch
+        if not vol.is_contiguous() or vol.dim() != 3:
+            raise ValueError("volume must be a contiguous 3-D tensor [nz, ny, nx]")
+        nz, ny, nx = vol.shape
+        code = _dtype_code(vol)
+        need = workspace_bytes((nx, ny, nz), code, brick, max_tf)
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device=vol.device)
+        self._check(self._lib.esk_set_volume(self._ctx, ctypes.c_void_p(vol.data_ptr()), code, nx, ny, nz,
+                                             float(value_range[0]), float(value_range[1]), brick, max_tf,
+                                             ctypes.c_void_p(workspace.data_ptr()), workspace.numel()))
+        self._keep = {"vol": vol, "ws": workspace}
+        self.dims = (nx, ny, nz)
+        self.brick = brick
+        self.dtype_code = code
+        return self
+
+    def set_tf(self, tf, build=("grid", "lbvh", "kd"), kd: Kd | None = None):
+        """tf: contiguous [N, 4] float32 device tensor; rebuilds the requested structures."""
+        if tf.dtype.is_floating_point is False or tf.dim() != 2 or tf.shape[1] != 4:
+            raise ValueError("TF must be an [N, 4] float32 tensor")
+        mask = 0
+        for b in build:
+            mask |= ACCEL[b]
+        kp = None
+        if mask & KD:
+            kd = kd or Kd()
+            kp = KdParams(kd.halting, kd.max_leaf, kd.bins)
+        self._check(self._lib.esk_set_transfer_function(self._ctx, ctypes.c_void_p(tf.data_ptr()),
+                                                        tf.shape[0], mask,
+                                                        ctypes.byref(kp) if kp is not None else None))
+        self._keep["tf"] = tf
+        return self
+
+    def render(self, cam: dict, W: int, H: int, accel="lbvh", step=0.5, ref=1.0, out=None,
+               counts=None):
+        """Returns an [H, W, 4] float32 device tensor (premultiplied RGBA, row
+        0 at the top).  counts: optional [H, W] int32 device tensor that
+        receives the number of composited samples per pixel."""
+        import torch
+        if out is None:
+            out = torch.empty((H, W, 4), dtype=torch.float32, device=self._keep["vol"].device)
+        c = camera_struct(cam)
+        self._check(self._lib.esk_render(self._ctx, ACCEL[accel] if isinstance(accel, str) else int(accel),
+                                         ctypes.byref(c), W, H, float(step), float(ref),
+                                         ctypes.c_void_p(out.data_ptr()),
+                                         ctypes.c_void_p(counts.data_ptr()) if counts is not None else None))
+        return out
+
+    def sync(self):
+        self._check(self._lib.esk_sync(self._ctx))
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(self._lib.esk_get_stats(self._ctx, ctypes.byref(s)))
+        return dict(n_bricks=s.n_bricks, n_nonempty=s.n_nonempty, lbvh_nodes=s.lbvh_nodes,
+                    kd_nodes=s.kd_nodes, lbvh_height=s.lbvh_height, kd_height=s.kd_height,
+                    nb=tuple(s.nb), built=s.built)
+
+    def export(self, what: str) -> np.ndarray:
+        code = EXPORTS[what]
+        used = ctypes.c_size_t()
+        st = self._lib.esk_export(self._ctx, code, None, 0, ctypes.byref(used))
+        if st not in (OK, ENOSPC):
+            self._check(st)
+        if what == "minmax":
+            dt = {U8: np.uint8, U16: np.uint16, F16: np.float16, F32: np.float32}[self.dtype_code]
+            buf = np.empty(used.value // np.dtype(dt).itemsize, dt)
+        else:
+            dt, width = _EXPORT_DTYPE[what]
+            buf = np.empty(used.value // np.dtype(dt).itemsize, dt)
+        if used.value:
+            self._check(self._lib.esk_export(self._ctx, code, buf.ctypes.data_as(ctypes.c_void_p),
+                                              buf.nbytes, ctypes.byref(used)))
+        if what == "minmax":
+            h = buf.size // 2
+            return buf[:h].copy(), buf[h:].copy()
+        if what in ("lbvh_lo", "lbvh_hi", "kd_lo", "kd_hi"):
+            return buf.reshape(-1, 3)
+        return buf

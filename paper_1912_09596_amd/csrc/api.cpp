@@ -1,0 +1,567 @@
+// api.cpp -- host runtime behind include/esk.h: argument validation,
+// workspace layout, and the stream-ordered orchestration of the kernels.
+// All argument checks run on the host before any device call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "esk_internal.hpp"
+
+namespace esk {
+
+int elem_size(int dtype)
+{
+    switch (dtype) {
+    case ESK_U8: return 1;
+    case ESK_U16: return 2;
+    case ESK_F16: return 2;
+    case ESK_F32: return 4;
+    }
+    return 0;
+}
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+Layout make_layout(int nbx, int nby, int nbz, int elem_bytes, int max_tf)
+{
+    Layout L;
+    std::memset(&L, 0, sizeof(L));
+    const int64_t nb = (int64_t)nbx * nby * nbz;
+    L.nb = nb;
+    L.nblk = (nb + kClassifyBlock - 1) / kClassifyBlock;
+    L.nsortblk = (nb + kSortBlockKeys - 1) / kSortBlockKeys;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + std::max<size_t>(bytes, 1), 256);
+        return o;
+    };
+    const size_t n4 = (size_t)nb * 4;
+    L.header = take(sizeof(DevHeader));
+    L.minv = take((size_t)nb * elem_bytes);
+    L.maxv = take((size_t)nb * elem_bytes);
+    L.tf = take((size_t)max_tf * 16);
+    L.tfP = take((size_t)(max_tf + 1) * 4);
+    L.flags = take((size_t)nb);
+    L.grid = take((size_t)L.nblk * (kClassifyBlock / 32) * 4);
+    L.blkcnt = take((size_t)L.nblk * 4);
+    L.ids = take(n4);
+    L.keys = take(n4);
+    L.skeys = take(n4);
+    L.tmpkeys = take(n4);
+    L.sids = take(n4);
+    L.hist = take((size_t)L.nsortblk * 256 * 4);
+    L.lb_left = take(n4);
+    L.lb_right = take(n4);
+    L.lb_axis = take(n4);
+    L.lb_parent = take(2 * n4);
+    L.lb_lo = take(2 * n4 * 3);
+    L.lb_hi = take(2 * n4 * 3);
+    L.lb_height = take(2 * n4);
+    L.lb_flag = take(n4);
+    L.kd_S = take(n4);
+    L.kd_lo = take(2 * n4 * 3);
+    L.kd_hi = take(2 * n4 * 3);
+    L.kd_axis = take(2 * n4);
+    L.kd_plane = take(2 * n4);
+    L.kd_first = take(2 * n4);
+    L.kd_split = take(2 * n4);
+    L.kd_clo = take(2 * n4 * 12);
+    L.total = off;
+    return L;
+}
+
+}  // namespace esk
+
+using namespace esk;
+
+struct esk_ctx {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    DevHeader *pinned = nullptr;   // host read-back slot
+    std::string err;
+    // volume
+    bool has_volume = false;
+    VolumeDesc vol{};
+    float vlo = 0.f, vhi = 1.f;
+    int max_tf = 0;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    Layout L{};
+    // TF / hierarchy
+    bool has_tf = false;
+    int N = 0;
+    int built = 0;
+    uint32_t kd_height = 0;
+    uint32_t kd_count = 0;
+};
+
+namespace {
+
+esk_status fail(esk_ctx *c, esk_status s, const char *fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        std::vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return s;
+}
+
+esk_status hip_check(esk_ctx *c, hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return ESK_OK;
+    return fail(c, ESK_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool valid_brick(int b) { return b == 4 || b == 8 || b == 16 || b == 32; }
+
+int log2i(int b)
+{
+    int l = 0;
+    while ((1 << l) < b) ++l;
+    return l;
+}
+
+int bits_for(int n)  // bits to index [0, n)
+{
+    int b = 0;
+    while ((1 << b) < n) ++b;
+    return b;
+}
+
+esk_status check_shape(esk_ctx *c, int nx, int ny, int nz, int dtype, int brick, int max_tf)
+{
+    if (nx < 1 || ny < 1 || nz < 1) return fail(c, ESK_EINVAL, "dims must be >= 1 (got %d %d %d)", nx, ny, nz);
+    if (elem_size(dtype) == 0) return fail(c, ESK_EINVAL, "unknown dtype %d", dtype);
+    if (!valid_brick(brick)) return fail(c, ESK_EINVAL, "brick must be 4, 8, 16 or 32 (got %d)", brick);
+    if (max_tf < 2 || max_tf > kMaxTF)
+        return fail(c, ESK_ELIMIT, "max_tf_entries must be in [2, %d] (got %d)", kMaxTF, max_tf);
+    const int nbx = (nx + brick - 1) / brick, nby = (ny + brick - 1) / brick, nbz = (nz + brick - 1) / brick;
+    if (nbx > kMaxBricksPerAxis || nby > kMaxBricksPerAxis || nbz > kMaxBricksPerAxis)
+        return fail(c, ESK_ELIMIT, "more than %d bricks on an axis (%d %d %d)", kMaxBricksPerAxis, nbx, nby, nbz);
+    return ESK_OK;
+}
+
+bool finite3(const float *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+template <typename T> T *at(esk_ctx *c, size_t off) { return reinterpret_cast<T *>(c->ws + off); }
+
+esk_status read_header(esk_ctx *c)
+{
+    hipError_t e = hipMemcpyAsync(c->pinned, at<DevHeader>(c, c->L.header), sizeof(DevHeader),
+                                  hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return hip_check(c, e, "reading device header");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *esk_strerror(esk_status s)
+{
+    switch (s) {
+    case ESK_OK: return "ok";
+    case ESK_EINVAL: return "invalid argument";
+    case ESK_ENOSPC: return "workspace too small";
+    case ESK_ELIMIT: return "size limit exceeded";
+    case ESK_EDEVICE: return "device error";
+    case ESK_ESTATE: return "call out of order";
+    case ESK_EINTERNAL: return "internal error";
+    }
+    return "unknown status";
+}
+
+const char *esk_last_error(const esk_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+esk_status esk_create(int device, void *hip_stream, esk_ctx **out)
+{
+    if (!out) return ESK_EINVAL;
+    *out = nullptr;
+    if (device < -1) return ESK_EINVAL;
+    esk_ctx *c = new (std::nothrow) esk_ctx();
+    if (!c) return ESK_EINTERNAL;
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    if (device >= 0) {
+        int count = 0;
+        hipError_t e = hipGetDeviceCount(&count);
+        if (e != hipSuccess || device >= count) {
+            delete c;
+            return ESK_EDEVICE;
+        }
+        e = hipSetDevice(device);
+        if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&c->pinned), sizeof(DevHeader));
+        if (e != hipSuccess) {
+            delete c;
+            return ESK_EDEVICE;
+        }
+        std::memset(c->pinned, 0, sizeof(DevHeader));
+    }
+    *out = c;
+    return ESK_OK;
+}
+
+esk_status esk_destroy(esk_ctx *c)
+{
+    if (!c) return ESK_EINVAL;
+    if (c->device >= 0) {
+        (void)hipSetDevice(c->device);
+        (void)hipStreamSynchronize(c->stream);
+        if (c->pinned) (void)hipHostFree(c->pinned);
+    }
+    delete c;
+    return ESK_OK;
+}
+
+esk_status esk_workspace_bytes(int nx, int ny, int nz, int dtype, int brick, int max_tf_entries, size_t *out)
+{
+    if (!out) return ESK_EINVAL;
+    esk_status s = check_shape(nullptr, nx, ny, nz, dtype, brick, max_tf_entries);
+    if (s != ESK_OK) return s;
+    const int nbx = (nx + brick - 1) / brick, nby = (ny + brick - 1) / brick, nbz = (nz + brick - 1) / brick;
+    *out = make_layout(nbx, nby, nbz, elem_size(dtype), max_tf_entries).total;
+    return ESK_OK;
+}
+
+esk_status esk_set_volume(esk_ctx *c, const void *d_vox, int dtype, int nx, int ny, int nz, float value_lo,
+                          float value_hi, int brick, int max_tf_entries, void *d_ws, size_t ws_bytes)
+{
+    if (!c) return ESK_EINVAL;
+    esk_status s = check_shape(c, nx, ny, nz, dtype, brick, max_tf_entries);
+    if (s != ESK_OK) return s;
+    if (!d_vox) return fail(c, ESK_EINVAL, "volume pointer is null");
+    if (!d_ws) return fail(c, ESK_EINVAL, "workspace pointer is null");
+    if ((reinterpret_cast<uintptr_t>(d_ws) & 255) != 0) return fail(c, ESK_EINVAL, "workspace must be 256-byte aligned");
+    if ((reinterpret_cast<uintptr_t>(d_vox) % elem_size(dtype)) != 0)
+        return fail(c, ESK_EINVAL, "volume pointer not aligned to its element size");
+    if ((dtype == ESK_F16 || dtype == ESK_F32) &&
+        !(std::isfinite(value_lo) && std::isfinite(value_hi) && value_lo < value_hi))
+        return fail(c, ESK_EINVAL, "value range must be finite with lo < hi");
+    const int nbx = (nx + brick - 1) / brick, nby = (ny + brick - 1) / brick, nbz = (nz + brick - 1) / brick;
+    Layout L = make_layout(nbx, nby, nbz, elem_size(dtype), max_tf_entries);
+    if (ws_bytes < L.total)
+        return fail(c, ESK_ENOSPC, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+    if (c->device < 0) return fail(c, ESK_ESTATE, "validation-only context");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_check(c, e, "hipSetDevice");
+    c->has_volume = false;
+    c->has_tf = false;
+    c->built = 0;
+    c->vol.vox = d_vox;
+    c->vol.dtype = dtype;
+    c->vol.nx = nx;
+    c->vol.ny = ny;
+    c->vol.nz = nz;
+    c->vol.B = brick;
+    c->vol.log2B = log2i(brick);
+    c->vol.nb[0] = nbx;
+    c->vol.nb[1] = nby;
+    c->vol.nb[2] = nbz;
+    c->vlo = value_lo;
+    c->vhi = value_hi;
+    c->max_tf = max_tf_entries;
+    c->ws = static_cast<char *>(d_ws);
+    c->ws_bytes = ws_bytes;
+    c->L = L;
+    e = hipMemsetAsync(c->ws + L.header, 0, sizeof(DevHeader), c->stream);
+    if (e == hipSuccess) e = launch_minmax(c->vol, c->ws + L.minv, c->ws + L.maxv, c->stream);
+    if (e != hipSuccess) return hip_check(c, e, "set_volume launch");
+    c->has_volume = true;
+    return ESK_OK;
+}
+
+static RebuildArgs rebuild_args(esk_ctx *c)
+{
+    RebuildArgs a;
+    std::memset(&a, 0, sizeof(a));
+    const Layout &L = c->L;
+    a.vol = c->vol;
+    a.vlo = c->vlo;
+    a.vhi = c->vhi;
+    a.N = c->N;
+    a.tf = at<float>(c, L.tf);
+    a.tfP = at<int32_t>(c, L.tfP);
+    a.minv = c->ws + L.minv;
+    a.maxv = c->ws + L.maxv;
+    a.flags = at<uint8_t>(c, L.flags);
+    a.grid = at<uint32_t>(c, L.grid);
+    a.blkcnt = at<uint32_t>(c, L.blkcnt);
+    a.ids = at<uint32_t>(c, L.ids);
+    a.keys = at<uint32_t>(c, L.keys);
+    a.skeys = at<uint32_t>(c, L.skeys);
+    a.tmpkeys = at<uint32_t>(c, L.tmpkeys);
+    a.sids = at<uint32_t>(c, L.sids);
+    a.hist = at<uint32_t>(c, L.hist);
+    a.lb_left = at<uint32_t>(c, L.lb_left);
+    a.lb_right = at<uint32_t>(c, L.lb_right);
+    a.lb_parent = at<uint32_t>(c, L.lb_parent);
+    a.lb_flag = at<uint32_t>(c, L.lb_flag);
+    a.lb_height = at<uint32_t>(c, L.lb_height);
+    a.lb_axis = at<int32_t>(c, L.lb_axis);
+    a.lb_lo = at<int32_t>(c, L.lb_lo);
+    a.lb_hi = at<int32_t>(c, L.lb_hi);
+    a.hdr = at<DevHeader>(c, L.header);
+    a.nb = L.nb;
+    a.nblk = L.nblk;
+    a.nsortblk = L.nsortblk;
+    a.key_bits = 3 * std::max({bits_for(c->vol.nb[0]), bits_for(c->vol.nb[1]), bits_for(c->vol.nb[2])});
+    return a;
+}
+
+static KdArgs kd_args(esk_ctx *c, const esk_kd_params *p)
+{
+    KdArgs k;
+    std::memset(&k, 0, sizeof(k));
+    const Layout &L = c->L;
+    for (int a = 0; a < 3; ++a) k.nb[a] = c->vol.nb[a];
+    k.B = c->vol.B;
+    k.n[0] = c->vol.nx;
+    k.n[1] = c->vol.ny;
+    k.n[2] = c->vol.nz;
+    k.flags = at<uint8_t>(c, L.flags);
+    k.S = at<int32_t>(c, L.kd_S);
+    k.lo = at<int32_t>(c, L.kd_lo);
+    k.hi = at<int32_t>(c, L.kd_hi);
+    k.axis = at<int32_t>(c, L.kd_axis);
+    k.plane = at<int32_t>(c, L.kd_plane);
+    k.first = at<int32_t>(c, L.kd_first);
+    k.split = at<int32_t>(c, L.kd_split);
+    k.clo = at<int32_t>(c, L.kd_clo);
+    k.hdr = at<DevHeader>(c, L.header);
+    if (p) {
+        k.halting = p->halting;
+        k.max_leaf = p->max_leaf;
+        k.bins = p->bins;
+    }
+    return k;
+}
+
+esk_status esk_set_transfer_function(esk_ctx *c, const float *d_rgba, int n_entries, int build_mask,
+                                     const esk_kd_params *kd)
+{
+    if (!c) return ESK_EINVAL;
+    if (!d_rgba) return fail(c, ESK_EINVAL, "TF pointer is null");
+    if ((reinterpret_cast<uintptr_t>(d_rgba) & 15) != 0) return fail(c, ESK_EINVAL, "TF must be 16-byte aligned");
+    if (n_entries < 2) return fail(c, ESK_EINVAL, "TF needs at least 2 entries (got %d)", n_entries);
+    if (build_mask & ~(ESK_ACCEL_GRID | ESK_ACCEL_LBVH | ESK_ACCEL_KD))
+        return fail(c, ESK_EINVAL, "unknown bits in build_mask 0x%x", build_mask);
+    if (build_mask & ESK_ACCEL_KD) {
+        if (!kd) return fail(c, ESK_EINVAL, "k-d build requested without parameters");
+        if (kd->halting != 0 && kd->halting != 1) return fail(c, ESK_EINVAL, "kd halting must be 0 or 1");
+        if (kd->max_leaf < 0 || kd->max_leaf > 4096) return fail(c, ESK_EINVAL, "kd max_leaf out of range");
+        if (kd->bins < 2 || kd->bins > 16) return fail(c, ESK_EINVAL, "kd bins must be in [2, 16]");
+    }
+    if (c->device < 0) return fail(c, ESK_ESTATE, "validation-only context");
+    if (!c->has_volume) return fail(c, ESK_ESTATE, "set_transfer_function before set_volume");
+    if (n_entries > c->max_tf)
+        return fail(c, ESK_ELIMIT, "TF has %d entries, workspace sized for %d", n_entries, c->max_tf);
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_check(c, e, "hipSetDevice");
+    c->has_tf = false;
+    c->built = 0;
+    c->N = n_entries;
+    const Layout &L = c->L;
+    e = hipMemcpyAsync(c->ws + L.tf, d_rgba, (size_t)n_entries * 16, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_check(c, e, "TF copy");
+    RebuildArgs a = rebuild_args(c);
+    e = launch_classify_compact(a, c->stream);
+    if (e != hipSuccess) return hip_check(c, e, "classify launch");
+    if (build_mask & ESK_ACCEL_LBVH) {
+        e = launch_sort(a, c->stream);
+        if (e == hipSuccess) e = launch_lbvh(a, c->stream);
+        if (e != hipSuccess) return hip_check(c, e, "LBVH launch");
+    }
+    if (build_mask & ESK_ACCEL_KD) {
+        KdArgs k = kd_args(c, kd);
+        e = launch_kd_prefix(k, c->stream);
+        if (e == hipSuccess) e = launch_kd_root(k, c->stream);
+        if (e != hipSuccess) return hip_check(c, e, "k-d launch");
+        esk_status st = read_header(c);
+        if (st != ESK_OK) return st;
+        const int64_t cap = 2 * L.nb;
+        while (c->pinned->kd_end > c->pinned->kd_begin) {
+            const uint32_t begin = c->pinned->kd_begin, end = c->pinned->kd_end;
+            if ((int64_t)end + 2 * ((int64_t)end - begin) > cap)
+                return fail(c, ESK_EINTERNAL, "k-d node capacity exceeded");
+            e = launch_kd_level(k, begin, end, c->stream);
+            if (e != hipSuccess) return hip_check(c, e, "k-d level launch");
+            st = read_header(c);
+            if (st != ESK_OK) return st;
+        }
+        c->kd_count = c->pinned->kd_count;
+        c->kd_height = c->pinned->kd_height;
+    }
+    c->built = build_mask;
+    c->has_tf = true;
+    return ESK_OK;
+}
+
+esk_status esk_render(esk_ctx *c, int accel, const esk_camera *cam, int width, int height, float step,
+                      float opacity_ref_step, float *d_rgba_out, int32_t *d_count_out)
+{
+    if (!c) return ESK_EINVAL;
+    if (!cam) return fail(c, ESK_EINVAL, "camera is null");
+    if (accel != ESK_ACCEL_NONE && accel != ESK_ACCEL_GRID && accel != ESK_ACCEL_LBVH && accel != ESK_ACCEL_KD)
+        return fail(c, ESK_EINVAL, "unknown accel %d", accel);
+    if (width < 1 || height < 1 || width > 32768 || height > 32768)
+        return fail(c, ESK_EINVAL, "image size %d x %d out of range", width, height);
+    if (!(std::isfinite(step) && step > 0.0f)) return fail(c, ESK_EINVAL, "step must be finite and > 0");
+    if (!(std::isfinite(opacity_ref_step) && opacity_ref_step >= 0.0f))
+        return fail(c, ESK_EINVAL, "opacity_ref_step must be finite and >= 0");
+    if (!finite3(cam->eye) || !finite3(cam->dir00) || !finite3(cam->du) || !finite3(cam->dv))
+        return fail(c, ESK_EINVAL, "camera has non-finite components");
+    if (!d_rgba_out) return fail(c, ESK_EINVAL, "output pointer is null");
+    if ((reinterpret_cast<uintptr_t>(d_rgba_out) & 15) != 0) return fail(c, ESK_EINVAL, "output must be 16-byte aligned");
+    if (d_count_out && (reinterpret_cast<uintptr_t>(d_count_out) & 3) != 0)
+        return fail(c, ESK_EINVAL, "count output must be 4-byte aligned");
+    if (c->device < 0) return fail(c, ESK_ESTATE, "validation-only context");
+    if (!c->has_volume || !c->has_tf) return fail(c, ESK_ESTATE, "render before set_volume/set_transfer_function");
+    if (accel != ESK_ACCEL_NONE && !(c->built & accel))
+        return fail(c, ESK_ESTATE, "accel %d was not built by the last rebuild", accel);
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_check(c, e, "hipSetDevice");
+    const Layout &L = c->L;
+    RenderArgs r;
+    std::memset(&r, 0, sizeof(r));
+    r.vol = c->vol;
+    if (c->vol.dtype == ESK_U8) { r.vlo = 0.0f; r.vscale = 1.0f / 255.0f; }
+    else if (c->vol.dtype == ESK_U16) { r.vlo = 0.0f; r.vscale = 1.0f / 65535.0f; }
+    else { r.vlo = c->vlo; r.vscale = 1.0f / (c->vhi - c->vlo); }
+    r.tf = at<float>(c, L.tf);
+    r.N = c->N;
+    r.cam = *cam;
+    r.W = width;
+    r.H = height;
+    r.dt = step;
+    r.correct = opacity_ref_step > 0.0f;
+    r.expo = r.correct ? step / opacity_ref_step : 1.0f;
+    r.out = d_rgba_out;
+    r.count = d_count_out;
+    r.grid = at<uint32_t>(c, L.grid);
+    r.lb_left = at<uint32_t>(c, L.lb_left);
+    r.lb_right = at<uint32_t>(c, L.lb_right);
+    r.lb_axis = at<int32_t>(c, L.lb_axis);
+    r.lb_lo = at<int32_t>(c, L.lb_lo);
+    r.lb_hi = at<int32_t>(c, L.lb_hi);
+    r.kd_lo = at<int32_t>(c, L.kd_lo);
+    r.kd_hi = at<int32_t>(c, L.kd_hi);
+    r.kd_axis = at<int32_t>(c, L.kd_axis);
+    r.kd_plane = at<int32_t>(c, L.kd_plane);
+    r.kd_first = at<int32_t>(c, L.kd_first);
+    r.hdr = at<DevHeader>(c, L.header);
+    r.stack_cap = 0;
+    if (accel == ESK_ACCEL_LBVH) r.stack_cap = 32;
+    if (accel == ESK_ACCEL_KD) {
+        if ((int)c->kd_height > kMaxKdStack)
+            return fail(c, ESK_ELIMIT, "k-d tree height %u exceeds the traversal stack (%d)", c->kd_height, kMaxKdStack);
+        r.stack_cap = std::max(1, (int)c->kd_height);
+    }
+    e = launch_render(accel, r, c->stream);
+    return hip_check(c, e, "render launch");
+}
+
+esk_status esk_sync(esk_ctx *c)
+{
+    if (!c) return ESK_EINVAL;
+    if (c->device < 0) return fail(c, ESK_ESTATE, "validation-only context");
+    hipError_t e = hipSetDevice(c->device);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return hip_check(c, e, "stream synchronize");
+}
+
+esk_status esk_get_stats(esk_ctx *c, esk_stats *out)
+{
+    if (!c || !out) return ESK_EINVAL;
+    if (c->device < 0) return fail(c, ESK_ESTATE, "validation-only context");
+    if (!c->has_volume) return fail(c, ESK_ESTATE, "no volume");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_check(c, e, "hipSetDevice");
+    esk_status s = read_header(c);
+    if (s != ESK_OK) return s;
+    std::memset(out, 0, sizeof(*out));
+    out->n_bricks = c->L.nb;
+    for (int a = 0; a < 3; ++a) out->nb[a] = c->vol.nb[a];
+    out->built = c->has_tf ? c->built : 0;
+    if (c->has_tf) {
+        const int64_t n = c->pinned->n;
+        out->n_nonempty = n;
+        if (c->built & ESK_ACCEL_LBVH) {
+            out->lbvh_nodes = n > 0 ? 2 * n - 1 : 0;
+            out->lbvh_height = (int32_t)c->pinned->lbvh_height;
+        }
+        if (c->built & ESK_ACCEL_KD) {
+            out->kd_nodes = c->pinned->kd_count;
+            out->kd_height = (int32_t)c->pinned->kd_height;
+        }
+    }
+    return ESK_OK;
+}
+
+esk_status esk_export(esk_ctx *c, int what, void *host, size_t cap, size_t *used)
+{
+    if (!c || !used) return ESK_EINVAL;
+    if (c->device < 0) return fail(c, ESK_ESTATE, "validation-only context");
+    if (!c->has_volume) return fail(c, ESK_ESTATE, "no volume");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_check(c, e, "hipSetDevice");
+    esk_status s = read_header(c);
+    if (s != ESK_OK) return s;
+    const Layout &L = c->L;
+    const int64_t nb = L.nb;
+    const int64_t n = c->has_tf ? c->pinned->n : 0;
+    const int64_t m = (c->has_tf && (c->built & ESK_ACCEL_KD)) ? c->pinned->kd_count : 0;
+    const int64_t ni = n > 0 ? n - 1 : 0;
+    size_t off = 0, bytes = 0;
+    const bool need_tf = what != ESK_X_MINMAX;
+    if (need_tf && !c->has_tf) return fail(c, ESK_ESTATE, "no transfer function set");
+    const bool lbvh = c->built & ESK_ACCEL_LBVH;
+    switch (what) {
+    case ESK_X_MINMAX: {
+        // min and max are separate regions: copy both
+        const size_t half = (size_t)nb * elem_size(c->vol.dtype);
+        *used = 2 * half;
+        if (cap < *used || !host) return fail(c, ESK_ENOSPC, "export needs %zu bytes", *used);
+        e = hipMemcpy(host, c->ws + L.minv, half, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(static_cast<char *>(host) + half, c->ws + L.maxv, half, hipMemcpyDeviceToHost);
+        return hip_check(c, e, "export copy");
+    }
+    case ESK_X_TF_PREFIX: off = L.tfP; bytes = (size_t)(c->N + 1) * 4; break;
+    case ESK_X_FLAGS: off = L.flags; bytes = (size_t)nb; break;
+    case ESK_X_IDS: off = L.ids; bytes = (size_t)n * 4; break;
+    case ESK_X_KEYS: off = L.keys; bytes = (size_t)n * 4; break;
+    case ESK_X_SORTED_KEYS: if (!lbvh) goto notbuilt; off = L.skeys; bytes = (size_t)n * 4; break;
+    case ESK_X_SORTED_IDS: if (!lbvh) goto notbuilt; off = L.sids; bytes = (size_t)n * 4; break;
+    case ESK_X_LBVH_LEFT: if (!lbvh) goto notbuilt; off = L.lb_left; bytes = (size_t)ni * 4; break;
+    case ESK_X_LBVH_RIGHT: if (!lbvh) goto notbuilt; off = L.lb_right; bytes = (size_t)ni * 4; break;
+    case ESK_X_LBVH_AXIS: if (!lbvh) goto notbuilt; off = L.lb_axis; bytes = (size_t)ni * 4; break;
+    case ESK_X_LBVH_LO: if (!lbvh) goto notbuilt; off = L.lb_lo; bytes = (size_t)ni * 12; break;
+    case ESK_X_LBVH_HI: if (!lbvh) goto notbuilt; off = L.lb_hi; bytes = (size_t)ni * 12; break;
+    case ESK_X_KD_LO: if (!(c->built & ESK_ACCEL_KD)) goto notbuilt; off = L.kd_lo; bytes = (size_t)m * 12; break;
+    case ESK_X_KD_HI: if (!(c->built & ESK_ACCEL_KD)) goto notbuilt; off = L.kd_hi; bytes = (size_t)m * 12; break;
+    case ESK_X_KD_AXIS: if (!(c->built & ESK_ACCEL_KD)) goto notbuilt; off = L.kd_axis; bytes = (size_t)m * 4; break;
+    case ESK_X_KD_PLANE: if (!(c->built & ESK_ACCEL_KD)) goto notbuilt; off = L.kd_plane; bytes = (size_t)m * 4; break;
+    case ESK_X_KD_FIRST: if (!(c->built & ESK_ACCEL_KD)) goto notbuilt; off = L.kd_first; bytes = (size_t)m * 4; break;
+    case ESK_X_GRID: off = L.grid; bytes = (size_t)((nb + 31) / 32) * 4; break;
+    default: return fail(c, ESK_EINVAL, "unknown export %d", what);
+    }
+    *used = bytes;
+    if (bytes == 0) return ESK_OK;
+    if (cap < bytes || !host) return fail(c, ESK_ENOSPC, "export needs %zu bytes", bytes);
+    e = hipMemcpy(host, c->ws + off, bytes, hipMemcpyDeviceToHost);
+    return hip_check(c, e, "export copy");
+notbuilt:
+    return fail(c, ESK_ESTATE, "export %d: structure not built by the last rebuild", what);
+}
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+// esk_internal.hpp -- shared between the host runtime (api.cpp) and the HIP
+// kernel translation units of libesk.  Not installed, not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/esk.h"
+
+namespace esk {
+
+constexpr int kMaxTF = 4096;          // TF entries the ABI accepts
+constexpr int kMaxBricksPerAxis = 1024;  // 10 bits per axis of the 30-bit Morton code
+constexpr uint32_t kLeaf = 0x80000000u;
+constexpr int kClassifyBlock = 1024;  // bricks per classification / compaction block
+constexpr int kSortSingleMax = 32768; // keys one workgroup sorts in LDS
+constexpr int kSortBlockKeys = 4096;  // keys per block of the multi-block sort
+constexpr int kMaxKdStack = 128;      // deepest k-d tree the renderer traverses
+
+// Small device-resident state written by the rebuild kernels.
+struct DevHeader {
+    uint32_t n;            // non-empty bricks
+    uint32_t lbvh_height;  // levels
+    uint32_t kd_count;     // k-d nodes emitted so far
+    uint32_t kd_height;    // levels emitted so far
+    uint32_t kd_begin;     // current level [begin, end)
+    uint32_t kd_end;
+    uint32_t pad[58];
+};
+static_assert(sizeof(DevHeader) == 256, "header is one 256-byte slot");
+
+// Byte offsets of every array inside the caller's workspace.
+struct Layout {
+    int64_t nb;            // bricks
+    int64_t nblk;          // classification blocks
+    int64_t nsortblk;      // multi-block sort blocks
+    size_t header, minv, maxv, tf, tfP, flags, grid, blkcnt;
+    size_t ids, keys, skeys, tmpkeys, sids, hist;
+    size_t lb_left, lb_right, lb_axis, lb_parent, lb_lo, lb_hi, lb_height, lb_flag;
+    size_t kd_S, kd_lo, kd_hi, kd_axis, kd_plane, kd_first, kd_split, kd_clo, kd_chi;
+    size_t total;
+};
+
+Layout make_layout(int nbx, int nby, int nbz, int elem_bytes, int max_tf);
+
+int elem_size(int dtype);
+
+// ---- launchers (each enqueues on `s`; returns hipSuccess or the launch error)
+struct VolumeDesc {
+    const void *vox;
+    int dtype, nx, ny, nz, B, log2B, nb[3];
+};
+
+hipError_t launch_minmax(const VolumeDesc &v, void *minv, void *maxv, hipStream_t s);
+
+struct RebuildArgs {
+    VolumeDesc vol;
+    float vlo, vhi;
+    int N;                 // TF entries
+    const float *tf;       // workspace copy
+    int32_t *tfP;
+    const void *minv, *maxv;
+    uint8_t *flags;
+    uint32_t *grid;
+    uint32_t *blkcnt;
+    uint32_t *ids, *keys, *skeys, *tmpkeys, *sids, *hist;
+    uint32_t *lb_left, *lb_right, *lb_parent, *lb_flag, *lb_height;
+    int32_t *lb_axis, *lb_lo, *lb_hi;
+    DevHeader *hdr;
+    int64_t nb, nblk, nsortblk;
+    int key_bits;          // Morton bits that can be non-zero
+};
+
+hipError_t launch_classify_compact(const RebuildArgs &a, hipStream_t s);
+hipError_t launch_sort(const RebuildArgs &a, hipStream_t s);
+hipError_t launch_lbvh(const RebuildArgs &a, hipStream_t s);
+
+struct KdArgs {
+    int nb[3], B, n[3];
+    const uint8_t *flags;
+    int32_t *S;
+    int32_t *lo, *hi, *axis, *plane, *first, *split, *clo;  // clo: [node][side][6 faces]
+    DevHeader *hdr;
+    int halting, max_leaf, bins;
+};
+
+hipError_t launch_kd_prefix(const KdArgs &k, hipStream_t s);
+hipError_t launch_kd_root(const KdArgs &k, hipStream_t s);
+hipError_t launch_kd_level(const KdArgs &k, uint32_t begin, uint32_t end, hipStream_t s);
+
+struct RenderArgs {
+    VolumeDesc vol;
+    float vlo, vscale;     // s = clamp((v - vlo) * vscale, 0, 1)
+    const float *tf;
+    int N;
+    esk_camera cam;
+    int W, H;
+    float dt, expo;
+    int correct;
+    float *out;
+    int32_t *count;
+    const uint32_t *grid;
+    const uint32_t *lb_left, *lb_right;
+    const int32_t *lb_axis, *lb_lo, *lb_hi;
+    const int32_t *kd_lo, *kd_hi, *kd_axis, *kd_plane, *kd_first;
+    const DevHeader *hdr;
+    int stack_cap;
+};
+
+hipError_t launch_render(int accel, const RenderArgs &r, hipStream_t s);
+
+}  // namespace esk

@@ -1,0 +1,289 @@
+// kdtree.hip -- binned k-d tree over brick occupancy (Sec. 3.2, 3.2.2, 4.3),
+// built level by level on the device.
+//
+// The paper's GPU builder recurses on the host and launches two reductions
+// per candidate plane.  Here the occupancy of any box of bricks is an O(1)
+// query into a 3-D inclusive prefix count over the brick flags (the summed-
+// volume-table idea of Sec. 3.2, applied at brick granularity), so a tight
+// box is 6 binary searches and one wave evaluates every candidate plane of a
+// node at once: lanes take (candidate, side, face) tasks.  One launch
+// evaluates a whole level; a single-workgroup launch numbers the children in
+// breadth-first order (left child first) with a block scan.
+#include "esk_internal.hpp"
+#include "device_util.hpp"
+
+namespace esk {
+namespace {
+
+// ---------------------------------------------------------------------------
+// 3-D inclusive prefix count S over the flags (one pass per axis)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_prefix_axis(KdArgs k, int axis)
+{
+    const int64_t nbx = k.nb[0], nby = k.nb[1], nbz = k.nb[2];
+    const int64_t line = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int64_t base, stride, len;
+    if (axis == 0) {          // lines along x, indexed by (y, z)
+        if (line >= nby * nbz) return;
+        base = line * nbx; stride = 1; len = nbx;
+    } else if (axis == 1) {   // along y, indexed by (x, z)
+        if (line >= nbx * nbz) return;
+        const int64_t x = line % nbx, z = line / nbx;
+        base = x + nbx * nby * z; stride = nbx; len = nby;
+    } else {                  // along z, indexed by (x, y)
+        if (line >= nbx * nby) return;
+        base = line; stride = nbx * nby; len = nbz;
+    }
+    int32_t run = 0;
+    for (int64_t i = 0; i < len; ++i) {
+        const int64_t idx = base + i * stride;
+        run += (axis == 0) ? (int32_t)k.flags[idx] : k.S[idx];
+        k.S[idx] = run;
+    }
+}
+
+struct Box {
+    int lo[3], hi[3];
+};
+
+__device__ inline int32_t S_at(const KdArgs &k, int x, int y, int z)
+{
+    if (x < 0 || y < 0 || z < 0) return 0;
+    return k.S[(int64_t)x + (int64_t)k.nb[0] * ((int64_t)y + (int64_t)k.nb[1] * z)];
+}
+
+// number of flagged bricks in [lo, hi)
+__device__ inline int32_t box_count(const KdArgs &k, const int lo[3], const int hi[3])
+{
+    if (hi[0] <= lo[0] || hi[1] <= lo[1] || hi[2] <= lo[2]) return 0;
+    const int x0 = lo[0] - 1, y0 = lo[1] - 1, z0 = lo[2] - 1;
+    const int x1 = hi[0] - 1, y1 = hi[1] - 1, z1 = hi[2] - 1;
+    return S_at(k, x1, y1, z1) - S_at(k, x0, y1, z1) - S_at(k, x1, y0, z1) - S_at(k, x1, y1, z0)
+         + S_at(k, x0, y0, z1) + S_at(k, x0, y1, z0) + S_at(k, x1, y0, z0) - S_at(k, x0, y0, z0);
+}
+
+// one face of the tight box of region [lo, hi) (which must hold a flagged
+// brick): face q in 0..2 = lower bound on axis q, 3..5 = upper bound (exclusive)
+__device__ inline int tight_face(const KdArgs &k, const int lo[3], const int hi[3], int face)
+{
+    const int q = face % 3;
+    int a = lo[q], b = hi[q] - 1;
+    int l[3] = {lo[0], lo[1], lo[2]}, h[3] = {hi[0], hi[1], hi[2]};
+    if (face < 3) {            // smallest c with a flagged brick in [lo_q, c]
+        while (a < b) {
+            const int m = (a + b) >> 1;
+            h[q] = m + 1;
+            if (box_count(k, l, h) > 0) b = m; else a = m + 1;
+        }
+        return a;
+    }
+    while (a < b) {            // largest c with a flagged brick in [c, hi_q)
+        const int m = (a + b + 1) >> 1;
+        l[q] = m;
+        if (box_count(k, l, h) > 0) a = m; else b = m - 1;
+    }
+    return a + 1;
+}
+
+__device__ inline int64_t box_volume(const KdArgs &k, const int lo[3], const int hi[3])
+{
+    int64_t v = 1;
+    for (int q = 0; q < 3; ++q) v *= (int64_t)min(k.B * hi[q], k.n[q]) - (int64_t)k.B * lo[q];
+    return v;
+}
+
+// root: tight box of all flagged bricks (6 lanes of one wave)
+__global__ __launch_bounds__(64) void k_kd_root(KdArgs k)
+{
+    __shared__ int face[6];
+    const int lane = threadIdx.x;
+    const int lo[3] = {0, 0, 0}, hi[3] = {k.nb[0], k.nb[1], k.nb[2]};
+    const int32_t total = box_count(k, lo, hi);
+    if (total == 0) {
+        if (lane == 0) {
+            k.hdr->kd_count = 0;
+            k.hdr->kd_height = 0;
+            k.hdr->kd_begin = 0;
+            k.hdr->kd_end = 0;
+        }
+        return;
+    }
+    if (lane < 6) face[lane] = tight_face(k, lo, hi, lane);
+    __syncthreads();
+    if (lane < 3) {
+        k.lo[lane] = face[lane];
+        k.hi[lane] = face[3 + lane];
+    }
+    if (lane == 0) {
+        k.hdr->kd_count = 1;
+        k.hdr->kd_height = 1;
+        k.hdr->kd_begin = 0;
+        k.hdr->kd_end = 1;
+    }
+}
+
+// the j-th candidate plane of node box [lo, hi): planes lo + floor(i*e/bins),
+// i = 1..bins-1, inside (lo, hi), deduplicated, axes in order x, y, z.
+// Returns the count; fills (axis, plane) for index `want` if it exists.
+__device__ inline int candidate(const int lo[3], const int hi[3], int bins, int want, int *ax, int *pl)
+{
+    int c = 0;
+    for (int a = 0; a < 3; ++a) {
+        const int e = hi[a] - lo[a];
+        if (e < 2) continue;
+        int prev = -1;
+        for (int j = 1; j < bins; ++j) {
+            const int p = lo[a] + (int)(((int64_t)j * e) / bins);
+            if (p <= lo[a] || p >= hi[a] || p == prev) continue;
+            prev = p;
+            if (c == want) { *ax = a; *pl = p; }
+            ++c;
+        }
+    }
+    return c;
+}
+
+constexpr int kMaxCand = 45;   // 3 axes x (16 bins - 1)
+
+// one wave per node of the level [begin, end)
+__global__ __launch_bounds__(256) void k_kd_eval(KdArgs k, uint32_t begin, uint32_t end)
+{
+    __shared__ int tb[4][kMaxCand + 1][2][6];   // per wave: tight boxes (candidate, side, face)
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t node = (int64_t)begin + (int64_t)blockIdx.x * 4 + wave;
+    if (node >= end) return;
+    int lo[3], hi[3];
+    for (int q = 0; q < 3; ++q) {
+        lo[q] = k.lo[3 * node + q];
+        hi[q] = k.hi[3 * node + q];
+    }
+    const int64_t V = box_volume(k, lo, hi);
+    const int rlo[3] = {k.lo[0], k.lo[1], k.lo[2]}, rhi[3] = {k.hi[0], k.hi[1], k.hi[2]};
+    const int64_t vroot = box_volume(k, rlo, rhi);
+    const bool allowed = k.halting == 0 ? (10 * V > vroot) : (V > 512);
+    int dummy_a = 0, dummy_p = 0;
+    const int ncand = allowed ? candidate(lo, hi, k.bins, -1, &dummy_a, &dummy_p) : 0;
+    int best = -1;
+    int64_t best_cost = 0;
+    if (ncand > 0) {
+        // tasks: (candidate, side, face)
+        for (int t = lane; t < ncand * 12; t += 64) {
+            const int c = t / 12, side = (t / 6) & 1, face = t % 6;
+            int a = 0, p = 0;
+            candidate(lo, hi, k.bins, c, &a, &p);
+            int rl[3] = {lo[0], lo[1], lo[2]}, rh[3] = {hi[0], hi[1], hi[2]};
+            if (side == 0) rh[a] = p; else rl[a] = p;
+            tb[wave][c][side][face] = tight_face(k, rl, rh, face);
+        }
+        wave_lds_sync();
+        int64_t cost = 0x7fffffffffffffffLL;
+        if (lane < ncand) {
+            const int *L = tb[wave][lane][0], *R = tb[wave][lane][1];
+            cost = box_volume(k, L, L + 3) + box_volume(k, R, R + 3);
+        }
+        // argmin over (cost, candidate index): lower index wins ties
+        int idx = lane < ncand ? lane : 0x7fffffff;
+        for (int o = 32; o >= 1; o >>= 1) {
+            const int64_t oc = __shfl_xor(cost, o, 64);
+            const int oi = __shfl_xor(idx, o, 64);
+            if (oc < cost || (oc == cost && oi < idx)) { cost = oc; idx = oi; }
+        }
+        best = idx;
+        best_cost = cost;
+    }
+    int axis = -1, plane = 0;
+    int cl[2][6];
+    if (best >= 0 && best_cost < V) {
+        candidate(lo, hi, k.bins, best, &axis, &plane);
+        for (int s = 0; s < 2; ++s)
+            for (int f = 0; f < 6; ++f) cl[s][f] = tb[wave][best][s][f];
+    } else if (best >= 0 && k.max_leaf > 0 &&
+               V > (int64_t)k.max_leaf * k.max_leaf * k.max_leaf) {
+        // maximum leaf size: middle of the axis with the largest voxel extent
+        int64_t best_ext = -1;
+        for (int a = 0; a < 3; ++a) {
+            const int e = hi[a] - lo[a];
+            if (e < 2) continue;
+            const int64_t ext = (int64_t)min(k.B * hi[a], k.n[a]) - (int64_t)k.B * lo[a];
+            if (ext > best_ext) { best_ext = ext; axis = a; plane = lo[a] + e / 2; }
+        }
+        if (lane < 12) {
+            const int side = lane / 6, face = lane % 6;
+            int rl[3] = {lo[0], lo[1], lo[2]}, rh[3] = {hi[0], hi[1], hi[2]};
+            if (side == 0) rh[axis] = plane; else rl[axis] = plane;
+            tb[wave][kMaxCand][side][face] = tight_face(k, rl, rh, face);
+        }
+        wave_lds_sync();
+        for (int s = 0; s < 2; ++s)
+            for (int f = 0; f < 6; ++f) cl[s][f] = tb[wave][kMaxCand][s][f];
+    }
+    if (lane == 0) {
+        k.axis[node] = axis;
+        k.plane[node] = axis >= 0 ? plane : 0;
+        k.split[node] = axis >= 0 ? 1 : 0;
+        if (axis >= 0)
+            for (int s = 0; s < 2; ++s)
+                for (int f = 0; f < 6; ++f) k.clo[12 * node + 6 * s + f] = cl[s][f];
+        if (axis < 0) k.first[node] = -1;
+    }
+}
+
+// single workgroup: breadth-first numbering of the children of [begin, end)
+__global__ __launch_bounds__(1024) void k_kd_emit(KdArgs k, uint32_t begin, uint32_t end)
+{
+    __shared__ uint32_t scratch[17];
+    const int64_t width = (int64_t)end - begin;
+    const int64_t per = (width + 1023) / 1024;
+    const int64_t i0 = begin + threadIdx.x * per;
+    const int64_t i1 = min((int64_t)end, i0 + per);
+    uint32_t c = 0;
+    for (int64_t i = i0; i < i1; ++i) c += (uint32_t)k.split[i];
+    uint32_t total;
+    uint32_t run = block_exclusive_scan<1024>(c, scratch, &total);
+    for (int64_t i = i0; i < i1; ++i) {
+        if (!k.split[i]) continue;
+        const int64_t child = (int64_t)end + 2 * (int64_t)run;
+        k.first[i] = (int32_t)child;
+        for (int s = 0; s < 2; ++s)
+            for (int q = 0; q < 3; ++q) {
+                k.lo[3 * (child + s) + q] = k.clo[12 * i + 6 * s + q];
+                k.hi[3 * (child + s) + q] = k.clo[12 * i + 6 * s + 3 + q];
+            }
+        ++run;
+    }
+    if (threadIdx.x == 0) {
+        k.hdr->kd_begin = end;
+        k.hdr->kd_end = end + 2 * total;
+        k.hdr->kd_count = end + 2 * total;
+        if (total > 0) k.hdr->kd_height += 1;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_kd_prefix(const KdArgs &k, hipStream_t s)
+{
+    const int64_t lines[3] = {(int64_t)k.nb[1] * k.nb[2], (int64_t)k.nb[0] * k.nb[2],
+                              (int64_t)k.nb[0] * k.nb[1]};
+    for (int a = 0; a < 3; ++a)
+        hipLaunchKernelGGL(k_prefix_axis, dim3((unsigned)((lines[a] + 255) / 256)), dim3(256), 0, s, k, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_kd_root(const KdArgs &k, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_kd_root, dim3(1), dim3(64), 0, s, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_kd_level(const KdArgs &k, uint32_t begin, uint32_t end, hipStream_t s)
+{
+    const int64_t width = (int64_t)end - begin;
+    if (width <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_kd_eval, dim3((unsigned)((width + 3) / 4)), dim3(256), 0, s, k, begin, end);
+    hipLaunchKernelGGL(k_kd_emit, dim3(1), dim3(1024), 0, s, k, begin, end);
+    return hipGetLastError();
+}
+
+}  // namespace esk

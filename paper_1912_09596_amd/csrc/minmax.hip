@@ -1,0 +1,264 @@
+// minmax.hip -- per-brick min/max of raw voxel values over each brick plus a
+// one-voxel apron (the TF-independent half of brick classification; Sec. 2
+// min-max range queries, Sec. 3.1 bricks).  HBM-bound: every voxel is read
+// once per brick row it borders; the apron rows shared by neighbouring brick
+// rows are re-read from L2 because neighbouring rows run on the same XCD.
+//
+// Work decomposition: one workgroup (4 waves) per (x segment, brick row by,
+// brick slab bz).  A segment is 64 lanes x E voxels of one voxel row.  Each
+// wave streams a quarter of the (B+2)^2 voxel rows of the window with 16-byte
+// loads, keeping per-column min/max in registers (packed u16 / f16 min-max for
+// the narrow types).  The four waves then meet in LDS, and one thread per
+// brick reduces its B+2 columns (the apron columns at the segment edges come
+// from two extra scalar loads per row).
+#include "esk_internal.hpp"
+
+namespace esk {
+namespace {
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
+
+// Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of logical blocks so neighbouring brick rows (which share
+// apron voxel rows) meet in the same L2.
+__device__ inline int xcd_remap(int b, int G)
+{
+    if (G < 8) return b;
+    int xcd = b & 7, per = G >> 3, rem = G & 7;
+    return xcd * per + min(xcd, rem) + (b >> 3);
+}
+
+template <typename T> struct Acc;
+
+template <> struct Acc<uint8_t> {
+    static constexpr int E = 16, LOADS = 1;
+    u16x2 mn[8], mx[8];
+    __device__ void init()
+    {
+        for (int i = 0; i < 8; ++i) { mn[i] = u16x2{0xffff, 0xffff}; mx[i] = u16x2{0, 0}; }
+    }
+    __device__ void update(const uint4 *v)
+    {
+        const uint32_t w[4] = {v[0].x, v[0].y, v[0].z, v[0].w};
+        for (int i = 0; i < 4; ++i) {
+            u16x2 lo = __builtin_bit_cast(u16x2, w[i] & 0x00ff00ffu);
+            u16x2 hi = __builtin_bit_cast(u16x2, (w[i] >> 8) & 0x00ff00ffu);
+            mn[2 * i] = __builtin_elementwise_min(mn[2 * i], lo);
+            mx[2 * i] = __builtin_elementwise_max(mx[2 * i], lo);
+            mn[2 * i + 1] = __builtin_elementwise_min(mn[2 * i + 1], hi);
+            mx[2 * i + 1] = __builtin_elementwise_max(mx[2 * i + 1], hi);
+        }
+    }
+    // column e of this lane: word e/4, byte e%4 -> pair 2*(e/4) + (byte&1), element byte/2
+    __device__ float cmin(int e) const { int b = e & 3; return (float)mn[2 * (e >> 2) + (b & 1)][b >> 1]; }
+    __device__ float cmax(int e) const { int b = e & 3; return (float)mx[2 * (e >> 2) + (b & 1)][b >> 1]; }
+};
+
+template <> struct Acc<uint16_t> {
+    static constexpr int E = 8, LOADS = 1;
+    u16x2 mn[4], mx[4];
+    __device__ void init()
+    {
+        for (int i = 0; i < 4; ++i) { mn[i] = u16x2{0xffff, 0xffff}; mx[i] = u16x2{0, 0}; }
+    }
+    __device__ void update(const uint4 *v)
+    {
+        const uint32_t w[4] = {v[0].x, v[0].y, v[0].z, v[0].w};
+        for (int i = 0; i < 4; ++i) {
+            u16x2 x = __builtin_bit_cast(u16x2, w[i]);
+            mn[i] = __builtin_elementwise_min(mn[i], x);
+            mx[i] = __builtin_elementwise_max(mx[i], x);
+        }
+    }
+    __device__ float cmin(int e) const { return (float)mn[e >> 1][e & 1]; }
+    __device__ float cmax(int e) const { return (float)mx[e >> 1][e & 1]; }
+};
+
+template <> struct Acc<_Float16> {
+    static constexpr int E = 8, LOADS = 1;
+    h16x2 mn[4], mx[4];
+    __device__ void init()
+    {
+        const _Float16 pinf = __builtin_bit_cast(_Float16, (uint16_t)0x7c00);
+        const _Float16 ninf = __builtin_bit_cast(_Float16, (uint16_t)0xfc00);
+        for (int i = 0; i < 4; ++i) { mn[i] = h16x2{pinf, pinf}; mx[i] = h16x2{ninf, ninf}; }
+    }
+    __device__ void update(const uint4 *v)
+    {
+        const uint32_t w[4] = {v[0].x, v[0].y, v[0].z, v[0].w};
+        for (int i = 0; i < 4; ++i) {
+            h16x2 x = __builtin_bit_cast(h16x2, w[i]);
+            mn[i] = __builtin_elementwise_min(mn[i], x);
+            mx[i] = __builtin_elementwise_max(mx[i], x);
+        }
+    }
+    __device__ float cmin(int e) const { return (float)mn[e >> 1][e & 1]; }
+    __device__ float cmax(int e) const { return (float)mx[e >> 1][e & 1]; }
+};
+
+template <> struct Acc<float> {
+    static constexpr int E = 8, LOADS = 2;
+    float mn[8], mx[8];
+    __device__ void init()
+    {
+        for (int i = 0; i < 8; ++i) { mn[i] = __builtin_inff(); mx[i] = -__builtin_inff(); }
+    }
+    __device__ void update(const uint4 *v)
+    {
+        const uint32_t w[8] = {v[0].x, v[0].y, v[0].z, v[0].w, v[1].x, v[1].y, v[1].z, v[1].w};
+        for (int i = 0; i < 8; ++i) {
+            float x = __builtin_bit_cast(float, w[i]);
+            mn[i] = fminf(mn[i], x);
+            mx[i] = fmaxf(mx[i], x);
+        }
+    }
+    __device__ float cmin(int e) const { return mn[e]; }
+    __device__ float cmax(int e) const { return mx[e]; }
+};
+
+template <typename T> __device__ inline float to_float(T v) { return (float)v; }
+
+template <typename T> __device__ inline T from_float(float f) { return (T)f; }
+
+// Loads the E voxels [xs, xs+E) of one row into uint4 words.  VEC: the row is
+// 16-byte aligned and nx % E == 0, so the chunk is either whole or absent.
+template <typename T, bool VEC>
+__device__ inline void load_chunk(const T *row, int xs, int nx, uint4 *buf)
+{
+    constexpr int E = Acc<T>::E, LOADS = Acc<T>::LOADS;
+    if (VEC) {
+        if (xs < nx) {
+            const uint4 *p = reinterpret_cast<const uint4 *>(row + xs);
+            for (int l = 0; l < LOADS; ++l) buf[l] = p[l];
+        } else {
+            for (int l = 0; l < LOADS; ++l) buf[l] = make_uint4(0, 0, 0, 0);
+        }
+    } else {
+        T tmp[E];
+        for (int e = 0; e < E; ++e) tmp[e] = (xs + e < nx) ? row[xs + e] : (T)0;
+        __builtin_memcpy(buf, tmp, sizeof(tmp));
+    }
+}
+
+template <typename T, bool VEC>
+__global__ __launch_bounds__(256) void k_minmax(const T *__restrict__ vol, int nx, int ny, int nz,
+                                                int B, int nbx, int nby, int nseg,
+                                                T *__restrict__ outmin, T *__restrict__ outmax)
+{
+    constexpr int E = Acc<T>::E, LOADS = Acc<T>::LOADS, SEG = 64 * E, U = 4;
+    __shared__ float smn[4][SEG], smx[4][SEG];
+    __shared__ float emn[4][2], emx[4][2];
+
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int seg = lb % nseg;
+    const int rest = lb / nseg;
+    const int by = rest % nby, bz = rest / nby;
+    const int x0 = seg * SEG;
+    const int y0 = max(0, by * B - 1), y1 = min(ny - 1, by * B + B);
+    const int z0 = max(0, bz * B - 1), z1 = min(nz - 1, bz * B + B);
+    const int ry = y1 - y0 + 1;
+    const int R = ry * (z1 - z0 + 1);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int xs = x0 + lane * E;
+
+    Acc<T> acc;
+    acc.init();
+    float eln = __builtin_inff(), elx = -__builtin_inff();
+    float ern = __builtin_inff(), erx = -__builtin_inff();
+    const bool has_left = (lane == 0) && x0 > 0;
+    const bool has_right = (lane == 63) && (x0 + SEG) < nx;
+
+    for (int r0 = wave; r0 < R; r0 += 4 * U) {
+        uint4 buf[U][LOADS];
+        float el[U], er[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int r = r0 + 4 * u;
+            el[u] = __builtin_inff();
+            er[u] = __builtin_inff();
+            if (r < R) {
+                const int y = y0 + r % ry, z = z0 + r / ry;
+                const T *row = vol + ((size_t)z * ny + y) * (size_t)nx;
+                load_chunk<T, VEC>(row, xs, nx, buf[u]);
+                if (has_left) el[u] = to_float(row[x0 - 1]);
+                if (has_right) er[u] = to_float(row[x0 + SEG]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (r0 + 4 * u < R) {
+                acc.update(buf[u]);
+                if (has_left) { eln = fminf(eln, el[u]); elx = fmaxf(elx, el[u]); }
+                if (has_right) { ern = fminf(ern, er[u]); erx = fmaxf(erx, er[u]); }
+            }
+        }
+    }
+
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        smn[wave][lane * E + e] = acc.cmin(e);
+        smx[wave][lane * E + e] = acc.cmax(e);
+    }
+    if (lane == 0) { emn[wave][0] = eln; emx[wave][0] = elx; }
+    if (lane == 63) { emn[wave][1] = ern; emx[wave][1] = erx; }
+    __syncthreads();
+
+    const int per_seg = SEG / B;
+    const int j = threadIdx.x;
+    if (j < per_seg) {
+        const int bx = seg * per_seg + j;
+        if (bx < nbx) {
+            float mn = __builtin_inff(), mx = -__builtin_inff();
+            const int c0 = j * B - 1, c1 = j * B + B;  // apron columns, segment-local
+            for (int c = c0; c <= c1; ++c) {
+                const int x = x0 + c;
+                if (x < 0 || x >= nx) continue;
+                for (int w = 0; w < 4; ++w) {
+                    float a, b;
+                    if (c < 0) { a = emn[w][0]; b = emx[w][0]; }
+                    else if (c >= SEG) { a = emn[w][1]; b = emx[w][1]; }
+                    else { a = smn[w][c]; b = smx[w][c]; }
+                    mn = fminf(mn, a);
+                    mx = fmaxf(mx, b);
+                }
+            }
+            const size_t id = (size_t)bx + (size_t)nbx * ((size_t)by + (size_t)nby * bz);
+            outmin[id] = from_float<T>(mn);
+            outmax[id] = from_float<T>(mx);
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_typed(const VolumeDesc &v, void *minv, void *maxv, hipStream_t s)
+{
+    constexpr int SEG = 64 * Acc<T>::E;
+    const int nseg = (v.nx + SEG - 1) / SEG;
+    const int64_t blocks = (int64_t)nseg * v.nb[1] * v.nb[2];
+    if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
+    const bool vec = (v.nx % Acc<T>::E == 0) && ((reinterpret_cast<uintptr_t>(v.vox) & 15) == 0);
+    const T *vol = static_cast<const T *>(v.vox);
+    if (vec)
+        hipLaunchKernelGGL((k_minmax<T, true>), dim3((unsigned)blocks), dim3(256), 0, s, vol, v.nx, v.ny,
+                           v.nz, v.B, v.nb[0], v.nb[1], nseg, (T *)minv, (T *)maxv);
+    else
+        hipLaunchKernelGGL((k_minmax<T, false>), dim3((unsigned)blocks), dim3(256), 0, s, vol, v.nx, v.ny,
+                           v.nz, v.B, v.nb[0], v.nb[1], nseg, (T *)minv, (T *)maxv);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_minmax(const VolumeDesc &v, void *minv, void *maxv, hipStream_t s)
+{
+    switch (v.dtype) {
+    case ESK_U8: return launch_typed<uint8_t>(v, minv, maxv, s);
+    case ESK_U16: return launch_typed<uint16_t>(v, minv, maxv, s);
+    case ESK_F16: return launch_typed<_Float16>(v, minv, maxv, s);
+    case ESK_F32: return launch_typed<float>(v, minv, maxv, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace esk

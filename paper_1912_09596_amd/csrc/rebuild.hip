@@ -1,0 +1,470 @@
+// rebuild.hip -- per-TF rebuild up to the LBVH (Sec. 3.1): TF prefix count,
+// brick classification + macrocell-grid bitmask, compaction, Morton codes,
+// radix sort, Karras hierarchy, bottom-up AABB refit.
+//
+// All of this is O(bricks) and latency-bound at interactive sizes (tens of
+// thousands of bricks), so kernels are few and wide: classification fuses the
+// TF prefix count (each block rebuilds it in LDS from the TF copy), the grid
+// bitmask (wave ballots) and the per-block non-empty counts; compaction fuses
+// the Morton encoding; one workgroup sorts up to 32K keys entirely in LDS.
+#include "esk_internal.hpp"
+#include "device_util.hpp"
+
+namespace esk {
+namespace {
+
+__device__ inline uint32_t spread3(uint32_t v)
+{
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__device__ inline uint32_t compact3(uint32_t v)
+{
+    v &= 0x09249249u;
+    v = (v | (v >> 2)) & 0x030c30c3u;
+    v = (v | (v >> 4)) & 0x0300f00fu;
+    v = (v | (v >> 8)) & 0x030000ffu;
+    v = (v | (v >> 16)) & 0x3ffu;
+    return v;
+}
+
+// x -> bits 3i+2, y -> 3i+1, z -> 3i
+__device__ inline uint32_t morton3(uint32_t x, uint32_t y, uint32_t z)
+{
+    return (spread3(x) << 2) | (spread3(y) << 1) | spread3(z);
+}
+
+__device__ inline uint64_t lanemask_lt() { return (1ull << (threadIdx.x & 63)) - 1ull; }
+
+// ---------------------------------------------------------------------------
+// a2 + a3 + grid: classification
+// ---------------------------------------------------------------------------
+
+template <typename T> __device__ inline float raw(const void *p, int64_t i)
+{
+    return (float)static_cast<const T *>(p)[i];
+}
+
+// floor of x(v) = s(v) * (N-1); integer types exact, float types in FP32
+// (this translation unit is compiled without FP contraction)
+__device__ inline int tf_floor_index(float v, int dtype, float lo, float hi, int N)
+{
+    if (dtype == ESK_U8) return ((int)v * (N - 1)) / 255;
+    if (dtype == ESK_U16) return ((int)v * (N - 1)) / 65535;
+    float num = v - lo;
+    float den = hi - lo;
+    float s = num / den;
+    s = s < 0.0f ? 0.0f : s;
+    s = s > 1.0f ? 1.0f : s;
+    float x = s * (float)(N - 1);
+    return (int)floorf(x);
+}
+
+__device__ inline float load_minmax(const void *p, int dtype, int64_t i)
+{
+    switch (dtype) {
+    case ESK_U8: return raw<uint8_t>(p, i);
+    case ESK_U16: return raw<uint16_t>(p, i);
+    case ESK_F16: return raw<_Float16>(p, i);
+    default: return raw<float>(p, i);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_classify(RebuildArgs a)
+{
+    __shared__ int32_t P[kMaxTF + 1];
+    __shared__ uint32_t scratch[8];
+    __shared__ uint32_t wcount[16];
+    const int N = a.N;
+    // TF prefix count: 16 entries per thread
+    {
+        const int per = (N + 255) / 256;
+        const int i0 = threadIdx.x * per;
+        uint32_t c = 0;
+        for (int i = i0; i < min(N, i0 + per); ++i) c += a.tf[4 * i + 3] > 0.0f ? 1u : 0u;
+        uint32_t tot;
+        uint32_t run = block_exclusive_scan<256>(c, scratch, &tot);
+        for (int i = i0; i < min(N, i0 + per); ++i) {
+            P[i] = (int32_t)run;
+            run += a.tf[4 * i + 3] > 0.0f ? 1u : 0u;
+        }
+        if (threadIdx.x == 0) P[N] = (int32_t)tot;
+        __syncthreads();
+        if (blockIdx.x == 0)
+            for (int i = threadIdx.x; i <= N; i += 256) a.tfP[i] = P[i];
+    }
+    const int64_t base = (int64_t)blockIdx.x * kClassifyBlock;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int j = 0; j < 4; ++j) {
+        const int64_t b = base + 256 * j + threadIdx.x;
+        int flag = 0;
+        if (b < a.nb) {
+            float mn = load_minmax(a.minv, a.vol.dtype, b);
+            float mx = load_minmax(a.maxv, a.vol.dtype, b);
+            int lo = tf_floor_index(mn, a.vol.dtype, a.vlo, a.vhi, N) - 1;
+            int hi = tf_floor_index(mx, a.vol.dtype, a.vlo, a.vhi, N) + 2;
+            lo = max(lo, 0);
+            hi = min(hi, N - 1);
+            flag = (P[hi + 1] - P[lo]) > 0;
+            a.flags[b] = (uint8_t)flag;
+        }
+        const uint64_t m = __ballot(flag);
+        if (lane == 0) {
+            const int64_t word = (base + 256 * j + 64 * wave) >> 5;
+            a.grid[word] = (uint32_t)m;
+            a.grid[word + 1] = (uint32_t)(m >> 32);
+            wcount[4 * j + wave] = __popcll(m);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int i = 0; i < 16; ++i) t += wcount[i];
+        a.blkcnt[blockIdx.x] = t;
+    }
+}
+
+// exclusive scan of the per-block counts (single workgroup); total -> hdr->n
+__global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t *cnt, int64_t nblk, DevHeader *hdr)
+{
+    __shared__ uint32_t scratch[17];
+    const int64_t per = (nblk + 1023) / 1024;
+    const int64_t i0 = threadIdx.x * per;
+    uint32_t c = 0;
+    for (int64_t i = i0; i < min(nblk, i0 + per); ++i) c += cnt[i];
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan<1024>(c, scratch, &tot);
+    for (int64_t i = i0; i < min(nblk, i0 + per); ++i) {
+        uint32_t t = cnt[i];
+        cnt[i] = run;
+        run += t;
+    }
+    if (threadIdx.x == 0) {
+        hdr->n = tot;
+        hdr->lbvh_height = 0;
+    }
+}
+
+// a4 + a5: compaction in ascending brick id, with Morton keys
+__global__ __launch_bounds__(256) void k_compact(RebuildArgs a)
+{
+    __shared__ uint32_t woff[16];
+    const int64_t base = (int64_t)blockIdx.x * kClassifyBlock;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t *gw = a.grid + (base >> 5);
+    if (threadIdx.x < 16) {
+        // word pair of (j, wave) = 2*(4*j + wave) relative to the block
+        const int q = threadIdx.x;
+        woff[q] = __popc(gw[2 * q]) + __popc(gw[2 * q + 1]);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = a.blkcnt[blockIdx.x];
+        for (int q = 0; q < 16; ++q) {
+            uint32_t t = woff[q];
+            woff[q] = run;
+            run += t;
+        }
+    }
+    __syncthreads();
+    for (int j = 0; j < 4; ++j) {
+        const int q = 4 * j + wave;
+        const uint64_t m = (uint64_t)gw[2 * q] | ((uint64_t)gw[2 * q + 1] << 32);
+        if ((m >> lane) & 1ull) {
+            const int64_t b = base + 64 * q + lane;
+            const uint32_t pos = woff[q] + (uint32_t)__popcll(m & lanemask_lt());
+            const uint32_t bx = (uint32_t)(b % a.vol.nb[0]);
+            const uint32_t by = (uint32_t)((b / a.vol.nb[0]) % a.vol.nb[1]);
+            const uint32_t bz = (uint32_t)(b / ((int64_t)a.vol.nb[0] * a.vol.nb[1]));
+            a.ids[pos] = (uint32_t)b;
+            a.keys[pos] = morton3(bx, by, bz);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a6: LSD radix sort of the Morton keys (ids are recovered from keys)
+// ---------------------------------------------------------------------------
+
+// LDS index with one pad word every 32 so that blocked per-thread access
+// (thread t reads items t*I .. t*I+I-1) spreads over the banks
+__device__ inline int padx(int i) { return i + (i >> 5); }
+
+// Stable sort of n <= THREADS*ITEMS keys held in LDS `s` (padded indexing)
+// by bits [bit0, bit0+nbits), two bits per pass (four buckets).
+template <int THREADS, int ITEMS>
+__device__ void lds_split_sort(uint32_t *s, int n, int bit0, int nbits, uint32_t *scratch)
+{
+    const int I = (n + THREADS - 1) / THREADS;  // items per thread this call
+    const int first = threadIdx.x * I;
+    const int cnt = max(0, min(I, n - first));
+    for (int bit = bit0; bit < bit0 + nbits; bit += 2) {
+        const int width = min(2, bit0 + nbits - bit);
+        const uint32_t mask = (1u << width) - 1u;
+        uint32_t k[ITEMS];
+        uint32_t c01 = 0, c23 = 0;  // packed counts: buckets 0,1 in c01; 2,3 in c23 (16 bits each)
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            if (j < cnt) {
+                k[j] = s[padx(first + j)];
+                const uint32_t d = (k[j] >> bit) & mask;
+                const uint32_t inc = 1u << (16 * (d & 1));
+                if (d < 2) c01 += inc; else c23 += inc;
+            }
+        }
+        uint32_t t01, t23;
+        const uint32_t e01 = block_exclusive_scan<THREADS>(c01, scratch, &t01);
+        const uint32_t e23 = block_exclusive_scan<THREADS>(c23, scratch, &t23);
+        const uint32_t n0 = t01 & 0xffffu, n1 = t01 >> 16, n2 = t23 & 0xffffu;
+        uint32_t off[4] = {e01 & 0xffffu, n0 + (e01 >> 16), n0 + n1 + (e23 & 0xffffu),
+                           n0 + n1 + n2 + (e23 >> 16)};
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            if (j < cnt) {
+                const uint32_t d = (k[j] >> bit) & mask;
+                uint32_t p;
+                // select without dynamic register indexing
+                if (d == 0) p = off[0]++;
+                else if (d == 1) p = off[1]++;
+                else if (d == 2) p = off[2]++;
+                else p = off[3]++;
+                s[padx((int)p)] = k[j];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// single workgroup: sorts all n <= 32768 keys in LDS, writes sorted keys and ids
+__global__ __launch_bounds__(1024) void k_sort_single(RebuildArgs a)
+{
+    extern __shared__ uint32_t s[];
+    __shared__ uint32_t scratch[17];
+    const int n = (int)a.hdr->n;
+    for (int i = threadIdx.x; i < n; i += 1024) s[padx(i)] = a.keys[i];
+    __syncthreads();
+    lds_split_sort<1024, 32>(s, n, 0, a.key_bits, scratch);
+    for (int i = threadIdx.x; i < n; i += 1024) a.skeys[i] = s[padx(i)];
+}
+
+// multi-block LSD pass, 8-bit digits: per-block histograms (digit-major)
+__global__ __launch_bounds__(256) void k_sort_hist(const uint32_t *in, const DevHeader *hdr, int bit,
+                                                   uint32_t *hist, int64_t nblocks)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t n = hdr->n;
+    const int64_t base = (int64_t)blockIdx.x * kSortBlockKeys;
+    for (int i = threadIdx.x; i < kSortBlockKeys; i += 256) {
+        const int64_t g = base + i;
+        if (g < n) atomicAdd(&h[(in[g] >> bit) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// exclusive scan over the digit-major histogram (single workgroup)
+__global__ __launch_bounds__(1024) void k_sort_scan(uint32_t *hist, int64_t len)
+{
+    __shared__ uint32_t scratch[17];
+    const int64_t per = (len + 1023) / 1024;
+    const int64_t i0 = threadIdx.x * per;
+    uint32_t c = 0;
+    for (int64_t i = i0; i < min(len, i0 + per); ++i) c += hist[i];
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan<1024>(c, scratch, &tot);
+    for (int64_t i = i0; i < min(len, i0 + per); ++i) {
+        uint32_t t = hist[i];
+        hist[i] = run;
+        run += t;
+    }
+}
+
+// stable scatter: the block sorts its keys locally by the digit, then each key
+// goes to (global offset of its digit in this block) + (rank inside the digit)
+__global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t *in, uint32_t *out,
+                                                      const DevHeader *hdr, int bit,
+                                                      const uint32_t *hist, int64_t nblocks)
+{
+    __shared__ uint32_t s[kSortBlockKeys + kSortBlockKeys / 32];
+    __shared__ uint32_t scratch[5];
+    __shared__ uint32_t start[256];
+    const int64_t n = hdr->n;
+    const int64_t base = (int64_t)blockIdx.x * kSortBlockKeys;
+    const int cnt = (int)max((int64_t)0, min((int64_t)kSortBlockKeys, n - base));
+    if (cnt == 0) return;
+    for (int i = threadIdx.x; i < cnt; i += 256) s[padx(i)] = in[base + i];
+    __syncthreads();
+    lds_split_sort<256, 16>(s, cnt, bit, 8, scratch);
+    // first local position of each digit
+    start[threadIdx.x] = 0xffffffffu;
+    __syncthreads();
+    for (int i = threadIdx.x; i < cnt; i += 256) {
+        const uint32_t d = (s[padx(i)] >> bit) & 255u;
+        if (i == 0 || ((s[padx(i - 1)] >> bit) & 255u) != d) start[d] = (uint32_t)i;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < cnt; i += 256) {
+        const uint32_t k = s[padx(i)];
+        const uint32_t d = (k >> bit) & 255u;
+        const uint32_t pos = hist[(int64_t)d * nblocks + blockIdx.x] + ((uint32_t)i - start[d]);
+        out[pos] = k;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a7 + a8: Karras hierarchy and bottom-up refit
+// ---------------------------------------------------------------------------
+
+__device__ inline int delta(const uint32_t *k, int n, int i, int j)
+{
+    if (j < 0 || j >= n) return -1;
+    return __clz(k[i] ^ k[j]);
+}
+
+// one thread per key: leaf j gets its brick id and box; internal node i < n-1
+// gets its children (Karras 2012: direction, range by doubling + binary
+// search, split by binary search) and registers itself as their parent.
+// Node numbering: internal i -> i, leaf j -> (n-1)+j.
+__global__ __launch_bounds__(256) void k_karras(RebuildArgs a)
+{
+    const int n = (int)a.hdr->n;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t *k = a.skeys;
+    {
+        const uint32_t key = k[i];
+        const uint32_t bx = compact3(key >> 2), by = compact3(key >> 1), bz = compact3(key);
+        a.sids[i] = bx + (uint32_t)a.vol.nb[0] * (by + (uint32_t)a.vol.nb[1] * bz);
+        const int node = (n - 1) + i;
+        const int b[3] = {(int)bx, (int)by, (int)bz};
+        const int nn[3] = {a.vol.nx, a.vol.ny, a.vol.nz};
+        for (int q = 0; q < 3; ++q) {
+            a.lb_lo[3 * node + q] = a.vol.B * b[q];
+            a.lb_hi[3 * node + q] = min(a.vol.B * b[q] + a.vol.B, nn[q]);
+        }
+        a.lb_height[node] = 1;
+    }
+    if (i >= n - 1) return;
+    const int d = (delta(k, n, i, i + 1) - delta(k, n, i, i - 1)) > 0 ? 1 : -1;
+    const int dmin = delta(k, n, i, i - d);
+    int lmax = 2;
+    while (delta(k, n, i, i + lmax * d) > dmin) lmax <<= 1;
+    int l = 0;
+    for (int t = lmax >> 1; t >= 1; t >>= 1)
+        if (delta(k, n, i, i + (l + t) * d) > dmin) l += t;
+    const int j = i + l * d;
+    const int dnode = delta(k, n, i, j);
+    int s = 0;
+    for (int div = 2;; div <<= 1) {
+        const int t = (l + div - 1) / div;
+        if (delta(k, n, i, i + (s + t) * d) > dnode) s += t;
+        if (t == 1) break;
+    }
+    const int g = i + s * d + min(d, 0);
+    const int lo = min(i, j), hi = max(i, j);
+    const uint32_t left = (lo == g) ? (kLeaf | (uint32_t)g) : (uint32_t)g;
+    const uint32_t right = (hi == g + 1) ? (kLeaf | (uint32_t)(g + 1)) : (uint32_t)(g + 1);
+    a.lb_left[i] = left;
+    a.lb_right[i] = right;
+    const int hb = 31 - dnode;  // highest differing bit of the range
+    a.lb_axis[i] = 2 - hb % 3;
+    a.lb_parent[(left & kLeaf) ? (n - 1) + g : g] = (uint32_t)i;
+    a.lb_parent[(right & kLeaf) ? (n - 1) + g + 1 : g + 1] = (uint32_t)i;
+    a.lb_flag[i] = 0;
+}
+
+// one thread per leaf climbs to the root; the second child to arrive at a
+// node computes its union box and height (release/acquire at agent scope so
+// the sibling's box is visible across XCDs)
+__global__ __launch_bounds__(256) void k_refit(RebuildArgs a)
+{
+    const int n = (int)a.hdr->n;
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    if (n == 1) {
+        a.hdr->lbvh_height = 1;
+        return;
+    }
+    uint32_t cur = a.lb_parent[(n - 1) + j];
+    while (true) {
+        __threadfence();
+        const uint32_t old = __hip_atomic_fetch_add(&a.lb_flag[cur], 1u, __ATOMIC_ACQ_REL,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        if (old == 0) return;
+        __threadfence();
+        const uint32_t l = a.lb_left[cur], r = a.lb_right[cur];
+        const int ln = (l & kLeaf) ? (n - 1) + (int)(l & ~kLeaf) : (int)l;
+        const int rn = (r & kLeaf) ? (n - 1) + (int)(r & ~kLeaf) : (int)r;
+        for (int q = 0; q < 3; ++q) {
+            const int lo0 = __hip_atomic_load(&a.lb_lo[3 * ln + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int lo1 = __hip_atomic_load(&a.lb_lo[3 * rn + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int hi0 = __hip_atomic_load(&a.lb_hi[3 * ln + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int hi1 = __hip_atomic_load(&a.lb_hi[3 * rn + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.lb_lo[3 * cur + q], min(lo0, lo1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.lb_hi[3 * cur + q], max(hi0, hi1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const uint32_t hl = __hip_atomic_load(&a.lb_height[ln], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t hr = __hip_atomic_load(&a.lb_height[rn], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t h = 1 + max(hl, hr);
+        __hip_atomic_store(&a.lb_height[cur], h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cur == 0) {
+            a.hdr->lbvh_height = h;
+            return;
+        }
+        cur = a.lb_parent[cur];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_classify_compact(const RebuildArgs &a, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)a.nblk;
+    hipLaunchKernelGGL(k_classify, dim3(blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, a.blkcnt, a.nblk, a.hdr);
+    hipLaunchKernelGGL(k_compact, dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort(const RebuildArgs &a, hipStream_t s)
+{
+    if (a.nb <= kSortSingleMax) {
+        const size_t lds = sizeof(uint32_t) * (kSortSingleMax + kSortSingleMax / 32);
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sort_single),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_sort_single, dim3(1), dim3(1024), lds, s, a);
+        return hipGetLastError();
+    }
+    // multi-block: ping-pong keys -> tmpkeys -> ... ending in skeys
+    const int passes = (a.key_bits + 7) / 8;
+    const uint32_t *src = a.keys;
+    for (int p = 0; p < passes; ++p) {
+        uint32_t *dst = ((passes - 1 - p) % 2 == 0) ? a.skeys : a.tmpkeys;
+        hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)a.nsortblk), dim3(256), 0, s, src, a.hdr, 8 * p,
+                           a.hist, a.nsortblk);
+        hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, a.hist, 256 * a.nsortblk);
+        hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)a.nsortblk), dim3(256), 0, s, src, dst, a.hdr,
+                           8 * p, a.hist, a.nsortblk);
+        src = dst;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_lbvh(const RebuildArgs &a, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)((a.nb + 255) / 256);
+    hipLaunchKernelGGL(k_karras, dim3(blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_refit, dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace esk

@@ -1,0 +1,430 @@
+// render.hip -- ray marching with empty-space skipping (Sec. 3, Sec. 4.1).
+//
+// Emission-absorption, post-classification (interpolate, then look up the
+// TF), no gradient shading, no early ray termination.  One lane per pixel,
+// one wave per 8x8 pixel tile, four waves per 16x16 tile.
+//
+// Every accelerator visits a subset of one global sample lattice per ray,
+// t_k = t0 + (k+1/2) dt, and only ever drops samples that lie in empty
+// bricks (alpha exactly 0), so every mode produces the same image as the
+// full march, bit for bit:
+//  - NONE: every k with t_k < t_exit whose point lies in [0,n)^3.
+//  - GRID: the same loop, but a sample in an empty macrocell (= brick) jumps
+//    to the last sample still inside that brick.  Sample points are
+//    monotone per component in k, so if the first and the last sample of the
+//    jump lie in the same brick, so do all samples between them.
+//  - LBVH / KD: ordered traversal (near child first by the sign of the ray
+//    direction along the node's split axis; children are separated by that
+//    plane, so leaves come out in sample order).  For each leaf, a
+//    conservative k range comes from an expanded slab test and each sample is
+//    kept iff its point lies inside the leaf's box (half-open).
+//
+// Geometry (ray set-up, slabs, t_k, p_k, membership) is FP32 without
+// contraction: the whole file is compiled with -ffp-contract=off, and the
+// value path uses explicit fmaf.
+#include "esk_internal.hpp"
+
+namespace esk {
+namespace {
+
+constexpr float kBoxEps = 1.0f / 32.0f;   // voxel-space slack of the culling tests
+
+struct Ray {
+    float o[3], d[3];
+    float t0, tx;
+};
+
+__device__ inline void make_ray(const esk_camera &c, int px, int py, Ray &r)
+{
+    const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+    float v[3];
+    for (int a = 0; a < 3; ++a) {
+        const float t1 = fx * c.du[a];
+        const float t2 = fy * c.dv[a];
+        if (c.ortho) {
+            r.o[a] = (c.eye[a] + t1) + t2;
+            v[a] = c.dir00[a];
+        } else {
+            r.o[a] = c.eye[a];
+            v[a] = (c.dir00[a] + t1) + t2;
+        }
+    }
+    const float l2 = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
+    const float len = sqrtf(l2);
+    for (int a = 0; a < 3; ++a) r.d[a] = v[a] / len;
+}
+
+__device__ inline bool slab(const Ray &r, const float lo[3], const float hi[3], float &tn, float &tf)
+{
+    float t0 = -3.402823466e+38f, t1 = 3.402823466e+38f;
+    for (int a = 0; a < 3; ++a) {
+        if (r.d[a] != 0.0f) {
+            const float ta = (lo[a] - r.o[a]) / r.d[a];
+            const float tb = (hi[a] - r.o[a]) / r.d[a];
+            const float mn = ta < tb ? ta : tb;
+            const float mx = ta < tb ? tb : ta;
+            if (mn > t0) t0 = mn;
+            if (mx < t1) t1 = mx;
+        } else if (r.o[a] < lo[a] || r.o[a] >= hi[a]) {
+            return false;
+        }
+    }
+    tn = t0;
+    tf = t1;
+    return true;
+}
+
+__device__ inline float lattice_t(const Ray &r, float dt, int k)
+{
+    const float kk = (float)k + 0.5f;
+    const float step = kk * dt;
+    return r.t0 + step;
+}
+
+__device__ inline void point_at(const Ray &r, float t, float p[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        const float td = t * r.d[a];
+        p[a] = r.o[a] + td;
+    }
+}
+
+struct Accum {
+    float c[3], a;
+    int n;
+};
+
+template <typename T, typename IDX>
+__device__ inline float trilinear(const T *__restrict__ vol, int nx, int ny, int nz, const float p[3])
+{
+    const float ux = p[0] - 0.5f, uy = p[1] - 0.5f, uz = p[2] - 0.5f;
+    const float fx = floorf(ux), fy = floorf(uy), fz = floorf(uz);
+    const float wx = ux - fx, wy = uy - fy, wz = uz - fz;
+    const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
+    const int x0 = min(max(ix, 0), nx - 1), x1 = min(max(ix + 1, 0), nx - 1);
+    const int y0 = min(max(iy, 0), ny - 1), y1 = min(max(iy + 1, 0), ny - 1);
+    const int z0 = min(max(iz, 0), nz - 1), z1 = min(max(iz + 1, 0), nz - 1);
+    const IDX sy = (IDX)nx, sz = (IDX)nx * (IDX)ny;
+    const IDX r00 = (IDX)z0 * sz + (IDX)y0 * sy, r10 = (IDX)z0 * sz + (IDX)y1 * sy;
+    const IDX r01 = (IDX)z1 * sz + (IDX)y0 * sy, r11 = (IDX)z1 * sz + (IDX)y1 * sy;
+    const float v000 = (float)vol[r00 + x0], v100 = (float)vol[r00 + x1];
+    const float v010 = (float)vol[r10 + x0], v110 = (float)vol[r10 + x1];
+    const float v001 = (float)vol[r01 + x0], v101 = (float)vol[r01 + x1];
+    const float v011 = (float)vol[r11 + x0], v111 = (float)vol[r11 + x1];
+    const float c00 = fmaf(wx, v100 - v000, v000), c10 = fmaf(wx, v110 - v010, v010);
+    const float c01 = fmaf(wx, v101 - v001, v001), c11 = fmaf(wx, v111 - v011, v011);
+    const float c0 = fmaf(wy, c10 - c00, c00), c1 = fmaf(wy, c11 - c01, c01);
+    return fmaf(wz, c1 - c0, c0);
+}
+
+struct Shade {
+    const float4 *tf;
+    int N;
+    float vlo, vscale, expo;
+    int correct;
+};
+
+// post-classification + opacity correction + front-to-back "over"
+__device__ inline void composite(const Shade &s, float v, Accum &acc)
+{
+    float x = (v - s.vlo) * s.vscale;
+    x = fminf(fmaxf(x, 0.0f), 1.0f) * (float)(s.N - 1);
+    const int i0 = min((int)x, s.N - 2);
+    const float f = x - (float)i0;
+    const float4 a = s.tf[i0], b = s.tf[i0 + 1];
+    const float r = fmaf(f, b.x - a.x, a.x);
+    const float g = fmaf(f, b.y - a.y, a.y);
+    const float bl = fmaf(f, b.z - a.z, a.z);
+    float al = fmaf(f, b.w - a.w, a.w);
+    if (s.correct) {
+        // 1 - (1-a)^(dt/ref); exactly 0 for a == 0
+        const float l = __builtin_amdgcn_logf(1.0f - al);
+        const float e = __builtin_amdgcn_exp2f(s.expo * l);
+        al = al > 0.0f ? 1.0f - e : 0.0f;
+    }
+    const float w = (1.0f - acc.a) * al;
+    acc.c[0] = fmaf(w, r, acc.c[0]);
+    acc.c[1] = fmaf(w, g, acc.c[1]);
+    acc.c[2] = fmaf(w, bl, acc.c[2]);
+    acc.a = acc.a + w;
+    acc.n += 1;
+}
+
+struct Vol {
+    int n[3];
+    float fn[3];
+};
+
+__device__ inline bool inside(const Vol &v, const float p[3])
+{
+    return p[0] >= 0.0f && p[0] < v.fn[0] && p[1] >= 0.0f && p[1] < v.fn[1] && p[2] >= 0.0f &&
+           p[2] < v.fn[2];
+}
+
+// conservative hit of a box [lo, hi) (integer voxel bounds) by the ray segment
+__device__ inline bool hit_box(const Ray &r, float dt, const int lo[3], const int hi[3])
+{
+    float l[3], h[3];
+    for (int a = 0; a < 3; ++a) {
+        l[a] = (float)lo[a] - kBoxEps;
+        h[a] = (float)hi[a] + kBoxEps;
+    }
+    float tn, tf;
+    if (!slab(r, l, h, tn, tf)) return false;
+    return tn <= tf + dt && tf >= r.t0 - dt && tn <= r.tx + dt;
+}
+
+// samples of the lattice that fall in the leaf box [lo, hi)
+template <typename T, typename IDX>
+__device__ inline void march_leaf(const Ray &r, float dt, const int lo[3], const int hi[3],
+                                  const T *__restrict__ vol, const Vol &v, const Shade &s, Accum &acc)
+{
+    float l[3], h[3], bl[3], bh[3];
+    for (int a = 0; a < 3; ++a) {
+        bl[a] = (float)lo[a];
+        bh[a] = (float)hi[a];
+        l[a] = bl[a] - kBoxEps;
+        h[a] = bh[a] + kBoxEps;
+    }
+    float tn, tf;
+    if (!slab(r, l, h, tn, tf)) return;
+    float fa = (tn - r.t0) / dt - 0.5f;
+    float fb = (tf - r.t0) / dt - 0.5f;
+    fa = fminf(fmaxf(fa, -4.0f), 1.0e9f);
+    fb = fminf(fmaxf(fb, -4.0f), 1.0e9f);
+    const int ka = max(0, (int)floorf(fa) - 1);
+    const int kb = (int)floorf(fb) + 2;
+    for (int k = ka; k < kb; ++k) {
+        const float t = lattice_t(r, dt, k);
+        if (!(t < r.tx)) break;
+        float p[3];
+        point_at(r, t, p);
+        if (p[0] >= bl[0] && p[0] < bh[0] && p[1] >= bl[1] && p[1] < bh[1] && p[2] >= bl[2] && p[2] < bh[2])
+            composite(s, trilinear<T, IDX>(vol, v.n[0], v.n[1], v.n[2], p), acc);
+    }
+}
+
+template <int ACCEL, typename T, typename IDX>
+__global__ __launch_bounds__(256) void k_render(RenderArgs ra)
+{
+    extern __shared__ float4 lds[];
+    const bool tf_lds = ra.N <= 1024;
+    if (tf_lds) {
+        const float4 *src = reinterpret_cast<const float4 *>(ra.tf);
+        for (int i = threadIdx.x; i < ra.N; i += 256) lds[i] = src[i];
+        __syncthreads();
+    }
+    int *stk = reinterpret_cast<int *>(lds + (tf_lds ? 1024 : 0));
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int px = blockIdx.x * 16 + (wave & 1) * 8 + (lane & 7);
+    const int py = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
+    if (px >= ra.W || py >= ra.H) return;
+
+    const T *__restrict__ vol = static_cast<const T *>(ra.vol.vox);
+    Vol v;
+    v.n[0] = ra.vol.nx; v.n[1] = ra.vol.ny; v.n[2] = ra.vol.nz;
+    for (int a = 0; a < 3; ++a) v.fn[a] = (float)v.n[a];
+    Shade s;
+    s.tf = tf_lds ? lds : reinterpret_cast<const float4 *>(ra.tf);
+    s.N = ra.N;
+    s.vlo = ra.vlo;
+    s.vscale = ra.vscale;
+    s.expo = ra.expo;
+    s.correct = ra.correct;
+    const float dt = ra.dt;
+
+    Accum acc = {{0.0f, 0.0f, 0.0f}, 0.0f, 0};
+    Ray r;
+    make_ray(ra.cam, px, py, r);
+    const float zero[3] = {0.0f, 0.0f, 0.0f};
+    float tn, tx;
+    if (slab(r, zero, v.fn, tn, tx)) {
+        r.t0 = tn > 0.0f ? tn : 0.0f;
+        r.tx = tx;
+        if (ACCEL == ESK_ACCEL_NONE) {
+            for (int k = 0;; ++k) {
+                const float t = lattice_t(r, dt, k);
+                if (!(t < r.tx)) break;
+                float p[3];
+                point_at(r, t, p);
+                if (inside(v, p)) composite(s, trilinear<T, IDX>(vol, v.n[0], v.n[1], v.n[2], p), acc);
+            }
+        } else if (ACCEL == ESK_ACCEL_GRID) {
+            const int sh = ra.vol.log2B, B = ra.vol.B;
+            const int nbx = ra.vol.nb[0], nby = ra.vol.nb[1];
+            int k = 0;
+            while (true) {
+                const float t = lattice_t(r, dt, k);
+                if (!(t < r.tx)) break;
+                float p[3];
+                point_at(r, t, p);
+                if (!inside(v, p)) { ++k; continue; }
+                const int bx = (int)p[0] >> sh, by = (int)p[1] >> sh, bz = (int)p[2] >> sh;
+                const int64_t b = (int64_t)bx + (int64_t)nbx * ((int64_t)by + (int64_t)nby * bz);
+                if ((ra.grid[b >> 5] >> (b & 31)) & 1u) {
+                    composite(s, trilinear<T, IDX>(vol, v.n[0], v.n[1], v.n[2], p), acc);
+                    ++k;
+                    continue;
+                }
+                // empty macrocell: jump to the last sample inside it
+                const float blo[3] = {(float)(bx * B), (float)(by * B), (float)(bz * B)};
+                const float bhi[3] = {(float)min(bx * B + B, v.n[0]), (float)min(by * B + B, v.n[1]),
+                                      (float)min(bz * B + B, v.n[2])};
+                float cn, cx;
+                int next = k + 1;
+                if (slab(r, blo, bhi, cn, cx)) {
+                    float fj = (cx - r.t0) / dt - 0.5f;
+                    fj = fminf(fmaxf(fj, -4.0f), 1.0e9f);
+                    const int kj = (int)floorf(fj);
+                    for (int c = kj; c >= kj - 1; --c) {
+                        if (c <= k) break;
+                        float q[3];
+                        point_at(r, lattice_t(r, dt, c), q);
+                        if (inside(v, q) && ((int)q[0] >> sh) == bx && ((int)q[1] >> sh) == by &&
+                            ((int)q[2] >> sh) == bz) {
+                            next = c + 1;
+                            break;
+                        }
+                    }
+                }
+                k = next;
+            }
+        } else if (ACCEL == ESK_ACCEL_LBVH) {
+            const int N = (int)ra.hdr->n;
+            if (N > 0) {
+                auto box_of = [&](uint32_t node, int lo[3], int hi[3]) {
+                    const int u = (node & kLeaf) ? (N - 1) + (int)(node & ~kLeaf) : (int)node;
+                    for (int a = 0; a < 3; ++a) {
+                        lo[a] = ra.lb_lo[3 * u + a];
+                        hi[a] = ra.lb_hi[3 * u + a];
+                    }
+                };
+                uint32_t node = (N == 1) ? kLeaf : 0u;
+                int lo[3], hi[3];
+                box_of(node, lo, hi);
+                int sp = 0;
+                bool live = hit_box(r, dt, lo, hi);
+                while (live) {
+                    if (node & kLeaf) {
+                        box_of(node, lo, hi);
+                        march_leaf<T, IDX>(r, dt, lo, hi, vol, v, s, acc);
+                    } else {
+                        const int a = ra.lb_axis[node];
+                        const uint32_t l = ra.lb_left[node], rr = ra.lb_right[node];
+                        const uint32_t nr = r.d[a] < 0.0f ? rr : l;
+                        const uint32_t fr = r.d[a] < 0.0f ? l : rr;
+                        int l0[3], h0[3], l1[3], h1[3];
+                        box_of(nr, l0, h0);
+                        box_of(fr, l1, h1);
+                        const bool hn = hit_box(r, dt, l0, h0), hf = hit_box(r, dt, l1, h1);
+                        if (hn && hf && sp < ra.stack_cap) {
+                            stk[sp * 256 + threadIdx.x] = (int)fr;
+                            ++sp;
+                            node = nr;
+                            continue;
+                        }
+                        if (hn) { node = nr; continue; }
+                        if (hf) { node = fr; continue; }
+                    }
+                    if (sp == 0) break;
+                    --sp;
+                    node = (uint32_t)stk[sp * 256 + threadIdx.x];
+                }
+            }
+        } else if (ACCEL == ESK_ACCEL_KD) {
+            const int M = (int)ra.hdr->kd_count;
+            if (M > 0) {
+                const int B = ra.vol.B;
+                auto box_of = [&](int node, int lo[3], int hi[3]) {
+                    for (int a = 0; a < 3; ++a) {
+                        lo[a] = B * ra.kd_lo[3 * node + a];
+                        hi[a] = min(B * ra.kd_hi[3 * node + a], v.n[a]);
+                    }
+                };
+                int node = 0;
+                int lo[3], hi[3];
+                box_of(0, lo, hi);
+                int sp = 0;
+                bool live = hit_box(r, dt, lo, hi);
+                while (live) {
+                    const int a = ra.kd_axis[node];
+                    if (a < 0) {
+                        box_of(node, lo, hi);
+                        march_leaf<T, IDX>(r, dt, lo, hi, vol, v, s, acc);
+                    } else {
+                        const int c = ra.kd_first[node];
+                        const int nr = r.d[a] < 0.0f ? c + 1 : c;
+                        const int fr = r.d[a] < 0.0f ? c : c + 1;
+                        int l0[3], h0[3], l1[3], h1[3];
+                        box_of(nr, l0, h0);
+                        box_of(fr, l1, h1);
+                        const bool hn = hit_box(r, dt, l0, h0), hf = hit_box(r, dt, l1, h1);
+                        if (hn && hf && sp < ra.stack_cap) {
+                            stk[sp * 256 + threadIdx.x] = fr;
+                            ++sp;
+                            node = nr;
+                            continue;
+                        }
+                        if (hn) { node = nr; continue; }
+                        if (hf) { node = fr; continue; }
+                    }
+                    if (sp == 0) break;
+                    --sp;
+                    node = stk[sp * 256 + threadIdx.x];
+                }
+            }
+        }
+    }
+    const int64_t pix = (int64_t)py * ra.W + px;
+    reinterpret_cast<float4 *>(ra.out)[pix] = make_float4(acc.c[0], acc.c[1], acc.c[2], acc.a);
+    if (ra.count) ra.count[pix] = acc.n;
+}
+
+template <int ACCEL, typename T>
+hipError_t launch_accel(const RenderArgs &r, hipStream_t s)
+{
+    const dim3 grid((r.W + 15) / 16, (r.H + 15) / 16);
+    const size_t lds = (r.N <= 1024 ? 1024 * sizeof(float4) : 0) +
+                       (size_t)r.stack_cap * 256 * sizeof(int);
+    const int64_t nvox = (int64_t)r.vol.nx * r.vol.ny * r.vol.nz;
+    const bool narrow = nvox < (int64_t)0xffffffffLL;
+    const void *fn = narrow ? reinterpret_cast<const void *>(&k_render<ACCEL, T, uint32_t>)
+                            : reinterpret_cast<const void *>(&k_render<ACCEL, T, uint64_t>);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    if (narrow)
+        hipLaunchKernelGGL((k_render<ACCEL, T, uint32_t>), grid, dim3(256), lds, s, r);
+    else
+        hipLaunchKernelGGL((k_render<ACCEL, T, uint64_t>), grid, dim3(256), lds, s, r);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_typed(int accel, const RenderArgs &r, hipStream_t s)
+{
+    switch (accel) {
+    case ESK_ACCEL_NONE: return launch_accel<ESK_ACCEL_NONE, T>(r, s);
+    case ESK_ACCEL_GRID: return launch_accel<ESK_ACCEL_GRID, T>(r, s);
+    case ESK_ACCEL_LBVH: return launch_accel<ESK_ACCEL_LBVH, T>(r, s);
+    case ESK_ACCEL_KD: return launch_accel<ESK_ACCEL_KD, T>(r, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_render(int accel, const RenderArgs &r, hipStream_t s)
+{
+    switch (r.vol.dtype) {
+    case ESK_U8: return launch_typed<uint8_t>(accel, r, s);
+    case ESK_U16: return launch_typed<uint16_t>(accel, r, s);
+    case ESK_F16: return launch_typed<_Float16>(accel, r, s);
+    case ESK_F32: return launch_typed<float>(accel, r, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace esk

@@ -1,0 +1,126 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+symbol include/esk.h declares, sizes workspaces, and rejects bad arguments
+before touching a device (validation-only context, device = -1)."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+import paper_1912_09596_amd as esk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "esk.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(esk_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 11
+    L = esk.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_workspace_bytes_and_limits():
+    a = esk.workspace_bytes((64, 64, 64), esk.U8, 8, 256)
+    b = esk.workspace_bytes((512, 512, 512), esk.F32, 16, 256)
+    assert 0 < a < b
+    # same brick grid, wider dtype -> only the min/max arrays grow
+    c = esk.workspace_bytes((512, 512, 512), esk.U8, 16, 256)
+    assert b > c
+    out = ctypes.c_size_t()
+    L = esk.lib()
+    assert L.esk_workspace_bytes(64, 64, 64, esk.U8, 3, 256, ctypes.byref(out)) == esk.EINVAL
+    assert L.esk_workspace_bytes(64, 64, 64, 9, 8, 256, ctypes.byref(out)) == esk.EINVAL
+    assert L.esk_workspace_bytes(0, 64, 64, esk.U8, 8, 256, ctypes.byref(out)) == esk.EINVAL
+    assert L.esk_workspace_bytes(64, 64, 64, esk.U8, 8, 1, ctypes.byref(out)) == esk.ELIMIT
+    assert L.esk_workspace_bytes(64, 64, 64, esk.U8, 8, 4097, ctypes.byref(out)) == esk.ELIMIT
+    # 1024 bricks per axis is the Morton limit
+    assert L.esk_workspace_bytes(8192, 8, 8, esk.U8, 8, 256, ctypes.byref(out)) == esk.OK
+    assert L.esk_workspace_bytes(8193, 8, 8, esk.U8, 8, 256, ctypes.byref(out)) == esk.ELIMIT
+
+
+class _VCtx:
+    """validation-only context driven through the raw ABI"""
+
+    def __init__(self):
+        self.L = esk.lib()
+        self.c = ctypes.c_void_p()
+        assert self.L.esk_create(-1, None, ctypes.byref(self.c)) == esk.OK
+
+    def err(self):
+        return self.L.esk_last_error(self.c).decode()
+
+    def close(self):
+        assert self.L.esk_destroy(self.c) == esk.OK
+
+
+FAKE = ctypes.c_void_p(0x100000)   # never dereferenced: validation-only
+
+
+def test_set_volume_validation():
+    v = _VCtx()
+    L = v.L
+    need = esk.workspace_bytes((64, 64, 64), esk.F32, 8, 256)
+    sv = L.esk_set_volume
+    assert sv(v.c, None, esk.F32, 64, 64, 64, 0.0, 1.0, 8, 256, FAKE, need) == esk.EINVAL
+    assert sv(v.c, FAKE, esk.F32, 64, 64, 64, 0.0, 1.0, 8, 256, None, need) == esk.EINVAL
+    assert sv(v.c, FAKE, esk.F32, 64, 64, 64, 1.0, 1.0, 8, 256, FAKE, need) == esk.EINVAL
+    assert sv(v.c, FAKE, esk.F32, 64, 64, 64, 0.0, math.nan, 8, 256, FAKE, need) == esk.EINVAL
+    assert sv(v.c, FAKE, esk.F32, 64, 64, 64, 0.0, 1.0, 12, 256, FAKE, need) == esk.EINVAL
+    assert sv(v.c, FAKE, esk.F32, 64, 64, 64, 0.0, 1.0, 8, 256, ctypes.c_void_p(0x100010), need) == esk.EINVAL
+    assert sv(v.c, FAKE, esk.F32, 64, 64, 64, 0.0, 1.0, 8, 256, FAKE, need - 1) == esk.ENOSPC
+    assert "needs" in v.err()
+    assert sv(v.c, FAKE, esk.F32, 64, 64, 64, 0.0, 1.0, 8, 256, FAKE, need) == esk.ESTATE
+    # integer volumes ignore the value range
+    need8 = esk.workspace_bytes((64, 64, 64), esk.U8, 8, 256)
+    assert sv(v.c, FAKE, esk.U8, 64, 64, 64, 1.0, 1.0, 8, 256, FAKE, need8) == esk.ESTATE
+    v.close()
+
+
+def test_tf_and_render_validation():
+    v = _VCtx()
+    L = v.L
+    kd = esk.KdParams(1, 0, 4)
+    st = L.esk_set_transfer_function
+    assert st(v.c, None, 256, esk.LBVH, None) == esk.EINVAL
+    assert st(v.c, FAKE, 1, esk.LBVH, None) == esk.EINVAL
+    assert st(v.c, FAKE, 256, 8, None) == esk.EINVAL
+    assert st(v.c, FAKE, 256, esk.KD, None) == esk.EINVAL
+    assert st(v.c, FAKE, 256, esk.KD, ctypes.byref(esk.KdParams(2, 0, 4))) == esk.EINVAL
+    assert st(v.c, FAKE, 256, esk.KD, ctypes.byref(esk.KdParams(1, 0, 1))) == esk.EINVAL
+    assert st(v.c, FAKE, 256, esk.KD, ctypes.byref(esk.KdParams(1, 0, 17))) == esk.EINVAL
+    assert st(v.c, FAKE, 256, esk.KD | esk.LBVH, ctypes.byref(kd)) == esk.ESTATE
+    cam = esk.camera_struct(dict(ortho=0, eye=[0, 0, -10], dir00=[0, 0, 1], du=[0.01, 0, 0], dv=[0, -0.01, 0]))
+    r = L.esk_render
+    assert r(v.c, esk.LBVH, None, 64, 64, 0.5, 1.0, FAKE, None) == esk.EINVAL
+    assert r(v.c, 3, ctypes.byref(cam), 64, 64, 0.5, 1.0, FAKE, None) == esk.EINVAL
+    assert r(v.c, esk.LBVH, ctypes.byref(cam), 0, 64, 0.5, 1.0, FAKE, None) == esk.EINVAL
+    assert r(v.c, esk.LBVH, ctypes.byref(cam), 64, 64, 0.0, 1.0, FAKE, None) == esk.EINVAL
+    assert r(v.c, esk.LBVH, ctypes.byref(cam), 64, 64, 0.5, -1.0, FAKE, None) == esk.EINVAL
+    assert r(v.c, esk.LBVH, ctypes.byref(cam), 64, 64, 0.5, 1.0, None, None) == esk.EINVAL
+    assert r(v.c, esk.LBVH, ctypes.byref(cam), 64, 64, 0.5, 1.0, ctypes.c_void_p(0x100004), None) == esk.EINVAL
+    bad = esk.camera_struct(dict(ortho=0, eye=[0, math.inf, 0], dir00=[0, 0, 1], du=[1, 0, 0], dv=[0, 1, 0]))
+    assert r(v.c, esk.LBVH, ctypes.byref(bad), 64, 64, 0.5, 1.0, FAKE, None) == esk.EINVAL
+    assert r(v.c, esk.LBVH, ctypes.byref(cam), 64, 64, 0.5, 1.0, FAKE, None) == esk.ESTATE
+    assert L.esk_sync(v.c) == esk.ESTATE
+    s = esk.Stats()
+    assert L.esk_get_stats(v.c, ctypes.byref(s)) == esk.ESTATE
+    used = ctypes.c_size_t()
+    assert L.esk_export(v.c, 0, None, 0, ctypes.byref(used)) == esk.ESTATE
+    v.close()
+
+
+def test_status_strings_and_null_handles():
+    L = esk.lib()
+    for s in (esk.OK, esk.EINVAL, esk.ENOSPC, esk.ELIMIT, esk.EDEVICE, esk.ESTATE, esk.EINTERNAL):
+        assert L.esk_strerror(s)
+    assert L.esk_destroy(None) == esk.EINVAL
+    assert L.esk_sync(None) == esk.EINVAL
+    assert L.esk_create(-2, None, ctypes.byref(ctypes.c_void_p())) == esk.EINVAL

@@ -1,0 +1,289 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Integer work (min/max, flags, grid, compaction, Morton keys, sort, LBVH,
+k-d tree) must match bit for bit; images must be within 1e-3 max-abs RGBA of
+the FP64 oracle, per-pixel sample counts must match exactly, and every
+skipping mode must reproduce the GPU's own full march bit for bit."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-3
+KD_VARIANTS = [(0, 0), (1, 0), (1, 32), (1, 128)]
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(a):
+    torch = _torch()
+    if a.dtype == np.uint16:
+        return torch.from_numpy(a.view(np.int16).copy()).view(torch.uint16).cuda()
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def make_ctx():
+    import paper_1912_09596_amd as esk
+    _torch()
+    return esk, esk.Context(0)
+
+
+def check_hierarchies(ctx, vol, tf, B, lo=0.0, hi=1.0, kd=(1, 0), label=""):
+    """Compares every rebuild product with the oracle, bit for bit."""
+    nz, ny, nx = vol.shape
+    dims = (nx, ny, nz)
+    mn, mx = oracle.brick_minmax(vol, B)
+    gmn, gmx = ctx.export("minmax")
+    assert np.array_equal(gmn.astype(np.float64), mn), label
+    assert np.array_equal(gmx.astype(np.float64), mx), label
+    assert np.array_equal(ctx.export("tf_prefix"), oracle.tf_prefix(tf)), label
+    flags = oracle.classify(mn, mx, vol.dtype, tf, lo, hi)
+    assert np.array_equal(ctx.export("flags"), flags), label
+    grid = ctx.export("grid")
+    bits = np.unpackbits(grid.view(np.uint8), bitorder="little")[: flags.size]
+    assert np.array_equal(bits, flags), label
+    ids = oracle.compact(flags)
+    assert np.array_equal(ctx.export("ids"), ids), label
+    nb = oracle.brick_grid(dims, B)
+    keys = oracle.morton_keys(ids, nb[0], nb[1])
+    assert np.array_equal(ctx.export("keys"), keys), label
+    sk, si = oracle.sort_pairs(keys, ids)
+    assert np.array_equal(ctx.export("sorted_keys"), sk), label
+    assert np.array_equal(ctx.export("sorted_ids"), si), label
+    t = oracle.lbvh(sk, si, B, dims)
+    for name in ("left", "right", "axis", "lo", "hi"):
+        assert np.array_equal(ctx.export("lbvh_" + name), t[name]), (label, name)
+    st = ctx.stats()
+    assert st["n_nonempty"] == ids.size, label
+    assert st["lbvh_height"] == t["height"], label
+    assert st["lbvh_nodes"] == (2 * ids.size - 1 if ids.size else 0)
+    k = oracle.kd(flags, B, dims, kd[0], kd[1])
+    for name in ("lo", "hi", "axis", "plane"):
+        assert np.array_equal(ctx.export("kd_" + name), k[name]), (label, name)
+    assert np.array_equal(ctx.export("kd_first"), k["first_child"]), label
+    assert st["kd_nodes"] == len(k["axis"]) and st["kd_height"] == k["height"], label
+    return flags
+
+
+def run_case(vol, tf, B, lo=0.0, hi=1.0, kd=(1, 0), label=""):
+    esk, ctx = make_ctx()
+    torch = _torch()
+    dv = to_dev(vol)
+    dtf = to_dev(tf)
+    ctx.set_volume(dv, B, (lo, hi), max_tf=max(256, tf.shape[0]))
+    ctx.set_tf(dtf, build=("grid", "lbvh", "kd"), kd=esk.Kd(kd[0], kd[1], 4))
+    torch.cuda.synchronize()
+    flags = check_hierarchies(ctx, vol, tf, B, lo, hi, kd, label)
+    return esk, ctx, flags, dv, dtf
+
+
+def check_images(ctx, vol, tf, cam, W, H, flags, B, lo=0.0, hi=1.0, dt=0.5, ref=1.0, label=""):
+    torch = _torch()
+    ref_img, ref_cnt = oracle.render(vol, tf, cam, W, H, dt, ref, lo, hi, with_counts=True)
+    _, skip_cnt = oracle.render(vol, tf, cam, W, H, dt, ref, lo, hi, mode=1, flags=flags, B=B,
+                                with_counts=True)
+    imgs = {}
+    for accel in ("none", "grid", "lbvh", "kd"):
+        cnt = torch.empty((H, W), dtype=torch.int32, device="cuda")
+        img = ctx.render(cam, W, H, accel=accel, step=dt, ref=ref, counts=cnt)
+        torch.cuda.synchronize()
+        img, cnt = img.cpu().numpy(), cnt.cpu().numpy()
+        err = np.abs(img.astype(np.float64) - ref_img).max()
+        assert err <= TOL, (label, accel, err)
+        if accel == "none":
+            assert np.array_equal(cnt, ref_cnt), (label, "sample set differs from the oracle")
+        elif accel in ("grid", "lbvh"):
+            assert np.array_equal(cnt, skip_cnt), (label, accel)
+        else:
+            assert np.all(cnt >= skip_cnt) and np.all(cnt <= ref_cnt), label
+        imgs[accel] = img
+    for accel in ("grid", "lbvh", "kd"):
+        assert np.array_equal(imgs[accel], imgs["none"]), (label, accel, "skip != full march")
+    return imgs
+
+
+def test_c1_workload_full_parity():
+    w = synth.c1_workload()
+    log("case: C1 64^3 u8 blobs, B=8")
+    esk, ctx, flags, _, _ = run_case(w["vol"], w["tf"], w["brick"], label="C1")
+    assert 0 < flags.mean() < 1
+    check_images(ctx, w["vol"], w["tf"], w["cam"], w["W"], w["H"], flags, w["brick"], label="C1")
+    cam = synth.orthographic((64, 64, 64), 96, 80, synth.view_direction(5))
+    check_images(ctx, w["vol"], w["tf"], cam, 96, 80, flags, w["brick"], label="C1 ortho")
+
+
+@pytest.mark.parametrize("dims,B,dtype,seed", [
+    ((37, 50, 29), 8, np.uint8, 0),
+    ((45, 33, 52), 16, np.float32, 1),
+    ((61, 40, 47), 8, np.float16, 2),
+    ((70, 23, 38), 4, np.uint16, 3),
+    ((100, 90, 70), 32, np.uint8, 4),
+])
+def test_ragged_volumes(dims, B, dtype, seed):
+    log(f"case: ragged {dims} B={B} {np.dtype(dtype).name} seed={seed}")
+    base = synth.blobs_u8(dims, seed=50 + seed, n_blobs=7, cut=40)
+    if dtype == np.uint8:
+        vol = base
+    elif dtype == np.uint16:
+        vol = (base.astype(np.uint16) * 257).astype(np.uint16)
+    else:
+        vol = (base.astype(np.float64) / 255.0).astype(dtype)
+    tf = synth.tf_random(seed + 10, 256)
+    for kd in KD_VARIANTS:
+        esk, ctx, flags, _, _ = run_case(vol, tf, B, kd=kd, label=f"{dims} kd={kd}")
+    W, H = 72, 56
+    for i, ortho in enumerate((0, 1)):
+        d = synth.view_direction(seed * 3 + i)
+        cam = synth.orthographic(dims, W, H, d) if ortho else synth.perspective(dims, W, H, d)
+        check_images(ctx, vol, tf, cam, W, H, flags, B, label=f"{dims} ortho={ortho}")
+
+
+def test_float_value_range_and_opacity_modes():
+    log("case: f32 with value range [-2, 3], dt 0.37 / 1.0, ref 0")
+    dims = (40, 36, 44)
+    base = synth.blobs_u8(dims, seed=77, n_blobs=6, cut=30).astype(np.float64)
+    vol = (base / 255.0 * 5.0 - 2.0).astype(np.float32)
+    tf = synth.tf_random(99, 300)
+    esk, ctx, flags, _, _ = run_case(vol, tf, 8, lo=-2.0, hi=3.0, label="range")
+    cam = synth.perspective(dims, 64, 48, synth.view_direction(9))
+    for dt, ref in ((0.37, 1.0), (1.0, 0.0), (0.5, 2.0)):
+        check_images(ctx, vol, tf, cam, 64, 48, flags, 8, lo=-2.0, hi=3.0, dt=dt, ref=ref,
+                     label=f"dt={dt} ref={ref}")
+
+
+def test_degenerate_occupancies():
+    dims = (48, 40, 56)
+    vol = synth.blobs_u8(dims, seed=3, n_blobs=5, cut=50)
+    cam = synth.perspective(dims, 48, 40, synth.view_direction(2))
+    # all-zero alpha: nothing flagged, empty trees, black image
+    tf = synth.tf_ramp(256)
+    zero = tf.copy()
+    zero[:, 3] = 0
+    log("case: empty TF")
+    esk, ctx, flags, _, _ = run_case(vol, zero, 8, label="empty TF")
+    assert flags.sum() == 0
+    imgs = check_images(ctx, vol, zero, cam, 48, 40, flags, 8, label="empty TF")
+    assert np.all(imgs["lbvh"] == 0)
+    # every entry visible: every brick flagged
+    full = tf.copy()
+    full[:, 3] = 0.05
+    log("case: full TF")
+    esk, ctx, flags, _, _ = run_case(vol, full, 8, label="full TF")
+    assert flags.all()
+    check_images(ctx, vol, full, cam, 48, 40, flags, 8, label="full TF")
+    # exactly one and exactly two non-empty bricks
+    for spots in ([(20, 20, 20)], [(3, 4, 5), (44, 36, 50)]):
+        v = np.zeros(dims[::-1], np.uint8)
+        for (x, y, z) in spots:
+            v[z, y, x] = 250
+        log(f"case: spots {spots}")
+        only = np.zeros((256, 4), np.float32)
+        only[200:, :] = [1.0, 0.5, 0.25, 0.9]
+        esk, ctx, flags, _, _ = run_case(v, only, 32, label=f"spots {spots}")
+        check_images(ctx, v, only, cam, 48, 40, flags, 32, label=f"spots {spots}")
+
+
+def test_menger_sponge_kd_root_only():
+    vol = synth.menger_sponge(3, 3)
+    dims = vol.shape[::-1]
+    tf = synth.tf_ramp(256)
+    log("case: Menger sponge")
+    for kd in ((0, 0), (1, 0), (1, 32)):
+        esk, ctx, flags, _, _ = run_case(vol, tf, 4, kd=kd, label=f"menger {kd}")
+    assert ctx.stats()["kd_nodes"] > 1
+    cam = synth.perspective(dims, 64, 64, synth.view_direction(11))
+    check_images(ctx, vol, tf, cam, 64, 64, flags, 4, label="menger")
+
+
+def test_multiblock_sort_path():
+    # more than 32768 bricks -> the multi-block radix sort
+    dims = (300, 260, 200)
+    log(f"case: multi-block sort {dims} B=4")
+    vol = synth.blobs_u8(dims, seed=8, n_blobs=40, sigma=(6.0, 14.0), cut=20, centre_range=(0.05, 0.95))
+    tf = synth.tf_ramp(256, start=0.05)
+    esk, ctx, flags, _, _ = run_case(vol, tf, 4, label="multiblock")
+    assert ctx.stats()["n_bricks"] > 32768 and flags.sum() > 32768
+
+
+def test_rebuild_is_deterministic():
+    w = synth.c1_workload()
+    esk, ctx = make_ctx()
+    torch = _torch()
+    ctx.set_volume(to_dev(w["vol"]), 8, max_tf=256)
+    tf = to_dev(synth.tf_random(5, 256))
+    outs = []
+    for _ in range(3):
+        ctx.set_tf(tf, build=("grid", "lbvh", "kd"), kd=esk.Kd(1, 32, 4))
+        outs.append({k: ctx.export(k) for k in ("lbvh_left", "lbvh_right", "lbvh_lo", "lbvh_hi",
+                                                "kd_lo", "kd_axis", "kd_first")})
+        img = ctx.render(w["cam"], 128, 128, accel="lbvh")
+        torch.cuda.synchronize()
+        outs[-1]["img"] = img.cpu().numpy()
+    for o in outs[1:]:
+        for k in o:
+            assert np.array_equal(o[k], outs[0][k]), k
+
+
+def test_context_reuse_across_volumes_and_sizes():
+    esk, ctx = make_ctx()
+    torch = _torch()
+    for dims, B in (((64, 64, 64), 8), ((33, 70, 21), 16), ((64, 64, 64), 4)):
+        log(f"case: reuse {dims} B={B}")
+        vol = synth.blobs_u8(dims, seed=sum(dims), n_blobs=4)
+        tf = synth.tf_random(sum(dims), 256)
+        ctx.set_volume(to_dev(vol), B, max_tf=256)
+        ctx.set_tf(to_dev(tf), build=("grid", "lbvh", "kd"), kd=esk.Kd(1, 0, 4))
+        torch.cuda.synchronize()
+        check_hierarchies(ctx, vol, tf, B, label=f"reuse {dims}")
+
+
+@pytest.mark.slow
+def test_c2_full_size_sampled():
+    """512^3 f32 noise, 16^3 bricks, 1920x1080: hierarchies exact for several
+    TFs of the sequence; images on sampled pixels the oracle renders one by one."""
+    torch = _torch()
+    log("case: C2 512^3 f32 (generating volume)")
+    vol = synth.fractal_noise((512, 512, 512), seed=2)
+    tfs = synth.c2_tfs(100)
+    esk, ctx = make_ctx()
+    dv = to_dev(vol)
+    ctx.set_volume(dv, 16, (0.0, 1.0), max_tf=256)
+    rng = np.random.default_rng(0)
+    W, H = 1920, 1080
+    for i in (0, 1, 49, 99):
+        log(f"case: C2 TF {i}")
+        tf = tfs[i]
+        for kd in ((0, 0), (1, 32)):
+            ctx.set_tf(to_dev(tf), build=("grid", "lbvh", "kd"), kd=esk.Kd(kd[0], kd[1], 4))
+            torch.cuda.synchronize()
+            flags = check_hierarchies(ctx, vol, tf, 16, kd=kd, label=f"C2 tf{i} kd{kd}")
+        cam = synth.c2_camera(i)
+        pix = np.stack([rng.integers(0, W, 400), rng.integers(0, H, 400)], 1).astype(np.int32)
+        ref_img, ref_cnt = oracle.render(vol, tf, cam, W, H, pixels=pix, with_counts=True)
+        full = None
+        for accel in ("none", "grid", "lbvh", "kd"):
+            cnt = torch.empty((H, W), dtype=torch.int32, device="cuda")
+            img = ctx.render(cam, W, H, accel=accel, counts=cnt).cpu().numpy()
+            cnt = cnt.cpu().numpy()
+            got = img[pix[:, 1], pix[:, 0]].astype(np.float64)
+            assert np.abs(got - ref_img).max() <= TOL, (i, accel)
+            if accel == "none":
+                assert np.array_equal(cnt[pix[:, 1], pix[:, 0]], ref_cnt)
+                full = img
+            else:
+                assert np.array_equal(img, full), (i, accel)

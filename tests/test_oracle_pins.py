@@ -105,9 +105,10 @@ def test_classify_tf_extremes():
     assert np.all(oracle.classify(mn, mx, vol.dtype, full) == 1)
 
 
-@pytest.mark.parametrize("entry,flagged", [(98, 0), (99, 1), (100, 1), (101, 1), (102, 0)])
+@pytest.mark.parametrize("entry,flagged", [(98, 0), (99, 1), (100, 1), (101, 1), (102, 1), (103, 0)])
 def test_classify_u8_index_window(entry, flagged):
-    # u8, N = 256: x(v) = v exactly, so a constant-100 brick reads entries [99, 101]
+    # u8, N = 256: x(v) = v exactly, so a constant-100 brick's window is
+    # [floor(x) - 1, floor(x) + 2] = [99, 102]
     vol = np.full((16, 16, 16), 100, np.uint8)
     mn, mx = oracle.brick_minmax(vol, 8)
     tf = np.zeros((256, 4), np.float32)
