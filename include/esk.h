@@ -175,6 +175,21 @@ esk_status esk_set_transfer_function(esk_ctx *ctx, const float *d_rgba, int n_en
 esk_status esk_render(esk_ctx *ctx, int accel, const esk_camera *cam, int width, int height,
                       float step, float opacity_ref_step, float *d_rgba_out, int32_t *d_count_out);
 
+/* Batched rendering: n requests (each a context with its own volume, TF and
+ * hierarchy, all of the same volume dtype and on one device) rendered by one
+ * kernel launch on ctxs[0]'s stream, request i into d_outs[i] (heights[i] x
+ * widths[i] x RGBA float32), with accel, step and opacity_ref_step shared.
+ * Per-request semantics are exactly those of esk_render, so each image is
+ * bit-identical to rendering it alone.  Every context's earlier work must be
+ * ordered before this call (same stream, or synchronised by the caller).
+ * d_args: caller-owned device buffer of esk_render_batch_bytes(n) bytes,
+ * 16-byte aligned, that receives the per-request arguments; it may be reused
+ * once the stream has passed this call.  n in [1, 65535]. */
+esk_status esk_render_batch_bytes(int n, size_t *out);
+esk_status esk_render_batch(esk_ctx *const *ctxs, int n, int accel, const esk_camera *cams, const int *widths,
+                            const int *heights, float step, float opacity_ref_step, float *const *d_outs,
+                            void *d_args, size_t args_bytes);
+
 /* Waits for the context's stream; reports device faults. */
 esk_status esk_sync(esk_ctx *ctx);
 

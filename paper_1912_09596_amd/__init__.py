@@ -98,8 +98,12 @@ def lib() -> ctypes.CDLL:
     L.esk_strerror.restype = ctypes.c_char_p
     L.esk_last_error.argtypes = [P]
     L.esk_last_error.restype = ctypes.c_char_p
+    L.esk_render_batch_bytes.argtypes = [i32, ctypes.POINTER(sz)]
+    L.esk_render_batch.argtypes = [ctypes.POINTER(P), i32, i32, ctypes.POINTER(Camera), ctypes.POINTER(i32),
+                                   ctypes.POINTER(i32), f32, f32, ctypes.POINTER(P), P, sz]
     for name in ("esk_create", "esk_destroy", "esk_workspace_bytes", "esk_set_volume",
-                 "esk_set_transfer_function", "esk_render", "esk_sync", "esk_get_stats", "esk_export"):
+                 "esk_set_transfer_function", "esk_render", "esk_sync", "esk_get_stats", "esk_export",
+                 "esk_render_batch_bytes", "esk_render_batch"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -251,3 +255,33 @@ class Context:
         if what in ("lbvh_lo", "lbvh_hi", "kd_lo", "kd_hi"):
             return buf.reshape(-1, 3)
         return buf
+
+
+def render_batch(contexts, cams, sizes, accel="lbvh", step=0.5, ref=1.0, outs=None, args_buffer=None):
+    """Renders request i = (contexts[i], cams[i], sizes[i] = (W, H)) for all i
+    in one kernel launch on contexts[0]'s stream; returns the list of [H, W, 4]
+    images.  All contexts must hold volumes of one dtype on one device."""
+    import torch
+    n = len(contexts)
+    L = lib()
+    need = ctypes.c_size_t()
+    st = L.esk_render_batch_bytes(n, ctypes.byref(need))
+    if st != OK:
+        raise EskError(st, "bad batch size")
+    dev = contexts[0]._keep["vol"].device
+    if args_buffer is None or args_buffer.numel() < need.value:
+        args_buffer = torch.empty(need.value, dtype=torch.uint8, device=dev)
+    if outs is None:
+        outs = [torch.empty((h, w, 4), dtype=torch.float32, device=dev) for (w, h) in sizes]
+    ctx_arr = (ctypes.c_void_p * n)(*[c._ctx.value for c in contexts])
+    cam_arr = (Camera * n)(*[camera_struct(c) for c in cams])
+    w_arr = (ctypes.c_int * n)(*[int(w) for (w, h) in sizes])
+    h_arr = (ctypes.c_int * n)(*[int(h) for (w, h) in sizes])
+    out_arr = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+    code = ACCEL[accel] if isinstance(accel, str) else int(accel)
+    st = L.esk_render_batch(ctx_arr, n, code, cam_arr, w_arr, h_arr, float(step), float(ref), out_arr,
+                            ctypes.c_void_p(args_buffer.data_ptr()), args_buffer.numel())
+    if st != OK:
+        raise EskError(st, L.esk_last_error(contexts[0]._ctx).decode())
+    contexts[0]._keep["batch_args"] = args_buffer
+    return outs

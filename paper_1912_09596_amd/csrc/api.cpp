@@ -63,8 +63,9 @@ Layout make_layout(int nbx, int nby, int nbz, int elem_bytes, int max_tf)
     L.lb_parent = take(2 * n4);
     L.lb_lo = take(2 * n4 * 3);
     L.lb_hi = take(2 * n4 * 3);
-    L.lb_height = take(2 * n4);
-    L.lb_flag = take(n4);
+    L.lb_range = take(2 * n4);
+    L.lb_rnode = take((size_t)nb * sizeof(RNode));
+    L.lb_leafbox = take((size_t)nb * 16);
     L.kd_S = take(n4);
     L.kd_lo = take(2 * n4 * 3);
     L.kd_hi = take(2 * n4 * 3);
@@ -73,6 +74,8 @@ Layout make_layout(int nbx, int nby, int nbz, int elem_bytes, int max_tf)
     L.kd_first = take(2 * n4);
     L.kd_split = take(2 * n4);
     L.kd_clo = take(2 * n4 * 12);
+    L.kd_rnode = take(2 * (size_t)nb * sizeof(RNode));
+    L.kd_box = take(2 * (size_t)nb * 16);
     L.total = off;
     return L;
 }
@@ -100,6 +103,15 @@ struct esk_ctx {
     int built = 0;
     uint32_t kd_height = 0;
     uint32_t kd_count = 0;
+    bool kd_on_device = false;  // k-d build enqueued; completion and height not yet read back
+    esk_kd_params kd_params{1, 0, 4};
+    // host staging of batched render arguments (pinned; reused once the
+    // previous upload has completed)
+    RenderArgs *staging = nullptr;
+    int staging_cap = 0;
+    hipEvent_t staging_done = nullptr;
+    int kd_level_hint = 24;     // levels enqueued per rebuild (adapts to the last height)
+    int kd_levels_enqueued = 0;
 };
 
 namespace {
@@ -149,6 +161,8 @@ esk_status check_shape(esk_ctx *c, int nx, int ny, int nz, int dtype, int brick,
     const int nbx = (nx + brick - 1) / brick, nby = (ny + brick - 1) / brick, nbz = (nz + brick - 1) / brick;
     if (nbx > kMaxBricksPerAxis || nby > kMaxBricksPerAxis || nbz > kMaxBricksPerAxis)
         return fail(c, ESK_ELIMIT, "more than %d bricks on an axis (%d %d %d)", kMaxBricksPerAxis, nbx, nby, nbz);
+    if ((int64_t)nbx * nby * nbz > kMaxBricks)
+        return fail(c, ESK_ELIMIT, "more than %lld bricks", (long long)kMaxBricks);
     return ESK_OK;
 }
 
@@ -165,6 +179,35 @@ esk_status read_header(esk_ctx *c)
 }
 
 }  // namespace
+
+static KdArgs kd_args(esk_ctx *c, const esk_kd_params *p);
+
+// Makes sure the enqueued k-d build has reached its last level (enqueuing
+// more levels if the speculative batch was short), then reads the node count
+// and height back.  Synchronises.
+static esk_status kd_finish(esk_ctx *c)
+{
+    if (!c->kd_on_device) return ESK_OK;
+    esk_status st = read_header(c);
+    if (st != ESK_OK) return st;
+    KdArgs k = kd_args(c, &c->kd_params);
+    while (c->pinned->kd_end > c->pinned->kd_begin) {
+        if (c->kd_levels_enqueued > 4 * (c->vol.nb[0] + c->vol.nb[1] + c->vol.nb[2]) + 64)
+            return fail(c, ESK_EINTERNAL, "k-d build did not terminate");
+        hipError_t e = launch_kd_levels(k, 8, c->stream);
+        if (e == hipSuccess) e = launch_kd_pack(k, 2 * c->L.nb, c->stream);
+        if (e != hipSuccess) return hip_check(c, e, "k-d level launch");
+        c->kd_levels_enqueued += 8;
+        st = read_header(c);
+        if (st != ESK_OK) return st;
+    }
+    if (c->pinned->pad[0] != 0) return fail(c, ESK_EINTERNAL, "k-d node capacity exceeded");
+    c->kd_count = c->pinned->kd_count;
+    c->kd_height = c->pinned->kd_height;
+    c->kd_level_hint = std::max(16, (int)c->kd_height + 3);
+    c->kd_on_device = false;
+    return ESK_OK;
+}
 
 extern "C" {
 
@@ -219,6 +262,9 @@ esk_status esk_destroy(esk_ctx *c)
         (void)hipSetDevice(c->device);
         (void)hipStreamSynchronize(c->stream);
         if (c->pinned) (void)hipHostFree(c->pinned);
+        if (c->staging_done) (void)hipEventSynchronize(c->staging_done);
+        if (c->staging) (void)hipHostFree(c->staging);
+        if (c->staging_done) (void)hipEventDestroy(c->staging_done);
     }
     delete c;
     return ESK_OK;
@@ -306,11 +352,12 @@ static RebuildArgs rebuild_args(esk_ctx *c)
     a.lb_left = at<uint32_t>(c, L.lb_left);
     a.lb_right = at<uint32_t>(c, L.lb_right);
     a.lb_parent = at<uint32_t>(c, L.lb_parent);
-    a.lb_flag = at<uint32_t>(c, L.lb_flag);
-    a.lb_height = at<uint32_t>(c, L.lb_height);
+    a.lb_range = at<int2>(c, L.lb_range);
     a.lb_axis = at<int32_t>(c, L.lb_axis);
     a.lb_lo = at<int32_t>(c, L.lb_lo);
     a.lb_hi = at<int32_t>(c, L.lb_hi);
+    a.lb_rnode = at<RNode>(c, L.lb_rnode);
+    a.lb_leafbox = at<uint4>(c, L.lb_leafbox);
     a.hdr = at<DevHeader>(c, L.header);
     a.nb = L.nb;
     a.nblk = L.nblk;
@@ -338,7 +385,10 @@ static KdArgs kd_args(esk_ctx *c, const esk_kd_params *p)
     k.first = at<int32_t>(c, L.kd_first);
     k.split = at<int32_t>(c, L.kd_split);
     k.clo = at<int32_t>(c, L.kd_clo);
+    k.rnode = at<RNode>(c, L.kd_rnode);
+    k.box = at<uint4>(c, L.kd_box);
     k.hdr = at<DevHeader>(c, L.header);
+    k.cap = 2 * L.nb;
     if (p) {
         k.halting = p->halting;
         k.max_leaf = p->max_leaf;
@@ -370,6 +420,7 @@ esk_status esk_set_transfer_function(esk_ctx *c, const float *d_rgba, int n_entr
     if (e != hipSuccess) return hip_check(c, e, "hipSetDevice");
     c->has_tf = false;
     c->built = 0;
+    c->kd_on_device = false;
     c->N = n_entries;
     const Layout &L = c->L;
     e = hipMemcpyAsync(c->ws + L.tf, d_rgba, (size_t)n_entries * 16, hipMemcpyDeviceToDevice, c->stream);
@@ -384,31 +435,32 @@ esk_status esk_set_transfer_function(esk_ctx *c, const float *d_rgba, int n_entr
     }
     if (build_mask & ESK_ACCEL_KD) {
         KdArgs k = kd_args(c, kd);
-        e = launch_kd_prefix(k, c->stream);
-        if (e == hipSuccess) e = launch_kd_root(k, c->stream);
-        if (e != hipSuccess) return hip_check(c, e, "k-d launch");
-        esk_status st = read_header(c);
-        if (st != ESK_OK) return st;
-        const int64_t cap = 2 * L.nb;
-        while (c->pinned->kd_end > c->pinned->kd_begin) {
-            const uint32_t begin = c->pinned->kd_begin, end = c->pinned->kd_end;
-            if ((int64_t)end + 2 * ((int64_t)end - begin) > cap)
-                return fail(c, ESK_EINTERNAL, "k-d node capacity exceeded");
-            e = launch_kd_level(k, begin, end, c->stream);
-            if (e != hipSuccess) return hip_check(c, e, "k-d level launch");
-            st = read_header(c);
-            if (st != ESK_OK) return st;
+        c->kd_params = *kd;
+        if (kd_small(k)) {
+            e = launch_kd_prefix_root_small(k, c->stream);
+        } else {
+            e = launch_kd_prefix(k, c->stream);
+            if (e == hipSuccess) e = launch_kd_root(k, c->stream);
         }
-        c->kd_count = c->pinned->kd_count;
-        c->kd_height = c->pinned->kd_height;
+        // levels are enqueued speculatively (a launch past the last level
+        // exits at once); completion is checked when the tree is first used
+        if (e == hipSuccess) e = launch_kd_levels(k, c->kd_level_hint, c->stream);
+        if (e == hipSuccess) e = launch_kd_pack(k, 2 * L.nb, c->stream);
+        if (e != hipSuccess) return hip_check(c, e, "k-d launch");
+        c->kd_levels_enqueued = c->kd_level_hint;
+        c->kd_on_device = true;
     }
     c->built = build_mask;
     c->has_tf = true;
     return ESK_OK;
 }
 
-esk_status esk_render(esk_ctx *c, int accel, const esk_camera *cam, int width, int height, float step,
-                      float opacity_ref_step, float *d_rgba_out, int32_t *d_count_out)
+}  // extern "C"
+
+// validates one render request and fills its kernel arguments (may
+// synchronise once to finish a pending k-d build)
+static esk_status prepare_render(esk_ctx *c, int accel, const esk_camera *cam, int width, int height, float step,
+                                 float opacity_ref_step, float *d_rgba_out, int32_t *d_count_out, RenderArgs &r)
 {
     if (!c) return ESK_EINVAL;
     if (!cam) return fail(c, ESK_EINVAL, "camera is null");
@@ -432,7 +484,6 @@ esk_status esk_render(esk_ctx *c, int accel, const esk_camera *cam, int width, i
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_check(c, e, "hipSetDevice");
     const Layout &L = c->L;
-    RenderArgs r;
     std::memset(&r, 0, sizeof(r));
     r.vol = c->vol;
     if (c->vol.dtype == ESK_U8) { r.vlo = 0.0f; r.vscale = 1.0f / 255.0f; }
@@ -449,26 +500,111 @@ esk_status esk_render(esk_ctx *c, int accel, const esk_camera *cam, int width, i
     r.out = d_rgba_out;
     r.count = d_count_out;
     r.grid = at<uint32_t>(c, L.grid);
-    r.lb_left = at<uint32_t>(c, L.lb_left);
-    r.lb_right = at<uint32_t>(c, L.lb_right);
-    r.lb_axis = at<int32_t>(c, L.lb_axis);
     r.lb_lo = at<int32_t>(c, L.lb_lo);
     r.lb_hi = at<int32_t>(c, L.lb_hi);
-    r.kd_lo = at<int32_t>(c, L.kd_lo);
-    r.kd_hi = at<int32_t>(c, L.kd_hi);
-    r.kd_axis = at<int32_t>(c, L.kd_axis);
-    r.kd_plane = at<int32_t>(c, L.kd_plane);
-    r.kd_first = at<int32_t>(c, L.kd_first);
+    r.lb_rnode = at<RNode>(c, L.lb_rnode);
+    r.lb_leafbox = at<uint4>(c, L.lb_leafbox);
+    r.kd_rnode = at<RNode>(c, L.kd_rnode);
+    r.kd_box = at<uint4>(c, L.kd_box);
     r.hdr = at<DevHeader>(c, L.header);
     r.stack_cap = 0;
-    if (accel == ESK_ACCEL_LBVH) r.stack_cap = 32;
+    // a Karras tree splits on a strictly lower key bit at every level, so a
+    // root-to-leaf path holds at most key_bits internal nodes
+    if (accel == ESK_ACCEL_LBVH)
+        r.stack_cap = std::max(1, 3 * std::max({bits_for(c->vol.nb[0]), bits_for(c->vol.nb[1]),
+                                                bits_for(c->vol.nb[2])}));
     if (accel == ESK_ACCEL_KD) {
+        esk_status st = kd_finish(c);
+        if (st != ESK_OK) return st;
         if ((int)c->kd_height > kMaxKdStack)
-            return fail(c, ESK_ELIMIT, "k-d tree height %u exceeds the traversal stack (%d)", c->kd_height, kMaxKdStack);
+            return fail(c, ESK_ELIMIT, "k-d tree height %u exceeds the traversal stack (%d)", c->kd_height,
+                        kMaxKdStack);
         r.stack_cap = std::max(1, (int)c->kd_height);
     }
-    e = launch_render(accel, r, c->stream);
-    return hip_check(c, e, "render launch");
+    return ESK_OK;
+}
+
+extern "C" {
+
+esk_status esk_render(esk_ctx *c, int accel, const esk_camera *cam, int width, int height, float step,
+                      float opacity_ref_step, float *d_rgba_out, int32_t *d_count_out)
+{
+    RenderArgs r;
+    esk_status st = prepare_render(c, accel, cam, width, height, step, opacity_ref_step, d_rgba_out, d_count_out, r);
+    if (st != ESK_OK) return st;
+    return hip_check(c, launch_render(accel, r, c->stream), "render launch");
+}
+
+esk_status esk_render_batch_bytes(int n, size_t *out)
+{
+    if (!out || n < 1 || n > 65535) return ESK_EINVAL;
+    *out = (size_t)n * sizeof(RenderArgs);
+    return ESK_OK;
+}
+
+esk_status esk_render_batch(esk_ctx *const *ctxs, int n, int accel, const esk_camera *cams, const int *widths,
+                            const int *heights, float step, float opacity_ref_step, float *const *d_outs,
+                            void *d_args, size_t args_bytes)
+{
+    if (!ctxs || n < 1 || n > 65535 || !ctxs[0]) return ESK_EINVAL;
+    esk_ctx *c0 = ctxs[0];
+    if (!cams || !widths || !heights || !d_outs) return fail(c0, ESK_EINVAL, "null request array");
+    if (!d_args || (reinterpret_cast<uintptr_t>(d_args) & 15) != 0)
+        return fail(c0, ESK_EINVAL, "argument buffer must be non-null and 16-byte aligned");
+    if (args_bytes < (size_t)n * sizeof(RenderArgs))
+        return fail(c0, ESK_ENOSPC, "argument buffer has %zu bytes, needs %zu", args_bytes,
+                    (size_t)n * sizeof(RenderArgs));
+    for (int i = 0; i < n; ++i) {
+        if (!ctxs[i]) return fail(c0, ESK_EINVAL, "request %d has no context", i);
+        if (ctxs[i]->device != c0->device) return fail(c0, ESK_EINVAL, "request %d is on another device", i);
+        if (ctxs[i]->has_volume && c0->has_volume && ctxs[i]->vol.dtype != c0->vol.dtype)
+            return fail(c0, ESK_EINVAL, "request %d has another volume dtype", i);
+    }
+    if (c0->device < 0) return fail(c0, ESK_ESTATE, "validation-only context");
+    if (c0->staging_cap < n) {
+        if (c0->staging_done) (void)hipEventSynchronize(c0->staging_done);
+        if (c0->staging) (void)hipHostFree(c0->staging);
+        c0->staging = nullptr;
+        c0->staging_cap = 0;
+        hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&c0->staging), (size_t)n * sizeof(RenderArgs));
+        if (e != hipSuccess) return hip_check(c0, e, "staging allocation");
+        c0->staging_cap = n;
+    }
+    if (!c0->staging_done) {
+        hipError_t e = hipEventCreateWithFlags(&c0->staging_done, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_check(c0, e, "event creation");
+    }
+    hipError_t e = hipEventSynchronize(c0->staging_done);  // previous upload finished with the buffer
+    if (e != hipSuccess) return hip_check(c0, e, "staging wait");
+    size_t lds = 0;
+    bool narrow = true, tfl = true;
+    int tx = 1, ty = 1;
+    for (int i = 0; i < n; ++i) {
+        RenderArgs &r = c0->staging[i];
+        esk_status st = prepare_render(ctxs[i], accel, &cams[i], widths[i], heights[i], step, opacity_ref_step,
+                                       d_outs[i], nullptr, r);
+        if (st != ESK_OK) {
+            if (ctxs[i] != c0) fail(c0, st, "request %d: %s", i, ctxs[i]->err.c_str());
+            return st;
+        }
+        const int64_t nvox = (int64_t)r.vol.nx * r.vol.ny * r.vol.nz;
+        narrow = narrow && nvox < (int64_t)0xffffffffLL;
+        tfl = tfl && r.N <= 1024;
+        tx = std::max(tx, (r.W + 15) / 16);
+        ty = std::max(ty, (r.H + 15) / 16);
+    }
+    for (int i = 0; i < n; ++i) {
+        const RenderArgs &r = c0->staging[i];
+        lds = std::max(lds, (tfl ? (size_t)r.N * 16 : 0) + (size_t)r.stack_cap * 256 * sizeof(int));
+    }
+    e = hipSetDevice(c0->device);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_args, c0->staging, (size_t)n * sizeof(RenderArgs), hipMemcpyHostToDevice, c0->stream);
+    if (e == hipSuccess) e = hipEventRecord(c0->staging_done, c0->stream);
+    if (e == hipSuccess)
+        e = launch_render_batch(accel, c0->vol.dtype, static_cast<const RenderArgs *>(d_args), n, tx, ty, lds,
+                                narrow, tfl, c0->stream);
+    return hip_check(c0, e, "batched render launch");
 }
 
 esk_status esk_sync(esk_ctx *c)
@@ -487,7 +623,8 @@ esk_status esk_get_stats(esk_ctx *c, esk_stats *out)
     if (!c->has_volume) return fail(c, ESK_ESTATE, "no volume");
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_check(c, e, "hipSetDevice");
-    esk_status s = read_header(c);
+    esk_status s = (c->has_tf && (c->built & ESK_ACCEL_KD)) ? kd_finish(c) : ESK_OK;
+    if (s == ESK_OK) s = read_header(c);
     if (s != ESK_OK) return s;
     std::memset(out, 0, sizeof(*out));
     out->n_bricks = c->L.nb;
@@ -515,7 +652,8 @@ esk_status esk_export(esk_ctx *c, int what, void *host, size_t cap, size_t *used
     if (!c->has_volume) return fail(c, ESK_ESTATE, "no volume");
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_check(c, e, "hipSetDevice");
-    esk_status s = read_header(c);
+    esk_status s = (c->has_tf && (c->built & ESK_ACCEL_KD)) ? kd_finish(c) : ESK_OK;
+    if (s == ESK_OK) s = read_header(c);
     if (s != ESK_OK) return s;
     const Layout &L = c->L;
     const int64_t nb = L.nb;

@@ -46,4 +46,12 @@ __device__ inline void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// box [lo, hi) in voxels (each < 65536) as three words of two uint16
+__device__ inline void pack_box(const int lo[3], const int hi[3], uint32_t w[3])
+{
+    w[0] = (uint32_t)lo[0] | ((uint32_t)lo[1] << 16);
+    w[1] = (uint32_t)lo[2] | ((uint32_t)hi[0] << 16);
+    w[2] = (uint32_t)hi[1] | ((uint32_t)hi[2] << 16);
+}
+
 }  // namespace esk

@@ -17,6 +17,15 @@ constexpr int kClassifyBlock = 1024;  // bricks per classification / compaction 
 constexpr int kSortSingleMax = 32768; // keys one workgroup sorts in LDS
 constexpr int kSortBlockKeys = 4096;  // keys per block of the multi-block sort
 constexpr int kMaxKdStack = 128;      // deepest k-d tree the renderer traverses
+constexpr int64_t kMaxBricks = (int64_t)1 << 28;  // node indices fit the 29-bit fields of RNode
+constexpr uint32_t kIndexMask = 0x1fffffffu;
+
+// Traversal record of one internal node (32 bytes, two 16-byte loads): the
+// boxes of both children in voxels (uint16, half-open) and the children,
+// each with bit 31 = leaf; bits 29..30 of c0 hold this node's split axis.
+struct RNode {
+    uint32_t w[8];  // lo0.x|lo0.y, lo0.z|hi0.x, hi0.y|hi0.z, lo1.x|lo1.y, lo1.z|hi1.x, hi1.y|hi1.z, c0, c1
+};
 
 // Small device-resident state written by the rebuild kernels.
 struct DevHeader {
@@ -26,7 +35,8 @@ struct DevHeader {
     uint32_t kd_height;    // levels emitted so far
     uint32_t kd_begin;     // current level [begin, end)
     uint32_t kd_end;
-    uint32_t pad[58];
+    uint32_t kd_ticket;    // blocks of the current k-d level launch that finished
+    uint32_t pad[57];
 };
 static_assert(sizeof(DevHeader) == 256, "header is one 256-byte slot");
 
@@ -37,8 +47,8 @@ struct Layout {
     int64_t nsortblk;      // multi-block sort blocks
     size_t header, minv, maxv, tf, tfP, flags, grid, blkcnt;
     size_t ids, keys, skeys, tmpkeys, sids, hist;
-    size_t lb_left, lb_right, lb_axis, lb_parent, lb_lo, lb_hi, lb_height, lb_flag;
-    size_t kd_S, kd_lo, kd_hi, kd_axis, kd_plane, kd_first, kd_split, kd_clo, kd_chi;
+    size_t lb_left, lb_right, lb_axis, lb_parent, lb_lo, lb_hi, lb_range, lb_rnode, lb_leafbox;
+    size_t kd_S, kd_lo, kd_hi, kd_axis, kd_plane, kd_first, kd_split, kd_clo, kd_rnode, kd_box;
     size_t total;
 };
 
@@ -65,8 +75,11 @@ struct RebuildArgs {
     uint32_t *grid;
     uint32_t *blkcnt;
     uint32_t *ids, *keys, *skeys, *tmpkeys, *sids, *hist;
-    uint32_t *lb_left, *lb_right, *lb_parent, *lb_flag, *lb_height;
+    uint32_t *lb_left, *lb_right, *lb_parent;
     int32_t *lb_axis, *lb_lo, *lb_hi;
+    int2 *lb_range;        // [first, last] sorted-key range of each internal node
+    RNode *lb_rnode;
+    uint4 *lb_leafbox;
     DevHeader *hdr;
     int64_t nb, nblk, nsortblk;
     int key_bits;          // Morton bits that can be non-zero
@@ -81,13 +94,19 @@ struct KdArgs {
     const uint8_t *flags;
     int32_t *S;
     int32_t *lo, *hi, *axis, *plane, *first, *split, *clo;  // clo: [node][side][6 faces]
+    RNode *rnode;
+    uint4 *box;
     DevHeader *hdr;
     int halting, max_leaf, bins;
+    int64_t cap;           // node capacity of the k-d arrays (2 nb)
 };
 
+bool kd_small(const KdArgs &k);
+hipError_t launch_kd_prefix_root_small(const KdArgs &k, hipStream_t s);
 hipError_t launch_kd_prefix(const KdArgs &k, hipStream_t s);
 hipError_t launch_kd_root(const KdArgs &k, hipStream_t s);
-hipError_t launch_kd_level(const KdArgs &k, uint32_t begin, uint32_t end, hipStream_t s);
+hipError_t launch_kd_levels(const KdArgs &k, int count, hipStream_t s);
+hipError_t launch_kd_pack(const KdArgs &k, int64_t max_nodes, hipStream_t s);
 
 struct RenderArgs {
     VolumeDesc vol;
@@ -101,13 +120,18 @@ struct RenderArgs {
     float *out;
     int32_t *count;
     const uint32_t *grid;
-    const uint32_t *lb_left, *lb_right;
-    const int32_t *lb_axis, *lb_lo, *lb_hi;
-    const int32_t *kd_lo, *kd_hi, *kd_axis, *kd_plane, *kd_first;
+    const int32_t *lb_lo, *lb_hi;
+    const RNode *lb_rnode;
+    const uint4 *lb_leafbox;
+    const RNode *kd_rnode;
+    const uint4 *kd_box;
     const DevHeader *hdr;
     int stack_cap;
 };
 
 hipError_t launch_render(int accel, const RenderArgs &r, hipStream_t s);
+// n requests of one accel and volume dtype; d_args: n RenderArgs in device memory
+hipError_t launch_render_batch(int accel, int dtype, const RenderArgs *d_args, int n, int tiles_x, int tiles_y,
+                               size_t lds, bool narrow, bool tfl, hipStream_t s);
 
 }  // namespace esk

@@ -47,25 +47,30 @@ struct Box {
     int lo[3], hi[3];
 };
 
-__device__ inline int32_t S_at(const KdArgs &k, int x, int y, int z)
+// S: inclusive prefix count (global memory or an LDS copy), nbx x nby x nbz
+template <typename SP>
+__device__ inline int32_t S_at(const KdArgs &k, SP S, int x, int y, int z)
 {
     if (x < 0 || y < 0 || z < 0) return 0;
-    return k.S[(int64_t)x + (int64_t)k.nb[0] * ((int64_t)y + (int64_t)k.nb[1] * z)];
+    return S[x + k.nb[0] * (y + k.nb[1] * z)];
 }
 
 // number of flagged bricks in [lo, hi)
-__device__ inline int32_t box_count(const KdArgs &k, const int lo[3], const int hi[3])
+template <typename SP>
+__device__ inline int32_t box_count(const KdArgs &k, SP S, const int lo[3], const int hi[3])
 {
     if (hi[0] <= lo[0] || hi[1] <= lo[1] || hi[2] <= lo[2]) return 0;
     const int x0 = lo[0] - 1, y0 = lo[1] - 1, z0 = lo[2] - 1;
     const int x1 = hi[0] - 1, y1 = hi[1] - 1, z1 = hi[2] - 1;
-    return S_at(k, x1, y1, z1) - S_at(k, x0, y1, z1) - S_at(k, x1, y0, z1) - S_at(k, x1, y1, z0)
-         + S_at(k, x0, y0, z1) + S_at(k, x0, y1, z0) + S_at(k, x1, y0, z0) - S_at(k, x0, y0, z0);
+    return S_at(k, S, x1, y1, z1) - S_at(k, S, x0, y1, z1) - S_at(k, S, x1, y0, z1) -
+           S_at(k, S, x1, y1, z0) + S_at(k, S, x0, y0, z1) + S_at(k, S, x0, y1, z0) +
+           S_at(k, S, x1, y0, z0) - S_at(k, S, x0, y0, z0);
 }
 
 // one face of the tight box of region [lo, hi) (which must hold a flagged
 // brick): face q in 0..2 = lower bound on axis q, 3..5 = upper bound (exclusive)
-__device__ inline int tight_face(const KdArgs &k, const int lo[3], const int hi[3], int face)
+template <typename SP>
+__device__ inline int tight_face(const KdArgs &k, SP S, const int lo[3], const int hi[3], int face)
 {
     const int q = face % 3;
     int a = lo[q], b = hi[q] - 1;
@@ -74,14 +79,14 @@ __device__ inline int tight_face(const KdArgs &k, const int lo[3], const int hi[
         while (a < b) {
             const int m = (a + b) >> 1;
             h[q] = m + 1;
-            if (box_count(k, l, h) > 0) b = m; else a = m + 1;
+            if (box_count(k, S, l, h) > 0) b = m; else a = m + 1;
         }
         return a;
     }
     while (a < b) {            // largest c with a flagged brick in [c, hi_q)
         const int m = (a + b + 1) >> 1;
         l[q] = m;
-        if (box_count(k, l, h) > 0) a = m; else b = m - 1;
+        if (box_count(k, S, l, h) > 0) a = m; else b = m - 1;
     }
     return a + 1;
 }
@@ -99,17 +104,19 @@ __global__ __launch_bounds__(64) void k_kd_root(KdArgs k)
     __shared__ int face[6];
     const int lane = threadIdx.x;
     const int lo[3] = {0, 0, 0}, hi[3] = {k.nb[0], k.nb[1], k.nb[2]};
-    const int32_t total = box_count(k, lo, hi);
+    const int32_t total = box_count(k, (const int32_t *)k.S, lo, hi);
     if (total == 0) {
         if (lane == 0) {
             k.hdr->kd_count = 0;
             k.hdr->kd_height = 0;
             k.hdr->kd_begin = 0;
             k.hdr->kd_end = 0;
+            k.hdr->kd_ticket = 0;
+            k.hdr->pad[0] = 0;
         }
         return;
     }
-    if (lane < 6) face[lane] = tight_face(k, lo, hi, lane);
+    if (lane < 6) face[lane] = tight_face(k, (const int32_t *)k.S, lo, hi, lane);
     __syncthreads();
     if (lane < 3) {
         k.lo[lane] = face[lane];
@@ -120,6 +127,8 @@ __global__ __launch_bounds__(64) void k_kd_root(KdArgs k)
         k.hdr->kd_height = 1;
         k.hdr->kd_begin = 0;
         k.hdr->kd_end = 1;
+        k.hdr->kd_ticket = 0;
+        k.hdr->pad[0] = 0;
     }
 }
 
@@ -146,40 +155,38 @@ __device__ inline int candidate(const int lo[3], const int hi[3], int bins, int 
 
 constexpr int kMaxCand = 45;   // 3 axes x (16 bins - 1)
 
-// one wave per node of the level [begin, end)
-__global__ __launch_bounds__(256) void k_kd_eval(KdArgs k, uint32_t begin, uint32_t end)
+// Decides the split of one node (one wave): every (candidate plane, side,
+// face) binary search runs on its own lane; lane 0 writes axis, plane, split
+// flag and the two children's tight boxes.  tb: this wave's scratch.
+template <typename SP>
+__device__ void eval_node(const KdArgs &k, SP S, int64_t node, int64_t vroot, int16_t (*tb)[2][6])
 {
-    __shared__ int tb[4][kMaxCand + 1][2][6];   // per wave: tight boxes (candidate, side, face)
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t node = (int64_t)begin + (int64_t)blockIdx.x * 4 + wave;
-    if (node >= end) return;
+    const int lane = threadIdx.x & 63;
     int lo[3], hi[3];
     for (int q = 0; q < 3; ++q) {
         lo[q] = k.lo[3 * node + q];
         hi[q] = k.hi[3 * node + q];
     }
     const int64_t V = box_volume(k, lo, hi);
-    const int rlo[3] = {k.lo[0], k.lo[1], k.lo[2]}, rhi[3] = {k.hi[0], k.hi[1], k.hi[2]};
-    const int64_t vroot = box_volume(k, rlo, rhi);
     const bool allowed = k.halting == 0 ? (10 * V > vroot) : (V > 512);
     int dummy_a = 0, dummy_p = 0;
     const int ncand = allowed ? candidate(lo, hi, k.bins, -1, &dummy_a, &dummy_p) : 0;
     int best = -1;
     int64_t best_cost = 0;
     if (ncand > 0) {
-        // tasks: (candidate, side, face)
         for (int t = lane; t < ncand * 12; t += 64) {
             const int c = t / 12, side = (t / 6) & 1, face = t % 6;
             int a = 0, p = 0;
             candidate(lo, hi, k.bins, c, &a, &p);
             int rl[3] = {lo[0], lo[1], lo[2]}, rh[3] = {hi[0], hi[1], hi[2]};
             if (side == 0) rh[a] = p; else rl[a] = p;
-            tb[wave][c][side][face] = tight_face(k, rl, rh, face);
+            tb[c][side][face] = (int16_t)tight_face(k, S, rl, rh, face);
         }
         wave_lds_sync();
         int64_t cost = 0x7fffffffffffffffLL;
         if (lane < ncand) {
-            const int *L = tb[wave][lane][0], *R = tb[wave][lane][1];
+            int L[6], R[6];
+            for (int f = 0; f < 6; ++f) { L[f] = tb[lane][0][f]; R[f] = tb[lane][1][f]; }
             cost = box_volume(k, L, L + 3) + box_volume(k, R, R + 3);
         }
         // argmin over (cost, candidate index): lower index wins ties
@@ -197,7 +204,7 @@ __global__ __launch_bounds__(256) void k_kd_eval(KdArgs k, uint32_t begin, uint3
     if (best >= 0 && best_cost < V) {
         candidate(lo, hi, k.bins, best, &axis, &plane);
         for (int s = 0; s < 2; ++s)
-            for (int f = 0; f < 6; ++f) cl[s][f] = tb[wave][best][s][f];
+            for (int f = 0; f < 6; ++f) cl[s][f] = tb[best][s][f];
     } else if (best >= 0 && k.max_leaf > 0 &&
                V > (int64_t)k.max_leaf * k.max_leaf * k.max_leaf) {
         // maximum leaf size: middle of the axis with the largest voxel extent
@@ -208,15 +215,16 @@ __global__ __launch_bounds__(256) void k_kd_eval(KdArgs k, uint32_t begin, uint3
             const int64_t ext = (int64_t)min(k.B * hi[a], k.n[a]) - (int64_t)k.B * lo[a];
             if (ext > best_ext) { best_ext = ext; axis = a; plane = lo[a] + e / 2; }
         }
+        wave_lds_sync();
         if (lane < 12) {
             const int side = lane / 6, face = lane % 6;
             int rl[3] = {lo[0], lo[1], lo[2]}, rh[3] = {hi[0], hi[1], hi[2]};
             if (side == 0) rh[axis] = plane; else rl[axis] = plane;
-            tb[wave][kMaxCand][side][face] = tight_face(k, rl, rh, face);
+            tb[kMaxCand][side][face] = (int16_t)tight_face(k, S, rl, rh, face);
         }
         wave_lds_sync();
         for (int s = 0; s < 2; ++s)
-            for (int f = 0; f < 6; ++f) cl[s][f] = tb[wave][kMaxCand][s][f];
+            for (int f = 0; f < 6; ++f) cl[s][f] = tb[kMaxCand][s][f];
     }
     if (lane == 0) {
         k.axis[node] = axis;
@@ -226,41 +234,210 @@ __global__ __launch_bounds__(256) void k_kd_eval(KdArgs k, uint32_t begin, uint3
             for (int s = 0; s < 2; ++s)
                 for (int f = 0; f < 6; ++f) k.clo[12 * node + 6 * s + f] = cl[s][f];
         if (axis < 0) k.first[node] = -1;
+        __threadfence();  // the level's emitter may run on another XCD
+    }
+    wave_lds_sync();
+}
+
+__device__ inline int64_t root_volume(const KdArgs &k)
+{
+    const int rlo[3] = {k.lo[0], k.lo[1], k.lo[2]}, rhi[3] = {k.hi[0], k.hi[1], k.hi[2]};
+    return box_volume(k, rlo, rhi);
+}
+
+// Small grids (<= 32768 bricks): the 3-D prefix count is built in LDS by one
+// workgroup, written out, and the root's tight box found -- one launch
+// instead of three prefix passes plus the root kernel.
+constexpr int kKdSmallBricks = 32768;
+
+__global__ __launch_bounds__(1024) void k_kd_prefix_root_small(KdArgs k)
+{
+    extern __shared__ int32_t S[];
+    const int nbx = k.nb[0], nby = k.nb[1], nbz = k.nb[2];
+    const int nb = nbx * nby * nbz;
+    const int t = threadIdx.x;
+    for (int line = t; line < nby * nbz; line += 1024) {
+        int run = 0;
+        for (int x = 0; x < nbx; ++x) {
+            run += k.flags[(int64_t)line * nbx + x];
+            S[line * nbx + x] = run;
+        }
+    }
+    __syncthreads();
+    for (int line = t; line < nbx * nbz; line += 1024) {
+        const int x = line % nbx, z = line / nbx;
+        int run = 0;
+        for (int y = 0; y < nby; ++y) {
+            const int idx = x + nbx * (y + nby * z);
+            run += S[idx];
+            S[idx] = run;
+        }
+    }
+    __syncthreads();
+    for (int line = t; line < nbx * nby; line += 1024) {
+        int run = 0;
+        for (int z = 0; z < nbz; ++z) {
+            const int idx = line + nbx * nby * z;
+            run += S[idx];
+            S[idx] = run;
+        }
+    }
+    __syncthreads();
+    for (int i = t; i < nb; i += 1024) k.S[i] = S[i];
+    const int glo[3] = {0, 0, 0}, ghi[3] = {nbx, nby, nbz};
+    const bool any = box_count(k, (const int32_t *)S, glo, ghi) > 0;
+    if (any && t < 6) {
+        const int f = tight_face(k, (const int32_t *)S, glo, ghi, t);
+        if (t < 3) k.lo[t] = f; else k.hi[t - 3] = f;
+    }
+    if (t == 0) {
+        k.hdr->kd_count = any ? 1u : 0u;
+        k.hdr->kd_height = any ? 1u : 0u;
+        k.hdr->kd_begin = 0;
+        k.hdr->kd_end = any ? 1u : 0u;
+        k.hdr->kd_ticket = 0;
+        k.hdr->pad[0] = 0;
     }
 }
 
-// single workgroup: breadth-first numbering of the children of [begin, end)
-__global__ __launch_bounds__(1024) void k_kd_emit(KdArgs k, uint32_t begin, uint32_t end)
+// One level per launch, no host round trip: the level bounds come from the
+// device header (a level past the last one finds begin == end and exits).
+// Waves of a fixed grid evaluate the level's nodes; the last block to finish
+// (ticket counter, agent-scope release/acquire) numbers the children in
+// breadth-first order and publishes the next level.
+constexpr int kKdLevelBlocks = 128;
+
+__global__ __launch_bounds__(256) void k_kd_level(KdArgs k)
 {
-    __shared__ uint32_t scratch[17];
+    __shared__ int16_t tb[4][kMaxCand + 1][2][6];
+    __shared__ uint32_t scratch[5];
+    __shared__ uint32_t last;
+    const uint32_t begin = k.hdr->kd_begin, end = k.hdr->kd_end;
+    if (begin == end) return;
+    const int wave = threadIdx.x >> 6;
+    const int64_t vroot = root_volume(k);
+    for (int64_t node = (int64_t)begin + (int64_t)blockIdx.x * 4 + wave; node < end;
+         node += (int64_t)gridDim.x * 4)
+        eval_node(k, (const int32_t *)k.S, node, vroot, tb[wave]);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t old = __hip_atomic_fetch_add(&k.hdr->kd_ticket, 1u, __ATOMIC_ACQ_REL,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        last = (old == gridDim.x - 1) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    // breadth-first numbering of the children, 256 threads
     const int64_t width = (int64_t)end - begin;
-    const int64_t per = (width + 1023) / 1024;
+    const int64_t per = (width + 255) / 256;
     const int64_t i0 = begin + threadIdx.x * per;
     const int64_t i1 = min((int64_t)end, i0 + per);
     uint32_t c = 0;
-    for (int64_t i = i0; i < i1; ++i) c += (uint32_t)k.split[i];
+    for (int64_t i = i0; i < i1; ++i)
+        c += (uint32_t)__hip_atomic_load(&k.split[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint32_t total;
-    uint32_t run = block_exclusive_scan<1024>(c, scratch, &total);
-    for (int64_t i = i0; i < i1; ++i) {
-        if (!k.split[i]) continue;
-        const int64_t child = (int64_t)end + 2 * (int64_t)run;
-        k.first[i] = (int32_t)child;
-        for (int s = 0; s < 2; ++s)
-            for (int q = 0; q < 3; ++q) {
-                k.lo[3 * (child + s) + q] = k.clo[12 * i + 6 * s + q];
-                k.hi[3 * (child + s) + q] = k.clo[12 * i + 6 * s + 3 + q];
-            }
-        ++run;
+    uint32_t run = block_exclusive_scan<256>(c, scratch, &total);
+    const bool fits = (int64_t)end + 2 * (int64_t)total <= k.cap;
+    if (fits) {
+        for (int64_t i = i0; i < i1; ++i) {
+            if (!__hip_atomic_load(&k.split[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) continue;
+            const int64_t child = (int64_t)end + 2 * (int64_t)run;
+            k.first[i] = (int32_t)child;
+            for (int s2 = 0; s2 < 2; ++s2)
+                for (int q = 0; q < 3; ++q) {
+                    k.lo[3 * (child + s2) + q] = __hip_atomic_load(&k.clo[12 * i + 6 * s2 + q], __ATOMIC_RELAXED,
+                                                                   __HIP_MEMORY_SCOPE_AGENT);
+                    k.hi[3 * (child + s2) + q] = __hip_atomic_load(&k.clo[12 * i + 6 * s2 + 3 + q],
+                                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            ++run;
+        }
     }
+    __syncthreads();
     if (threadIdx.x == 0) {
+        if (!fits) k.hdr->pad[0] = 1u;  // cannot happen for a correct build: stop growing
+        const uint32_t next = fits ? end + 2 * total : end;
         k.hdr->kd_begin = end;
-        k.hdr->kd_end = end + 2 * total;
-        k.hdr->kd_count = end + 2 * total;
-        if (total > 0) k.hdr->kd_height += 1;
+        k.hdr->kd_end = next;
+        k.hdr->kd_count = next;
+        if (fits && total > 0) k.hdr->kd_height += 1;
+        k.hdr->kd_ticket = 0;
+        __threadfence();
     }
 }
 
+// voxel box of node m (bricks -> voxels, clipped to the volume)
+__device__ inline void kd_voxel_box(const KdArgs &k, int64_t m, int lo[3], int hi[3])
+{
+    for (int q = 0; q < 3; ++q) {
+        lo[q] = k.B * k.lo[3 * m + q];
+        hi[q] = min(k.B * k.hi[3 * m + q], k.n[q]);
+    }
+}
+
+// traversal records: every node's own voxel box, and an RNode per internal
+// node.  Runs only on a finished tree: while levels remain (begin != end) the
+// nodes of the pending level have not been evaluated, and their axis/first
+// entries are stale workspace contents that must not be used as indices.
+__global__ __launch_bounds__(256) void k_kd_pack(KdArgs k)
+{
+    const uint32_t count = k.hdr->kd_count;
+    if (k.hdr->kd_begin != k.hdr->kd_end || (int64_t)count > k.cap) return;
+    const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (m >= (int64_t)count) return;
+    int lo[3], hi[3];
+    uint32_t w[3];
+    kd_voxel_box(k, m, lo, hi);
+    pack_box(lo, hi, w);
+    k.box[m] = make_uint4(w[0], w[1], w[2], 0u);
+    const int a = k.axis[m];
+    if (a < 0) return;
+    const int c = k.first[m];
+    if (c <= m || (int64_t)c + 1 >= (int64_t)count || a > 2) return;  // never true for a finished tree
+    RNode rec;
+    kd_voxel_box(k, c, lo, hi);
+    pack_box(lo, hi, &rec.w[0]);
+    kd_voxel_box(k, c + 1, lo, hi);
+    pack_box(lo, hi, &rec.w[3]);
+    rec.w[6] = (uint32_t)c | ((uint32_t)a << 29) | (k.axis[c] < 0 ? kLeaf : 0u);
+    rec.w[7] = (uint32_t)(c + 1) | (k.axis[c + 1] < 0 ? kLeaf : 0u);
+    uint4 *dst = reinterpret_cast<uint4 *>(&k.rnode[m]);
+    dst[0] = make_uint4(rec.w[0], rec.w[1], rec.w[2], rec.w[3]);
+    dst[1] = make_uint4(rec.w[4], rec.w[5], rec.w[6], rec.w[7]);
+}
+
 }  // namespace
+
+hipError_t launch_kd_pack(const KdArgs &k, int64_t max_nodes, hipStream_t s)
+{
+    if (max_nodes <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_kd_pack, dim3((unsigned)((max_nodes + 255) / 256)), dim3(256), 0, s, k);
+    return hipGetLastError();
+}
+
+bool kd_small(const KdArgs &k)
+{
+    return (int64_t)k.nb[0] * k.nb[1] * k.nb[2] <= kKdSmallBricks;
+}
+
+hipError_t launch_kd_prefix_root_small(const KdArgs &k, hipStream_t s)
+{
+    const size_t lds = sizeof(int32_t) * (size_t)k.nb[0] * k.nb[1] * k.nb[2];
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_kd_prefix_root_small),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_kd_prefix_root_small, dim3(1), dim3(1024), lds, s, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_kd_levels(const KdArgs &k, int count, hipStream_t s)
+{
+    for (int i = 0; i < count; ++i)
+        hipLaunchKernelGGL(k_kd_level, dim3(kKdLevelBlocks), dim3(256), 0, s, k);
+    return hipGetLastError();
+}
 
 hipError_t launch_kd_prefix(const KdArgs &k, hipStream_t s)
 {
@@ -277,13 +454,5 @@ hipError_t launch_kd_root(const KdArgs &k, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_kd_level(const KdArgs &k, uint32_t begin, uint32_t end, hipStream_t s)
-{
-    const int64_t width = (int64_t)end - begin;
-    if (width <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_kd_eval, dim3((unsigned)((width + 3) / 4)), dim3(256), 0, s, k, begin, end);
-    hipLaunchKernelGGL(k_kd_emit, dim3(1), dim3(1024), 0, s, k, begin, end);
-    return hipGetLastError();
-}
 
 }  // namespace esk

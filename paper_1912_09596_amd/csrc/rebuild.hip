@@ -320,7 +320,7 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t *in, uint32
 }
 
 // ---------------------------------------------------------------------------
-// a7 + a8: Karras hierarchy and bottom-up refit
+// a7 + a8: Karras hierarchy, range-union AABBs, height
 // ---------------------------------------------------------------------------
 
 __device__ inline int delta(const uint32_t *k, int n, int i, int j)
@@ -350,7 +350,6 @@ __global__ __launch_bounds__(256) void k_karras(RebuildArgs a)
             a.lb_lo[3 * node + q] = a.vol.B * b[q];
             a.lb_hi[3 * node + q] = min(a.vol.B * b[q] + a.vol.B, nn[q]);
         }
-        a.lb_height[node] = 1;
     }
     if (i >= n - 1) return;
     const int d = (delta(k, n, i, i + 1) - delta(k, n, i, i - 1)) > 0 ? 1 : -1;
@@ -378,49 +377,80 @@ __global__ __launch_bounds__(256) void k_karras(RebuildArgs a)
     a.lb_axis[i] = 2 - hb % 3;
     a.lb_parent[(left & kLeaf) ? (n - 1) + g : g] = (uint32_t)i;
     a.lb_parent[(right & kLeaf) ? (n - 1) + g + 1 : g + 1] = (uint32_t)i;
-    a.lb_flag[i] = 0;
+    a.lb_range[i] = make_int2(lo, hi);
 }
 
-// one thread per leaf climbs to the root; the second child to arrive at a
-// node computes its union box and height (release/acquire at agent scope so
-// the sibling's box is visible across XCDs)
-__global__ __launch_bounds__(256) void k_refit(RebuildArgs a)
+// a8: AABBs.  Every internal node covers a contiguous range of sorted keys,
+// so its children's boxes are unions over two leaf ranges: one wave per
+// internal node reduces both ranges (no cross-node dependency, no atomics),
+// writes the node's own box (the union) and its traversal record.
+__global__ __launch_bounds__(256) void k_lbvh_boxes(RebuildArgs a)
+{
+    const int n = (int)a.hdr->n;
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n - 1) return;
+    const int2 rg = a.lb_range[i];
+    const uint32_t l = a.lb_left[i], r = a.lb_right[i];
+    const int g = (int)(l & ~kLeaf);
+    int box[2][6];
+    for (int side = 0; side < 2; ++side) {
+        const int j0 = side == 0 ? rg.x : g + 1, j1 = side == 0 ? g : rg.y;
+        int b[6] = {0x7fffffff, 0x7fffffff, 0x7fffffff, -1, -1, -1};
+        for (int j = j0 + lane; j <= j1; j += 64) {
+            const int u = (n - 1) + j;
+            for (int q = 0; q < 3; ++q) {
+                b[q] = min(b[q], a.lb_lo[3 * u + q]);
+                b[3 + q] = max(b[3 + q], a.lb_hi[3 * u + q]);
+            }
+        }
+        for (int o = 32; o >= 1; o >>= 1)
+            for (int q = 0; q < 3; ++q) {
+                b[q] = min(b[q], __shfl_xor(b[q], o, 64));
+                b[3 + q] = max(b[3 + q], __shfl_xor(b[3 + q], o, 64));
+            }
+        for (int q = 0; q < 6; ++q) box[side][q] = b[q];
+    }
+    if (lane == 0) {
+        for (int q = 0; q < 3; ++q) {
+            a.lb_lo[3 * i + q] = min(box[0][q], box[1][q]);
+            a.lb_hi[3 * i + q] = max(box[0][3 + q], box[1][3 + q]);
+        }
+        RNode rec;
+        pack_box(&box[0][0], &box[0][3], &rec.w[0]);
+        pack_box(&box[1][0], &box[1][3], &rec.w[3]);
+        rec.w[6] = l | ((uint32_t)a.lb_axis[i] << 29);
+        rec.w[7] = r;
+        uint4 *dst = reinterpret_cast<uint4 *>(&a.lb_rnode[i]);
+        dst[0] = make_uint4(rec.w[0], rec.w[1], rec.w[2], rec.w[3]);
+        dst[1] = make_uint4(rec.w[4], rec.w[5], rec.w[6], rec.w[7]);
+    }
+}
+
+// height in levels = 1 + the deepest leaf's number of ancestors; also packs
+// every leaf's box for the traversal
+__global__ __launch_bounds__(256) void k_lbvh_height(RebuildArgs a)
 {
     const int n = (int)a.hdr->n;
     const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= n) return;
-    if (n == 1) {
-        a.hdr->lbvh_height = 1;
-        return;
-    }
-    uint32_t cur = a.lb_parent[(n - 1) + j];
-    while (true) {
-        __threadfence();
-        const uint32_t old = __hip_atomic_fetch_add(&a.lb_flag[cur], 1u, __ATOMIC_ACQ_REL,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-        if (old == 0) return;
-        __threadfence();
-        const uint32_t l = a.lb_left[cur], r = a.lb_right[cur];
-        const int ln = (l & kLeaf) ? (n - 1) + (int)(l & ~kLeaf) : (int)l;
-        const int rn = (r & kLeaf) ? (n - 1) + (int)(r & ~kLeaf) : (int)r;
-        for (int q = 0; q < 3; ++q) {
-            const int lo0 = __hip_atomic_load(&a.lb_lo[3 * ln + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const int lo1 = __hip_atomic_load(&a.lb_lo[3 * rn + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const int hi0 = __hip_atomic_load(&a.lb_hi[3 * ln + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const int hi1 = __hip_atomic_load(&a.lb_hi[3 * rn + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&a.lb_lo[3 * cur + q], min(lo0, lo1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&a.lb_hi[3 * cur + q], max(hi0, hi1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t depth = 0;
+    if (j < n) {
+        const int u = (n - 1) + j;
+        uint32_t w[3];
+        pack_box(&a.lb_lo[3 * u], &a.lb_hi[3 * u], w);
+        a.lb_leafbox[j] = make_uint4(w[0], w[1], w[2], 0u);
+        if (n > 1) {
+            uint32_t cur = a.lb_parent[u];
+            depth = 1;
+            while (cur != 0) {
+                cur = a.lb_parent[cur];
+                ++depth;
+            }
         }
-        const uint32_t hl = __hip_atomic_load(&a.lb_height[ln], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t hr = __hip_atomic_load(&a.lb_height[rn], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t h = 1 + max(hl, hr);
-        __hip_atomic_store(&a.lb_height[cur], h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (cur == 0) {
-            a.hdr->lbvh_height = h;
-            return;
-        }
-        cur = a.lb_parent[cur];
+        depth += 1;
     }
+    for (int o = 32; o >= 1; o >>= 1) depth = max(depth, (uint32_t)__shfl_xor((int)depth, o, 64));
+    if ((threadIdx.x & 63) == 0 && depth > 0) atomicMax(&a.hdr->lbvh_height, depth);
 }
 
 }  // namespace
@@ -463,7 +493,8 @@ hipError_t launch_lbvh(const RebuildArgs &a, hipStream_t s)
 {
     const unsigned blocks = (unsigned)((a.nb + 255) / 256);
     hipLaunchKernelGGL(k_karras, dim3(blocks), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_refit, dim3(blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_lbvh_boxes, dim3((unsigned)((a.nb + 3) / 4)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_lbvh_height, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

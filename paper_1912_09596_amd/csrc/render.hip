@@ -31,6 +31,7 @@ constexpr float kBoxEps = 1.0f / 32.0f;   // voxel-space slack of the culling te
 
 struct Ray {
     float o[3], d[3];
+    float inv[3];   // 1/d (0 where d == 0): conservative tests only
     float t0, tx;
 };
 
@@ -51,7 +52,12 @@ __device__ inline void make_ray(const esk_camera &c, int px, int py, Ray &r)
     }
     const float l2 = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
     const float len = sqrtf(l2);
-    for (int a = 0; a < 3; ++a) r.d[a] = v[a] / len;
+    for (int a = 0; a < 3; ++a) {
+        r.d[a] = v[a] / len;
+        // d == 0: a huge reciprocal makes the slab unbounded when the origin
+        // is inside it and empty when outside, without a branch
+        r.inv[a] = r.d[a] != 0.0f ? __builtin_amdgcn_rcpf(r.d[a]) : 1.0e30f;
+    }
 }
 
 __device__ inline bool slab(const Ray &r, const float lo[3], const float hi[3], float &tn, float &tf)
@@ -72,6 +78,21 @@ __device__ inline bool slab(const Ray &r, const float lo[3], const float hi[3], 
     tn = t0;
     tf = t1;
     return true;
+}
+
+// the slab test with reciprocal multiplies and no branches: only used where
+// the result is widened by a margin and every sample is then checked exactly
+__device__ inline void slab_fast(const Ray &r, const float lo[3], const float hi[3], float &tn, float &tf)
+{
+    float t0 = -3.402823466e+38f, t1 = 3.402823466e+38f;
+    for (int a = 0; a < 3; ++a) {
+        const float ta = (lo[a] - r.o[a]) * r.inv[a];
+        const float tb = (hi[a] - r.o[a]) * r.inv[a];
+        t0 = fmaxf(t0, fminf(ta, tb));
+        t1 = fminf(t1, fmaxf(ta, tb));
+    }
+    tn = t0;
+    tf = t1;
 }
 
 __device__ inline float lattice_t(const Ray &r, float dt, int k)
@@ -157,8 +178,9 @@ struct Vol {
 
 __device__ inline bool inside(const Vol &v, const float p[3])
 {
-    return p[0] >= 0.0f && p[0] < v.fn[0] && p[1] >= 0.0f && p[1] < v.fn[1] && p[2] >= 0.0f &&
-           p[2] < v.fn[2];
+    // non-short-circuit: one mask, no branch per axis
+    return (p[0] >= 0.0f) & (p[0] < v.fn[0]) & (p[1] >= 0.0f) & (p[1] < v.fn[1]) & (p[2] >= 0.0f) &
+           (p[2] < v.fn[2]);
 }
 
 // conservative hit of a box [lo, hi) (integer voxel bounds) by the ray segment
@@ -170,7 +192,7 @@ __device__ inline bool hit_box(const Ray &r, float dt, const int lo[3], const in
         h[a] = (float)hi[a] + kBoxEps;
     }
     float tn, tf;
-    if (!slab(r, l, h, tn, tf)) return false;
+    slab_fast(r, l, h, tn, tf);
     return tn <= tf + dt && tf >= r.t0 - dt && tn <= r.tx + dt;
 }
 
@@ -187,9 +209,11 @@ __device__ inline void march_leaf(const Ray &r, float dt, const int lo[3], const
         h[a] = bh[a] + kBoxEps;
     }
     float tn, tf;
-    if (!slab(r, l, h, tn, tf)) return;
-    float fa = (tn - r.t0) / dt - 0.5f;
-    float fb = (tf - r.t0) / dt - 0.5f;
+    slab_fast(r, l, h, tn, tf);
+    if (tn > tf + dt) return;
+    const float idt = __builtin_amdgcn_rcpf(dt);
+    float fa = (tn - r.t0) * idt - 0.5f;
+    float fb = (tf - r.t0) * idt - 0.5f;
     fa = fminf(fmaxf(fa, -4.0f), 1.0e9f);
     fb = fminf(fmaxf(fb, -4.0f), 1.0e9f);
     const int ka = max(0, (int)floorf(fa) - 1);
@@ -199,26 +223,100 @@ __device__ inline void march_leaf(const Ray &r, float dt, const int lo[3], const
         if (!(t < r.tx)) break;
         float p[3];
         point_at(r, t, p);
-        if (p[0] >= bl[0] && p[0] < bh[0] && p[1] >= bl[1] && p[1] < bh[1] && p[2] >= bl[2] && p[2] < bh[2])
+        if ((p[0] >= bl[0]) & (p[0] < bh[0]) & (p[1] >= bl[1]) & (p[1] < bh[1]) & (p[2] >= bl[2]) &
+            (p[2] < bh[2]))
             composite(s, trilinear<T, IDX>(vol, v.n[0], v.n[1], v.n[2], p), acc);
     }
 }
 
-template <int ACCEL, typename T, typename IDX>
-__global__ __launch_bounds__(256) void k_render(RenderArgs ra)
+__device__ inline void unpack_box(uint32_t w0, uint32_t w1, uint32_t w2, int lo[3], int hi[3])
+{
+    lo[0] = (int)(w0 & 0xffffu);
+    lo[1] = (int)(w0 >> 16);
+    lo[2] = (int)(w1 & 0xffffu);
+    hi[0] = (int)(w1 >> 16);
+    hi[1] = (int)(w2 & 0xffffu);
+    hi[2] = (int)(w2 >> 16);
+}
+
+// Ordered traversal of a binary hierarchy stored as RNode records (LBVH or
+// k-d): near child first by the sign of the direction along the node's
+// split axis, far child on an LDS stack (lane-interleaved), leaves marched
+// in the order they are reached.  Popped leaves fetch their packed box.
+template <typename T, typename IDX>
+__device__ inline void traverse(const Ray &r, float dt, const RNode *__restrict__ nodes,
+                                const uint4 *__restrict__ leafbox, uint32_t root, int lo[3], int hi[3],
+                                int *stk, int cap, const T *__restrict__ vol, const Vol &v, const Shade &s,
+                                Accum &acc)
+{
+    if (!hit_box(r, dt, lo, hi)) return;
+    uint32_t cur = root;
+    int sp = 0;
+    while (true) {
+        if (cur & kLeaf) {
+            march_leaf<T, IDX>(r, dt, lo, hi, vol, v, s, acc);
+        } else {
+            const uint4 *q = reinterpret_cast<const uint4 *>(&nodes[cur & kIndexMask]);
+            const uint4 A = q[0], Q = q[1];
+            int l0[3], h0[3], l1[3], h1[3];
+            unpack_box(A.x, A.y, A.z, l0, h0);
+            unpack_box(A.w, Q.x, Q.y, l1, h1);
+            const uint32_t c0 = Q.z & (kLeaf | kIndexMask), c1 = Q.w;
+            const int axis = (int)((Q.z >> 29) & 3u);
+            const bool hit0 = hit_box(r, dt, l0, h0), hit1 = hit_box(r, dt, l1, h1);
+            // select, not index: a dynamic index would move the ray to scratch
+            const float da = axis == 0 ? r.d[0] : (axis == 1 ? r.d[1] : r.d[2]);
+            const bool flip = da < 0.0f;
+            const bool hn = flip ? hit1 : hit0, hf = flip ? hit0 : hit1;
+            const uint32_t nr = flip ? c1 : c0, fr = flip ? c0 : c1;
+            if (hn) {
+                if (hf && sp < cap) {
+                    stk[sp * 256 + threadIdx.x] = (int)fr;
+                    ++sp;
+                }
+                cur = nr;
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = flip ? l1[a] : l0[a];
+                    hi[a] = flip ? h1[a] : h0[a];
+                }
+                continue;
+            }
+            if (hf) {
+                cur = fr;
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = flip ? l0[a] : l1[a];
+                    hi[a] = flip ? h0[a] : h1[a];
+                }
+                continue;
+            }
+        }
+        if (sp == 0) break;
+        --sp;
+        cur = (uint32_t)stk[sp * 256 + threadIdx.x];
+        if (cur & kLeaf) {
+            const uint4 b = leafbox[cur & kIndexMask];
+            unpack_box(b.x, b.y, b.z, lo, hi);
+        }
+    }
+}
+
+// One 16x16 pixel tile (tbx, tby) of one request.  TFL: the TF (N <= 1024
+// entries) is staged in LDS; otherwise read from global memory.
+template <int ACCEL, typename T, typename IDX, bool TFL>
+__device__ inline void render_tile(const RenderArgs &ra, int tbx, int tby)
 {
     extern __shared__ float4 lds[];
-    const bool tf_lds = ra.N <= 1024;
+    constexpr bool tf_lds = TFL;
     if (tf_lds) {
         const float4 *src = reinterpret_cast<const float4 *>(ra.tf);
         for (int i = threadIdx.x; i < ra.N; i += 256) lds[i] = src[i];
         __syncthreads();
     }
-    int *stk = reinterpret_cast<int *>(lds + (tf_lds ? 1024 : 0));
+    int *stk = reinterpret_cast<int *>(lds + (tf_lds ? ra.N : 0));
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int px = blockIdx.x * 16 + (wave & 1) * 8 + (lane & 7);
-    const int py = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
+    const int px = tbx * 16 + (wave & 1) * 8 + (lane & 7);
+    const int py = tby * 16 + (wave >> 1) * 8 + (lane >> 3);
     if (px >= ra.W || py >= ra.H) return;
 
     const T *__restrict__ vol = static_cast<const T *>(ra.vol.vox);
@@ -273,8 +371,9 @@ __global__ __launch_bounds__(256) void k_render(RenderArgs ra)
                                       (float)min(bz * B + B, v.n[2])};
                 float cn, cx;
                 int next = k + 1;
-                if (slab(r, blo, bhi, cn, cx)) {
-                    float fj = (cx - r.t0) / dt - 0.5f;
+                slab_fast(r, blo, bhi, cn, cx);
+                {
+                    float fj = (cx - r.t0) * __builtin_amdgcn_rcpf(dt) - 0.5f;
                     fj = fminf(fmaxf(fj, -4.0f), 1.0e9f);
                     const int kj = (int)floorf(fj);
                     for (int c = kj; c >= kj - 1; --c) {
@@ -293,86 +392,19 @@ __global__ __launch_bounds__(256) void k_render(RenderArgs ra)
         } else if (ACCEL == ESK_ACCEL_LBVH) {
             const int N = (int)ra.hdr->n;
             if (N > 0) {
-                auto box_of = [&](uint32_t node, int lo[3], int hi[3]) {
-                    const int u = (node & kLeaf) ? (N - 1) + (int)(node & ~kLeaf) : (int)node;
-                    for (int a = 0; a < 3; ++a) {
-                        lo[a] = ra.lb_lo[3 * u + a];
-                        hi[a] = ra.lb_hi[3 * u + a];
-                    }
-                };
-                uint32_t node = (N == 1) ? kLeaf : 0u;
                 int lo[3], hi[3];
-                box_of(node, lo, hi);
-                int sp = 0;
-                bool live = hit_box(r, dt, lo, hi);
-                while (live) {
-                    if (node & kLeaf) {
-                        box_of(node, lo, hi);
-                        march_leaf<T, IDX>(r, dt, lo, hi, vol, v, s, acc);
-                    } else {
-                        const int a = ra.lb_axis[node];
-                        const uint32_t l = ra.lb_left[node], rr = ra.lb_right[node];
-                        const uint32_t nr = r.d[a] < 0.0f ? rr : l;
-                        const uint32_t fr = r.d[a] < 0.0f ? l : rr;
-                        int l0[3], h0[3], l1[3], h1[3];
-                        box_of(nr, l0, h0);
-                        box_of(fr, l1, h1);
-                        const bool hn = hit_box(r, dt, l0, h0), hf = hit_box(r, dt, l1, h1);
-                        if (hn && hf && sp < ra.stack_cap) {
-                            stk[sp * 256 + threadIdx.x] = (int)fr;
-                            ++sp;
-                            node = nr;
-                            continue;
-                        }
-                        if (hn) { node = nr; continue; }
-                        if (hf) { node = fr; continue; }
-                    }
-                    if (sp == 0) break;
-                    --sp;
-                    node = (uint32_t)stk[sp * 256 + threadIdx.x];
-                }
+                for (int a = 0; a < 3; ++a) { lo[a] = ra.lb_lo[a]; hi[a] = ra.lb_hi[a]; }
+                traverse<T, IDX>(r, dt, ra.lb_rnode, ra.lb_leafbox, N == 1 ? kLeaf : 0u, lo, hi, stk,
+                                 ra.stack_cap, vol, v, s, acc);
             }
         } else if (ACCEL == ESK_ACCEL_KD) {
             const int M = (int)ra.hdr->kd_count;
             if (M > 0) {
-                const int B = ra.vol.B;
-                auto box_of = [&](int node, int lo[3], int hi[3]) {
-                    for (int a = 0; a < 3; ++a) {
-                        lo[a] = B * ra.kd_lo[3 * node + a];
-                        hi[a] = min(B * ra.kd_hi[3 * node + a], v.n[a]);
-                    }
-                };
-                int node = 0;
                 int lo[3], hi[3];
-                box_of(0, lo, hi);
-                int sp = 0;
-                bool live = hit_box(r, dt, lo, hi);
-                while (live) {
-                    const int a = ra.kd_axis[node];
-                    if (a < 0) {
-                        box_of(node, lo, hi);
-                        march_leaf<T, IDX>(r, dt, lo, hi, vol, v, s, acc);
-                    } else {
-                        const int c = ra.kd_first[node];
-                        const int nr = r.d[a] < 0.0f ? c + 1 : c;
-                        const int fr = r.d[a] < 0.0f ? c : c + 1;
-                        int l0[3], h0[3], l1[3], h1[3];
-                        box_of(nr, l0, h0);
-                        box_of(fr, l1, h1);
-                        const bool hn = hit_box(r, dt, l0, h0), hf = hit_box(r, dt, l1, h1);
-                        if (hn && hf && sp < ra.stack_cap) {
-                            stk[sp * 256 + threadIdx.x] = fr;
-                            ++sp;
-                            node = nr;
-                            continue;
-                        }
-                        if (hn) { node = nr; continue; }
-                        if (hf) { node = fr; continue; }
-                    }
-                    if (sp == 0) break;
-                    --sp;
-                    node = stk[sp * 256 + threadIdx.x];
-                }
+                const uint4 b = ra.kd_box[0];
+                unpack_box(b.x, b.y, b.z, lo, hi);
+                traverse<T, IDX>(r, dt, ra.kd_rnode, ra.kd_box, M == 1 ? kLeaf : 0u, lo, hi, stk,
+                                 ra.stack_cap, vol, v, s, acc);
             }
         }
     }
@@ -381,24 +413,85 @@ __global__ __launch_bounds__(256) void k_render(RenderArgs ra)
     if (ra.count) ra.count[pix] = acc.n;
 }
 
+template <int ACCEL, typename T, typename IDX, bool TFL>
+__global__ __launch_bounds__(256) void k_render(RenderArgs ra)
+{
+    render_tile<ACCEL, T, IDX, TFL>(ra, blockIdx.x, blockIdx.y);
+}
+
+// Many requests in one launch: blockIdx.z picks the request, whose tiles
+// cover the front of the (max-sized) grid; the rest of its blocks exit.
+template <int ACCEL, typename T, typename IDX, bool TFL>
+__global__ __launch_bounds__(256) void k_render_batch(const RenderArgs *__restrict__ args)
+{
+    const RenderArgs ra = args[blockIdx.z];
+    if ((int)blockIdx.x * 16 >= ra.W || (int)blockIdx.y * 16 >= ra.H) return;  // uniform per block
+    render_tile<ACCEL, T, IDX, TFL>(ra, blockIdx.x, blockIdx.y);
+}
+
+template <int ACCEL, typename T, typename IDX, bool TFL>
+hipError_t launch_batch_inst(const RenderArgs *d_args, const dim3 &grid, size_t lds, hipStream_t s)
+{
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_render_batch<ACCEL, T, IDX, TFL>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_render_batch<ACCEL, T, IDX, TFL>), grid, dim3(256), lds, s, d_args);
+    return hipGetLastError();
+}
+
+template <int ACCEL, typename T>
+hipError_t launch_batch_accel(const RenderArgs *d_args, const dim3 &grid, size_t lds, bool narrow, bool tfl,
+                              hipStream_t s)
+{
+    if (narrow)
+        return tfl ? launch_batch_inst<ACCEL, T, uint32_t, true>(d_args, grid, lds, s)
+                   : launch_batch_inst<ACCEL, T, uint32_t, false>(d_args, grid, lds, s);
+    return tfl ? launch_batch_inst<ACCEL, T, uint64_t, true>(d_args, grid, lds, s)
+               : launch_batch_inst<ACCEL, T, uint64_t, false>(d_args, grid, lds, s);
+}
+
+template <typename T>
+hipError_t launch_batch_typed(int accel, const RenderArgs *d_args, const dim3 &grid, size_t lds, bool narrow,
+                              bool tfl, hipStream_t s)
+{
+    switch (accel) {
+    case ESK_ACCEL_NONE: return launch_batch_accel<ESK_ACCEL_NONE, T>(d_args, grid, lds, narrow, tfl, s);
+    case ESK_ACCEL_GRID: return launch_batch_accel<ESK_ACCEL_GRID, T>(d_args, grid, lds, narrow, tfl, s);
+    case ESK_ACCEL_LBVH: return launch_batch_accel<ESK_ACCEL_LBVH, T>(d_args, grid, lds, narrow, tfl, s);
+    case ESK_ACCEL_KD: return launch_batch_accel<ESK_ACCEL_KD, T>(d_args, grid, lds, narrow, tfl, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 template <int ACCEL, typename T>
 hipError_t launch_accel(const RenderArgs &r, hipStream_t s)
 {
     const dim3 grid((r.W + 15) / 16, (r.H + 15) / 16);
-    const size_t lds = (r.N <= 1024 ? 1024 * sizeof(float4) : 0) +
+    const size_t lds = (r.N <= 1024 ? (size_t)r.N * sizeof(float4) : 0) +
                        (size_t)r.stack_cap * 256 * sizeof(int);
     const int64_t nvox = (int64_t)r.vol.nx * r.vol.ny * r.vol.nz;
     const bool narrow = nvox < (int64_t)0xffffffffLL;
-    const void *fn = narrow ? reinterpret_cast<const void *>(&k_render<ACCEL, T, uint32_t>)
-                            : reinterpret_cast<const void *>(&k_render<ACCEL, T, uint64_t>);
+    const bool tfl = r.N <= 1024;
+    const void *fn;
+    if (narrow)
+        fn = tfl ? reinterpret_cast<const void *>(&k_render<ACCEL, T, uint32_t, true>)
+                 : reinterpret_cast<const void *>(&k_render<ACCEL, T, uint32_t, false>);
+    else
+        fn = tfl ? reinterpret_cast<const void *>(&k_render<ACCEL, T, uint64_t, true>)
+                 : reinterpret_cast<const void *>(&k_render<ACCEL, T, uint64_t, false>);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    if (narrow)
-        hipLaunchKernelGGL((k_render<ACCEL, T, uint32_t>), grid, dim3(256), lds, s, r);
-    else
-        hipLaunchKernelGGL((k_render<ACCEL, T, uint64_t>), grid, dim3(256), lds, s, r);
+    if (narrow) {
+        if (tfl) hipLaunchKernelGGL((k_render<ACCEL, T, uint32_t, true>), grid, dim3(256), lds, s, r);
+        else hipLaunchKernelGGL((k_render<ACCEL, T, uint32_t, false>), grid, dim3(256), lds, s, r);
+    } else {
+        if (tfl) hipLaunchKernelGGL((k_render<ACCEL, T, uint64_t, true>), grid, dim3(256), lds, s, r);
+        else hipLaunchKernelGGL((k_render<ACCEL, T, uint64_t, false>), grid, dim3(256), lds, s, r);
+    }
     return hipGetLastError();
 }
 
@@ -415,6 +508,19 @@ hipError_t launch_typed(int accel, const RenderArgs &r, hipStream_t s)
 }
 
 }  // namespace
+
+hipError_t launch_render_batch(int accel, int dtype, const RenderArgs *d_args, int n, int tiles_x, int tiles_y,
+                               size_t lds, bool narrow, bool tfl, hipStream_t s)
+{
+    const dim3 grid((unsigned)tiles_x, (unsigned)tiles_y, (unsigned)n);
+    switch (dtype) {
+    case ESK_U8: return launch_batch_typed<uint8_t>(accel, d_args, grid, lds, narrow, tfl, s);
+    case ESK_U16: return launch_batch_typed<uint16_t>(accel, d_args, grid, lds, narrow, tfl, s);
+    case ESK_F16: return launch_batch_typed<_Float16>(accel, d_args, grid, lds, narrow, tfl, s);
+    case ESK_F32: return launch_batch_typed<float>(accel, d_args, grid, lds, narrow, tfl, s);
+    }
+    return hipErrorInvalidValue;
+}
 
 hipError_t launch_render(int accel, const RenderArgs &r, hipStream_t s)
 {

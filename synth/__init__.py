@@ -267,3 +267,41 @@ def menger_sponge(level=3, scale=3, value=200):
         solid &= ~holes
     vol = np.repeat(np.repeat(np.repeat(solid, scale, 0), scale, 1), scale, 2)
     return (vol * value).astype(np.uint8)
+
+
+def batch_workload(count=64, seed=4, image=(512, 512), device="cuda"):
+    """Many uneven volumes, each with its own TF and camera: axis sizes drawn
+    from {32, 64, 128, 256, 512} independently (anisotropic), u8 sums of
+    Gaussian blobs with a cut chosen for 1-20 % non-empty voxels.  Volumes
+    are generated on `device` with torch (separable Gaussians) from seeded
+    parameters, so large batches build in seconds."""
+    import torch
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        dims = tuple(int(v) for v in rng.choice([32, 64, 128, 256, 512], size=3))
+        nb = int(rng.integers(3, 12))
+        density = float(rng.uniform(0.01, 0.20))
+        centres = rng.uniform(0.1, 0.9, size=(nb, 3)) * np.array(dims)
+        sig = rng.uniform(0.04, 0.12, size=nb) * min(dims)
+        nx, ny, nz = dims
+        x = torch.arange(nx, device=device, dtype=torch.float32) + 0.5
+        y = torch.arange(ny, device=device, dtype=torch.float32) + 0.5
+        z = torch.arange(nz, device=device, dtype=torch.float32) + 0.5
+        acc = torch.zeros((nz, ny, nx), device=device, dtype=torch.float32)
+        for c, s in zip(centres, sig):
+            gx = torch.exp(-((x - float(c[0])) ** 2) / (2 * s * s))
+            gy = torch.exp(-((y - float(c[1])) ** 2) / (2 * s * s))
+            gz = torch.exp(-((z - float(c[2])) ** 2) / (2 * s * s))
+            acc += gz[:, None, None] * gy[None, :, None] * gx[None, None, :]
+        acc = acc / acc.max()
+        flat = acc.reshape(-1)
+        k = max(1, int(density * flat.numel()))
+        cut = torch.topk(flat, k).values[-1]
+        vol = torch.where(acc >= cut, torch.clamp(acc * 255.0, 1.0, 255.0), torch.zeros_like(acc))
+        vol = vol.to(torch.uint8).contiguous()
+        tf = tf_random(seed * 1000 + i, 256)
+        W, H = image
+        cam = perspective(dims, W, H, view_direction(seed * 1000 + i))
+        out.append(dict(dims=dims, vol=vol, tf=tf, cam=cam, W=W, H=H, density=density))
+    return out
