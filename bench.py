@@ -149,6 +149,82 @@ def batched_vs_plain(esk, torch, count=64, reps=5):
             "images_identical": bool(same)}
 
 
+def serving(esk, torch, n_req=400, rate=200.0, seed=6):
+    """A Poisson stream of TF edits and renders over 16 resident volumes
+    (128^3..1024^3, u8 and f16), images 256^2..1920x1080: continuous
+    batching (paper_1912_09596_amd.serve) against serving one request at a
+    time on arrival, at the stream's rate and with every request queued at
+    t = 0 (saturation)."""
+    import numpy as np
+
+    import synth
+    from paper_1912_09596_amd.serve import Request, Server
+
+    vols = synth.serving_volumes(16)
+    tfs = [torch.from_numpy(synth.tf_random(seed * 100 + i, 256)).cuda() for i in range(32)]
+    srv = Server(hbm_budget_bytes=64 << 30, max_batch=32)
+    for v in vols:
+        srv.add_volume(v["name"], v["vol"], 16 if v["dims"][0] >= 512 else 8, tf=torch.from_numpy(v["tf"]).cuda())
+    sizes = [(256, 256), (512, 512), (1280, 720), (1920, 1080)]
+
+    def make(r, zero=False):
+        rng = np.random.default_rng(seed)
+        reqs, t = [], 0.0
+        for rid in range(n_req):
+            t += rng.exponential(1.0 / r)
+            v = vols[int(rng.integers(0, len(vols)))]
+            at = 0.0 if zero else t
+            if rng.random() < 0.3:
+                reqs.append(Request(rid, v["name"], "rebuild", at, tf=tfs[int(rng.integers(0, len(tfs)))]))
+            else:
+                W, H = sizes[int(rng.integers(0, len(sizes)))]
+                cam = synth.perspective(v["dims"], W, H, synth.view_direction(seed * 1000 + rid))
+                reqs.append(Request(rid, v["name"], "render", at, cam=cam, size=(W, H)))
+        return reqs
+
+    def plain(reqs):
+        outs = {}
+        t0 = time.perf_counter()
+        for r in sorted(reqs, key=lambda q: (q.arrival, q.rid)):
+            while time.perf_counter() - t0 < r.arrival:
+                pass
+            c = srv.contexts[r.volume]
+            if r.kind == "rebuild":
+                c.set_tf(r.tf, build=("lbvh",))
+            else:
+                outs[r.rid] = c.render(r.cam, r.size[0], r.size[1], accel="lbvh")
+            torch.cuda.synchronize()
+            r.done = time.perf_counter() - t0
+        return Server._summary(reqs, time.perf_counter() - t0), outs
+
+    init_tfs = {v["name"]: torch.from_numpy(v["tf"]).cuda() for v in vols}
+
+    def reset():
+        for name, tf in init_tfs.items():
+            srv.contexts[name].set_tf(tf, build=("lbvh",))
+        torch.cuda.synchronize()
+
+    def fmt(st):
+        return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+
+    out = {"volumes": "16 resident cubes 128^3..1024^3, u8 and f16 alternating, blob sums at 1-20% density",
+           "requests": n_req, "mix": "30% TF edits (LBVH rebuild), 70% renders 256^2..1920x1080", "accel": "lbvh"}
+    # warm up both paths once
+    srv.run(make(rate * 10, zero=True)[:32])
+    plain(make(rate * 10, zero=True)[:32])
+    for label, zero in (("poisson_200_per_s", False), ("saturated", True)):
+        reset()
+        reqs = make(rate, zero)
+        st_s = srv.run(reqs)
+        served_out = {r.rid: r.out for r in reqs if r.kind == "render"}
+        reset()
+        reqs_p = make(rate, zero)
+        st_p, plain_out = plain(reqs_p)
+        same = all(torch.equal(served_out[k], plain_out[k]) for k in plain_out)
+        out[label] = {"served": fmt(st_s), "one_at_a_time": fmt(st_p), "results_identical": bool(same)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,6 +232,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one plain 512 MiB device copy first (reference for HBM counters)")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--cpu-stride", type=int, default=1)
     args = ap.parse_args()
@@ -193,6 +271,13 @@ def main():
             ctx.render(cams[j], W, H, accel=a, step=0.5, ref=1.0, out=outs[a])
             if ev is not None:
                 ev[a][1].record(stream)
+
+    if args.copy_probe:
+        src = torch.empty(128 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     log(f"warmup {args.warmup}")
     for i in range(args.warmup):
@@ -291,6 +376,8 @@ def main():
     if not args.no_batch:
         log("batched vs plain")
         result["batched"] = batched_vs_plain(esk, torch)
+        log("serving")
+        result["serving"] = serving(esk, torch)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(vol, tfs, args.cpu_steps, args.cpu_stride)

@@ -112,6 +112,12 @@ struct esk_ctx {
     hipEvent_t staging_done = nullptr;
     int kd_level_hint = 24;     // levels enqueued per rebuild (adapts to the last height)
     int kd_levels_enqueued = 0;
+    // the k-d build runs on an auxiliary stream forked after classification,
+    // so its latency-bound level launches overlap work on the main stream
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_kd = nullptr;
+    DevHeader *pinned_kd = nullptr;   // header snapshot taken at the end of the k-d build
+    bool kd_joined = true;            // main stream already ordered after the last k-d build
 };
 
 namespace {
@@ -178,6 +184,17 @@ esk_status read_header(esk_ctx *c)
     return hip_check(c, e, "reading device header");
 }
 
+// orders the main stream after the last k-d build (before anything that
+// reads its results or rewrites the arrays it reads)
+esk_status join_kd(esk_ctx *c)
+{
+    if (c->kd_joined) return ESK_OK;
+    hipError_t e = hipStreamWaitEvent(c->stream, c->ev_kd, 0);
+    if (e != hipSuccess) return hip_check(c, e, "joining the k-d stream");
+    c->kd_joined = true;
+    return ESK_OK;
+}
+
 }  // namespace
 
 static KdArgs kd_args(esk_ctx *c, const esk_kd_params *p);
@@ -188,7 +205,11 @@ static KdArgs kd_args(esk_ctx *c, const esk_kd_params *p);
 static esk_status kd_finish(esk_ctx *c)
 {
     if (!c->kd_on_device) return ESK_OK;
-    esk_status st = read_header(c);
+    // wait for the k-d stream only: work queued on the main stream keeps running
+    hipError_t e0 = hipEventSynchronize(c->ev_kd);
+    if (e0 != hipSuccess) return hip_check(c, e0, "waiting for the k-d build");
+    std::memcpy(c->pinned, c->pinned_kd, sizeof(DevHeader));
+    esk_status st = join_kd(c);
     if (st != ESK_OK) return st;
     KdArgs k = kd_args(c, &c->kd_params);
     while (c->pinned->kd_end > c->pinned->kd_begin) {
@@ -245,11 +266,16 @@ esk_status esk_create(int device, void *hip_stream, esk_ctx **out)
         }
         e = hipSetDevice(device);
         if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&c->pinned), sizeof(DevHeader));
+        if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&c->pinned_kd), sizeof(DevHeader));
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);  // default priority
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_kd, hipEventDisableTiming);
         if (e != hipSuccess) {
-            delete c;
+            esk_destroy(c);
             return ESK_EDEVICE;
         }
         std::memset(c->pinned, 0, sizeof(DevHeader));
+        std::memset(c->pinned_kd, 0, sizeof(DevHeader));
     }
     *out = c;
     return ESK_OK;
@@ -265,6 +291,11 @@ esk_status esk_destroy(esk_ctx *c)
         if (c->staging_done) (void)hipEventSynchronize(c->staging_done);
         if (c->staging) (void)hipHostFree(c->staging);
         if (c->staging_done) (void)hipEventDestroy(c->staging_done);
+        if (c->aux) (void)hipStreamSynchronize(c->aux);
+        if (c->aux) (void)hipStreamDestroy(c->aux);
+        if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+        if (c->ev_kd) (void)hipEventDestroy(c->ev_kd);
+        if (c->pinned_kd) (void)hipHostFree(c->pinned_kd);
     }
     delete c;
     return ESK_OK;
@@ -301,6 +332,8 @@ esk_status esk_set_volume(esk_ctx *c, const void *d_vox, int dtype, int nx, int 
     if (c->device < 0) return fail(c, ESK_ESTATE, "validation-only context");
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_check(c, e, "hipSetDevice");
+    s = join_kd(c);
+    if (s != ESK_OK) return s;
     c->has_volume = false;
     c->has_tf = false;
     c->built = 0;
@@ -418,6 +451,8 @@ esk_status esk_set_transfer_function(esk_ctx *c, const float *d_rgba, int n_entr
         return fail(c, ESK_ELIMIT, "TF has %d entries, workspace sized for %d", n_entries, c->max_tf);
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_check(c, e, "hipSetDevice");
+    esk_status js = join_kd(c);
+    if (js != ESK_OK) return js;
     c->has_tf = false;
     c->built = 0;
     c->kd_on_device = false;
@@ -436,19 +471,30 @@ esk_status esk_set_transfer_function(esk_ctx *c, const float *d_rgba, int n_entr
     if (build_mask & ESK_ACCEL_KD) {
         KdArgs k = kd_args(c, kd);
         c->kd_params = *kd;
-        if (kd_small(k)) {
-            e = launch_kd_prefix_root_small(k, c->stream);
-        } else {
-            e = launch_kd_prefix(k, c->stream);
-            if (e == hipSuccess) e = launch_kd_root(k, c->stream);
+        // fork: the k-d build needs the flags only; it runs on the auxiliary
+        // stream while the main stream goes on (LBVH, grid/LBVH renders)
+        e = hipEventRecord(c->ev_fork, c->stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(c->aux, c->ev_fork, 0);
+        if (e == hipSuccess) {
+            if (kd_small(k)) {
+                e = launch_kd_prefix_root_small(k, c->aux);
+            } else {
+                e = launch_kd_prefix(k, c->aux);
+                if (e == hipSuccess) e = launch_kd_root(k, c->aux);
+            }
         }
         // levels are enqueued speculatively (a launch past the last level
         // exits at once); completion is checked when the tree is first used
-        if (e == hipSuccess) e = launch_kd_levels(k, c->kd_level_hint, c->stream);
-        if (e == hipSuccess) e = launch_kd_pack(k, 2 * L.nb, c->stream);
+        if (e == hipSuccess) e = launch_kd_levels(k, c->kd_level_hint, c->aux);
+        if (e == hipSuccess) e = launch_kd_pack(k, 2 * L.nb, c->aux);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->pinned_kd, at<DevHeader>(c, L.header), sizeof(DevHeader), hipMemcpyDeviceToHost,
+                               c->aux);
+        if (e == hipSuccess) e = hipEventRecord(c->ev_kd, c->aux);
         if (e != hipSuccess) return hip_check(c, e, "k-d launch");
         c->kd_levels_enqueued = c->kd_level_hint;
         c->kd_on_device = true;
+        c->kd_joined = false;
     }
     c->built = build_mask;
     c->has_tf = true;
@@ -613,6 +659,7 @@ esk_status esk_sync(esk_ctx *c)
     if (c->device < 0) return fail(c, ESK_ESTATE, "validation-only context");
     hipError_t e = hipSetDevice(c->device);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess && c->aux) e = hipStreamSynchronize(c->aux);
     return hip_check(c, e, "stream synchronize");
 }
 

@@ -307,8 +307,13 @@ __global__ __launch_bounds__(1024) void k_kd_prefix_root_small(KdArgs k)
 // breadth-first order and publishes the next level.
 constexpr int kKdLevelBlocks = 128;
 
+// LDS_S: the grid is small enough (<= 32768 bricks) for every block that has
+// nodes to stage the whole prefix count in LDS first, so the binary searches
+// read LDS instead of L2
+template <bool LDS_S>
 __global__ __launch_bounds__(256) void k_kd_level(KdArgs k)
 {
+    extern __shared__ int32_t Sl[];
     __shared__ int16_t tb[4][kMaxCand + 1][2][6];
     __shared__ uint32_t scratch[5];
     __shared__ uint32_t last;
@@ -316,9 +321,23 @@ __global__ __launch_bounds__(256) void k_kd_level(KdArgs k)
     if (begin == end) return;
     const int wave = threadIdx.x >> 6;
     const int64_t vroot = root_volume(k);
+    const bool busy = (int64_t)begin + (int64_t)blockIdx.x * 4 < (int64_t)end;  // uniform per block
+    if (LDS_S && busy) {
+        const int nb = k.nb[0] * k.nb[1] * k.nb[2];
+        const int n4 = nb >> 2;
+        const int4 *src = reinterpret_cast<const int4 *>(k.S);
+        int4 *dst = reinterpret_cast<int4 *>(Sl);
+        for (int i = threadIdx.x; i < n4; i += 256) dst[i] = src[i];
+        for (int i = 4 * n4 + threadIdx.x; i < nb; i += 256) Sl[i] = k.S[i];
+        __syncthreads();
+    }
     for (int64_t node = (int64_t)begin + (int64_t)blockIdx.x * 4 + wave; node < end;
-         node += (int64_t)gridDim.x * 4)
-        eval_node(k, (const int32_t *)k.S, node, vroot, tb[wave]);
+         node += (int64_t)gridDim.x * 4) {
+        if (LDS_S)
+            eval_node(k, (const int32_t *)Sl, node, vroot, tb[wave]);
+        else
+            eval_node(k, (const int32_t *)k.S, node, vroot, tb[wave]);
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
@@ -434,8 +453,17 @@ hipError_t launch_kd_prefix_root_small(const KdArgs &k, hipStream_t s)
 
 hipError_t launch_kd_levels(const KdArgs &k, int count, hipStream_t s)
 {
-    for (int i = 0; i < count; ++i)
-        hipLaunchKernelGGL(k_kd_level, dim3(kKdLevelBlocks), dim3(256), 0, s, k);
+    if (kd_small(k)) {
+        const size_t lds = sizeof(int32_t) * (size_t)k.nb[0] * k.nb[1] * k.nb[2];
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_kd_level<true>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        for (int i = 0; i < count; ++i)
+            hipLaunchKernelGGL(k_kd_level<true>, dim3(kKdLevelBlocks), dim3(256), lds, s, k);
+    } else {
+        for (int i = 0; i < count; ++i)
+            hipLaunchKernelGGL(k_kd_level<false>, dim3(kKdLevelBlocks), dim3(256), 0, s, k);
+    }
     return hipGetLastError();
 }
 

@@ -269,6 +269,49 @@ def menger_sponge(level=3, scale=3, value=200):
     return (vol * value).astype(np.uint8)
 
 
+def _blob_volume_torch(dims, nb, density, rng, device, dtype="u8"):
+    import torch
+    nx, ny, nz = dims
+    centres = rng.uniform(0.1, 0.9, size=(nb, 3)) * np.array(dims)
+    sig = rng.uniform(0.04, 0.12, size=nb) * min(dims)
+    x = torch.arange(nx, device=device, dtype=torch.float32) + 0.5
+    y = torch.arange(ny, device=device, dtype=torch.float32) + 0.5
+    z = torch.arange(nz, device=device, dtype=torch.float32) + 0.5
+    acc = torch.zeros((nz, ny, nx), device=device, dtype=torch.float32)
+    for c, s in zip(centres, sig):
+        gx = torch.exp(-((x - float(c[0])) ** 2) / (2 * s * s))
+        gy = torch.exp(-((y - float(c[1])) ** 2) / (2 * s * s))
+        gz = torch.exp(-((z - float(c[2])) ** 2) / (2 * s * s))
+        acc += gz[:, None, None] * gy[None, :, None] * gx[None, None, :]
+    acc = acc / acc.max()
+    flat = acc.reshape(-1)
+    k = max(1, int(density * flat.numel()))
+    # the k-th largest value, without sorting a billion voxels
+    sample = flat[torch.randint(0, flat.numel(), (1 << 20,), device=device,
+                                generator=torch.Generator(device=device).manual_seed(int(rng.integers(1 << 30))))]
+    cut = torch.quantile(sample, 1.0 - density)
+    if dtype == "f16":
+        vol = torch.where(acc >= cut, acc, torch.zeros_like(acc)).to(torch.float16)
+    else:
+        vol = torch.where(acc >= cut, torch.clamp(acc * 255.0, 1.0, 255.0), torch.zeros_like(acc)).to(torch.uint8)
+    del acc
+    return vol.contiguous()
+
+
+def serving_volumes(count=16, seed=5, sizes=(128, 256, 512, 1024), device="cuda"):
+    """Resident volumes for the serving workload: cubes of the given edge
+    sizes, alternating u8 and f16 storage, blob sums at 1-20 % density."""
+    rng = np.random.default_rng(seed)
+    vols = []
+    for i in range(count):
+        n = int(sizes[i % len(sizes)])
+        dt = "u8" if i % 2 == 0 else "f16"
+        vol = _blob_volume_torch((n, n, n), int(rng.integers(3, 12)), float(rng.uniform(0.01, 0.2)), rng,
+                                 device, dt)
+        vols.append(dict(name=f"vol{i}", dims=(n, n, n), vol=vol, dtype=dt, tf=tf_random(seed * 1000 + i, 256)))
+    return vols
+
+
 def batch_workload(count=64, seed=4, image=(512, 512), device="cuda"):
     """Many uneven volumes, each with its own TF and camera: axis sizes drawn
     from {32, 64, 128, 256, 512} independently (anisotropic), u8 sums of
