@@ -28,11 +28,14 @@ int elem_size(int dtype)
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-Layout make_layout(int nbx, int nby, int nbz, int elem_bytes, int max_tf)
+Layout make_layout(int nx, int ny, int nz, int brick, int elem_bytes, int max_tf)
 {
     Layout L;
     std::memset(&L, 0, sizeof(L));
+    const int nbx = (nx + brick - 1) / brick, nby = (ny + brick - 1) / brick, nbz = (nz + brick - 1) / brick;
     const int64_t nb = (int64_t)nbx * nby * nbz;
+    const int64_t nswz = (int64_t)((nx + kSwzEdge - 1) / kSwzEdge) * ((ny + kSwzEdge - 1) / kSwzEdge) *
+                         ((nz + kSwzEdge - 1) / kSwzEdge) * kSwzEdge * kSwzEdge * kSwzEdge;
     L.nb = nb;
     L.nblk = (nb + kClassifyBlock - 1) / kClassifyBlock;
     L.nsortblk = (nb + kSortBlockKeys - 1) / kSortBlockKeys;
@@ -44,6 +47,7 @@ Layout make_layout(int nbx, int nby, int nbz, int elem_bytes, int max_tf)
     };
     const size_t n4 = (size_t)nb * 4;
     L.header = take(sizeof(DevHeader));
+    L.swz = take((size_t)nswz * elem_bytes);
     L.minv = take((size_t)nb * elem_bytes);
     L.maxv = take((size_t)nb * elem_bytes);
     L.tf = take((size_t)max_tf * 16);
@@ -307,7 +311,7 @@ esk_status esk_workspace_bytes(int nx, int ny, int nz, int dtype, int brick, int
     esk_status s = check_shape(nullptr, nx, ny, nz, dtype, brick, max_tf_entries);
     if (s != ESK_OK) return s;
     const int nbx = (nx + brick - 1) / brick, nby = (ny + brick - 1) / brick, nbz = (nz + brick - 1) / brick;
-    *out = make_layout(nbx, nby, nbz, elem_size(dtype), max_tf_entries).total;
+    *out = make_layout(nx, ny, nz, brick, elem_size(dtype), max_tf_entries).total;
     return ESK_OK;
 }
 
@@ -326,7 +330,7 @@ esk_status esk_set_volume(esk_ctx *c, const void *d_vox, int dtype, int nx, int 
         !(std::isfinite(value_lo) && std::isfinite(value_hi) && value_lo < value_hi))
         return fail(c, ESK_EINVAL, "value range must be finite with lo < hi");
     const int nbx = (nx + brick - 1) / brick, nby = (ny + brick - 1) / brick, nbz = (nz + brick - 1) / brick;
-    Layout L = make_layout(nbx, nby, nbz, elem_size(dtype), max_tf_entries);
+    Layout L = make_layout(nx, ny, nz, brick, elem_size(dtype), max_tf_entries);
     if (ws_bytes < L.total)
         return fail(c, ESK_ENOSPC, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
     if (c->device < 0) return fail(c, ESK_ESTATE, "validation-only context");
@@ -354,7 +358,12 @@ esk_status esk_set_volume(esk_ctx *c, const void *d_vox, int dtype, int nx, int 
     c->ws_bytes = ws_bytes;
     c->L = L;
     e = hipMemsetAsync(c->ws + L.header, 0, sizeof(DevHeader), c->stream);
+    c->vol.swz = c->ws + L.swz;
+    c->vol.nq[0] = (nx + kSwzEdge - 1) / kSwzEdge;
+    c->vol.nq[1] = (ny + kSwzEdge - 1) / kSwzEdge;
+    c->vol.nq[2] = (nz + kSwzEdge - 1) / kSwzEdge;
     if (e == hipSuccess) e = launch_minmax(c->vol, c->ws + L.minv, c->ws + L.maxv, c->stream);
+    if (e == hipSuccess) e = launch_swizzle(c->vol, c->ws + L.swz, c->stream);
     if (e != hipSuccess) return hip_check(c, e, "set_volume launch");
     c->has_volume = true;
     return ESK_OK;
@@ -633,8 +642,8 @@ esk_status esk_render_batch(esk_ctx *const *ctxs, int n, int accel, const esk_ca
             if (ctxs[i] != c0) fail(c0, st, "request %d: %s", i, ctxs[i]->err.c_str());
             return st;
         }
-        const int64_t nvox = (int64_t)r.vol.nx * r.vol.ny * r.vol.nz;
-        narrow = narrow && nvox < (int64_t)0xffffffffLL;
+        const int64_t nbytes = (int64_t)r.vol.nq[0] * r.vol.nq[1] * r.vol.nq[2] * 512 * elem_size(r.vol.dtype);
+        narrow = narrow && nbytes < (int64_t)0xffffffffLL;
         tfl = tfl && r.N <= 1024;
         tx = std::max(tx, (r.W + 15) / 16);
         ty = std::max(ty, (r.H + 15) / 16);

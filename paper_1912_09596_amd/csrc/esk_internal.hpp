@@ -45,24 +45,33 @@ struct Layout {
     int64_t nb;            // bricks
     int64_t nblk;          // classification blocks
     int64_t nsortblk;      // multi-block sort blocks
-    size_t header, minv, maxv, tf, tfP, flags, grid, blkcnt;
+    size_t header, swz, minv, maxv, tf, tfP, flags, grid, blkcnt;
     size_t ids, keys, skeys, tmpkeys, sids, hist;
     size_t lb_left, lb_right, lb_axis, lb_parent, lb_lo, lb_hi, lb_range, lb_rnode, lb_leafbox;
     size_t kd_S, kd_lo, kd_hi, kd_axis, kd_plane, kd_first, kd_split, kd_clo, kd_rnode, kd_box;
     size_t total;
 };
 
-Layout make_layout(int nbx, int nby, int nbz, int elem_bytes, int max_tf);
+Layout make_layout(int nx, int ny, int nz, int brick, int elem_bytes, int max_tf);
 
 int elem_size(int dtype);
 
 // ---- launchers (each enqueues on `s`; returns hipSuccess or the launch error)
+// The renderer samples a copy of the volume stored in 8^3-voxel blocks
+// (512 voxels contiguous, x fastest inside a block, blocks x-fastest), made
+// at esk_set_volume: the 2x2x2 footprints of the 64 rays of a wave then fall
+// into a few blocks instead of dozens of voxel rows.
+constexpr int kSwzEdge = 8;
+
 struct VolumeDesc {
     const void *vox;
     int dtype, nx, ny, nz, B, log2B, nb[3];
+    const void *swz;       // blocked copy in the workspace
+    int nq[3];             // blocks per axis (ceil(n / 8))
 };
 
 hipError_t launch_minmax(const VolumeDesc &v, void *minv, void *maxv, hipStream_t s);
+hipError_t launch_swizzle(const VolumeDesc &v, void *swz, hipStream_t s);
 
 struct RebuildArgs {
     VolumeDesc vol;

@@ -327,7 +327,21 @@ __global__ __launch_bounds__(256) void k_kd_level(KdArgs k)
         const int n4 = nb >> 2;
         const int4 *src = reinterpret_cast<const int4 *>(k.S);
         int4 *dst = reinterpret_cast<int4 *>(Sl);
-        for (int i = threadIdx.x; i < n4; i += 256) dst[i] = src[i];
+        // eight 16-byte loads in flight per thread before the LDS writes
+        constexpr int U = 8;
+        for (int i0 = threadIdx.x; i0 < n4; i0 += 256 * U) {
+            int4 buf[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * 256;
+                buf[u] = i < n4 ? src[i] : make_int4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * 256;
+                if (i < n4) dst[i] = buf[u];
+            }
+        }
         for (int i = 4 * n4 + threadIdx.x; i < nb; i += 256) Sl[i] = k.S[i];
         __syncthreads();
     }

@@ -248,7 +248,50 @@ hipError_t launch_typed(const VolumeDesc &v, void *minv, void *maxv, hipStream_t
     return hipGetLastError();
 }
 
+// Blocked copy for the renderer: one workgroup per row of 8^3 blocks
+// (fixed qy, qz); threads stream voxel rows of the 8 x 8 slab coalesced and
+// write each voxel to its block.  Padding voxels (past the volume) are zero
+// and never sampled (the sampler clamps indices to the volume).
+template <typename T>
+__global__ __launch_bounds__(256) void k_swizzle(const T *__restrict__ vol, int nx, int ny, int nz, int nqx,
+                                                 int nqy, T *__restrict__ swz)
+{
+    const int qy = blockIdx.x % nqy, qz = blockIdx.x / nqy;
+    const int px = nqx * 8;
+    const size_t row_blocks = ((size_t)qz * nqy + qy) * nqx;
+    for (int r = 0; r < 64; ++r) {
+        const int zl = r >> 3, yl = r & 7;
+        const int y = qy * 8 + yl, z = qz * 8 + zl;
+        const bool in = (y < ny) && (z < nz);
+        const T *src = vol + ((size_t)z * ny + y) * (size_t)nx;
+        for (int x = threadIdx.x; x < px; x += 256) {
+            const T val = (in && x < nx) ? src[x] : (T)0;
+            swz[(row_blocks + (size_t)(x >> 3)) * 512 + zl * 64 + yl * 8 + (x & 7)] = val;
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_swz_typed(const VolumeDesc &v, void *swz, hipStream_t s)
+{
+    const int64_t blocks = (int64_t)v.nq[1] * v.nq[2];
+    hipLaunchKernelGGL((k_swizzle<T>), dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const T *>(v.vox), v.nx,
+                       v.ny, v.nz, v.nq[0], v.nq[1], static_cast<T *>(swz));
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_swizzle(const VolumeDesc &v, void *swz, hipStream_t s)
+{
+    switch (v.dtype) {
+    case ESK_U8: return launch_swz_typed<uint8_t>(v, swz, s);
+    case ESK_U16: return launch_swz_typed<uint16_t>(v, swz, s);
+    case ESK_F16: return launch_swz_typed<_Float16>(v, swz, s);
+    case ESK_F32: return launch_swz_typed<float>(v, swz, s);
+    }
+    return hipErrorInvalidValue;
+}
 
 hipError_t launch_minmax(const VolumeDesc &v, void *minv, void *maxv, hipStream_t s)
 {

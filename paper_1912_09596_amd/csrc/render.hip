@@ -115,23 +115,39 @@ struct Accum {
     int n;
 };
 
+struct Vol {
+    int n[3];
+    float fn[3];
+    uint32_t sy, sz;   // elements between block rows / block slabs of the blocked copy
+};
+
+// cell-centred trilinear interpolation (clamp to edge) from the blocked copy:
+// element (x, y, z) sits at (z>>3)*sz + (z&7)*64 + (y>>3)*sy + (y&7)*8 + (x>>3)*512 + (x&7)
 template <typename T, typename IDX>
-__device__ inline float trilinear(const T *__restrict__ vol, int nx, int ny, int nz, const float p[3])
+__device__ inline float trilinear(const T *__restrict__ vol, const Vol &v, const float p[3])
 {
     const float ux = p[0] - 0.5f, uy = p[1] - 0.5f, uz = p[2] - 0.5f;
     const float fx = floorf(ux), fy = floorf(uy), fz = floorf(uz);
     const float wx = ux - fx, wy = uy - fy, wz = uz - fz;
     const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
-    const int x0 = min(max(ix, 0), nx - 1), x1 = min(max(ix + 1, 0), nx - 1);
-    const int y0 = min(max(iy, 0), ny - 1), y1 = min(max(iy + 1, 0), ny - 1);
-    const int z0 = min(max(iz, 0), nz - 1), z1 = min(max(iz + 1, 0), nz - 1);
-    const IDX sy = (IDX)nx, sz = (IDX)nx * (IDX)ny;
-    const IDX r00 = (IDX)z0 * sz + (IDX)y0 * sy, r10 = (IDX)z0 * sz + (IDX)y1 * sy;
-    const IDX r01 = (IDX)z1 * sz + (IDX)y0 * sy, r11 = (IDX)z1 * sz + (IDX)y1 * sy;
-    const float v000 = (float)vol[r00 + x0], v100 = (float)vol[r00 + x1];
-    const float v010 = (float)vol[r10 + x0], v110 = (float)vol[r10 + x1];
-    const float v001 = (float)vol[r01 + x0], v101 = (float)vol[r01 + x1];
-    const float v011 = (float)vol[r11 + x0], v111 = (float)vol[r11 + x1];
+    const int x0 = min(max(ix, 0), v.n[0] - 1), x1 = min(max(ix + 1, 0), v.n[0] - 1);
+    const int y0 = min(max(iy, 0), v.n[1] - 1), y1 = min(max(iy + 1, 0), v.n[1] - 1);
+    const int z0 = min(max(iz, 0), v.n[2] - 1), z1 = min(max(iz + 1, 0), v.n[2] - 1);
+    // IDX = uint32_t: the copy is < 4 GiB, so byte offsets are 32-bit and every
+    // load is a scalar base plus one 32-bit vector offset
+    constexpr IDX E = (IDX)sizeof(T);
+    auto ox = [&](int x) { return ((IDX)(x >> 3) * 512 + (IDX)(x & 7)) * E; };
+    auto oy = [&](int y) { return ((IDX)(y >> 3) * v.sy + (IDX)(y & 7) * 8) * E; };
+    auto oz = [&](int z) { return ((IDX)(z >> 3) * v.sz + (IDX)(z & 7) * 64) * E; };
+    const IDX bx0 = ox(x0), bx1 = ox(x1);
+    const IDX r00 = oz(z0) + oy(y0), r10 = oz(z0) + oy(y1);
+    const IDX r01 = oz(z1) + oy(y0), r11 = oz(z1) + oy(y1);
+    const char *__restrict__ base = reinterpret_cast<const char *>(vol);
+    auto ld = [&](IDX off) { return (float)*reinterpret_cast<const T *>(base + off); };
+    const float v000 = ld(r00 + bx0), v100 = ld(r00 + bx1);
+    const float v010 = ld(r10 + bx0), v110 = ld(r10 + bx1);
+    const float v001 = ld(r01 + bx0), v101 = ld(r01 + bx1);
+    const float v011 = ld(r11 + bx0), v111 = ld(r11 + bx1);
     const float c00 = fmaf(wx, v100 - v000, v000), c10 = fmaf(wx, v110 - v010, v010);
     const float c01 = fmaf(wx, v101 - v001, v001), c11 = fmaf(wx, v111 - v011, v011);
     const float c0 = fmaf(wy, c10 - c00, c00), c1 = fmaf(wy, c11 - c01, c01);
@@ -170,11 +186,6 @@ __device__ inline void composite(const Shade &s, float v, Accum &acc)
     acc.a = acc.a + w;
     acc.n += 1;
 }
-
-struct Vol {
-    int n[3];
-    float fn[3];
-};
 
 __device__ inline bool inside(const Vol &v, const float p[3])
 {
@@ -225,7 +236,7 @@ __device__ inline void march_leaf(const Ray &r, float dt, const int lo[3], const
         point_at(r, t, p);
         if ((p[0] >= bl[0]) & (p[0] < bh[0]) & (p[1] >= bl[1]) & (p[1] < bh[1]) & (p[2] >= bl[2]) &
             (p[2] < bh[2]))
-            composite(s, trilinear<T, IDX>(vol, v.n[0], v.n[1], v.n[2], p), acc);
+            composite(s, trilinear<T, IDX>(vol, v, p), acc);
     }
 }
 
@@ -319,10 +330,12 @@ __device__ inline void render_tile(const RenderArgs &ra, int tbx, int tby)
     const int py = tby * 16 + (wave >> 1) * 8 + (lane >> 3);
     if (px >= ra.W || py >= ra.H) return;
 
-    const T *__restrict__ vol = static_cast<const T *>(ra.vol.vox);
+    const T *__restrict__ vol = static_cast<const T *>(ra.vol.swz);
     Vol v;
     v.n[0] = ra.vol.nx; v.n[1] = ra.vol.ny; v.n[2] = ra.vol.nz;
     for (int a = 0; a < 3; ++a) v.fn[a] = (float)v.n[a];
+    v.sy = 512u * (uint32_t)ra.vol.nq[0];
+    v.sz = 512u * (uint32_t)ra.vol.nq[0] * (uint32_t)ra.vol.nq[1];
     Shade s;
     s.tf = tf_lds ? lds : reinterpret_cast<const float4 *>(ra.tf);
     s.N = ra.N;
@@ -346,7 +359,7 @@ __device__ inline void render_tile(const RenderArgs &ra, int tbx, int tby)
                 if (!(t < r.tx)) break;
                 float p[3];
                 point_at(r, t, p);
-                if (inside(v, p)) composite(s, trilinear<T, IDX>(vol, v.n[0], v.n[1], v.n[2], p), acc);
+                if (inside(v, p)) composite(s, trilinear<T, IDX>(vol, v, p), acc);
             }
         } else if (ACCEL == ESK_ACCEL_GRID) {
             const int sh = ra.vol.log2B, B = ra.vol.B;
@@ -361,7 +374,7 @@ __device__ inline void render_tile(const RenderArgs &ra, int tbx, int tby)
                 const int bx = (int)p[0] >> sh, by = (int)p[1] >> sh, bz = (int)p[2] >> sh;
                 const int64_t b = (int64_t)bx + (int64_t)nbx * ((int64_t)by + (int64_t)nby * bz);
                 if ((ra.grid[b >> 5] >> (b & 31)) & 1u) {
-                    composite(s, trilinear<T, IDX>(vol, v.n[0], v.n[1], v.n[2], p), acc);
+                    composite(s, trilinear<T, IDX>(vol, v, p), acc);
                     ++k;
                     continue;
                 }
@@ -416,6 +429,9 @@ __device__ inline void render_tile(const RenderArgs &ra, int tbx, int tby)
 template <int ACCEL, typename T, typename IDX, bool TFL>
 __global__ __launch_bounds__(256) void k_render(RenderArgs ra)
 {
+    // plain row-major tiles: the round-robin spread over the XCDs balances
+    // the very uneven per-tile work (giving each XCD a band of tiles was
+    // measured 1.5-2x slower)
     render_tile<ACCEL, T, IDX, TFL>(ra, blockIdx.x, blockIdx.y);
 }
 
@@ -471,8 +487,8 @@ hipError_t launch_accel(const RenderArgs &r, hipStream_t s)
     const dim3 grid((r.W + 15) / 16, (r.H + 15) / 16);
     const size_t lds = (r.N <= 1024 ? (size_t)r.N * sizeof(float4) : 0) +
                        (size_t)r.stack_cap * 256 * sizeof(int);
-    const int64_t nvox = (int64_t)r.vol.nx * r.vol.ny * r.vol.nz;
-    const bool narrow = nvox < (int64_t)0xffffffffLL;
+    const int64_t nbytes = (int64_t)r.vol.nq[0] * r.vol.nq[1] * r.vol.nq[2] * 512 * (int64_t)sizeof(T);
+    const bool narrow = nbytes < (int64_t)0xffffffffLL;
     const bool tfl = r.N <= 1024;
     const void *fn;
     if (narrow)
