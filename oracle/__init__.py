@@ -66,6 +66,8 @@ def lib():
         _lib.orc_tf_prefix.argtypes = [P, i32, P]
         _lib.orc_classify.argtypes = [P, P, i64, i32, f32, f32, P, i32, P]
         _lib.orc_classify.restype = i64
+        _lib.orc_vote.argtypes = [P, i32, i32, i32, i32, i32, f32, f32, P, i32, P]
+        _lib.orc_vote.restype = i64
         _lib.orc_compact.argtypes = [P, i64, P]
         _lib.orc_compact.restype = i64
         _lib.orc_morton3.argtypes = [ctypes.c_uint32] * 3
@@ -132,6 +134,20 @@ def classify(mn, mx, dtype, tf, lo=0.0, hi=1.0) -> np.ndarray:
     r = lib().orc_classify(_p(mn), _p(mx), mn.shape[0], code, lo, hi, _p(tf), tf.shape[0], _p(flags))
     if r < 0:
         raise ValueError("orc_classify failed")
+    return flags
+
+
+def vote(vol, B, tf, lo=0.0, hi=1.0) -> np.ndarray:
+    """a3 variant: per-voxel vote flags (a brick's own voxels, TF lookup in FP32)."""
+    vol = np.ascontiguousarray(vol)
+    tf = np.ascontiguousarray(tf, dtype=np.float32)
+    nz, ny, nx = vol.shape
+    nb = int(np.prod(brick_grid((nx, ny, nz), B)))
+    flags = np.empty(nb, np.uint8)
+    code = DTYPE_CODE[vol.dtype]
+    r = lib().orc_vote(_p(vol), code, nx, ny, nz, B, lo, hi, _p(tf), tf.shape[0], _p(flags))
+    if r < 0:
+        raise ValueError("orc_vote failed")
     return flags
 
 

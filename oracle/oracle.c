@@ -159,6 +159,49 @@ int64_t orc_classify(const double *mn, const double *mx, int64_t nb, int dtype, 
     return count;
 }
 
+/* ------------------------------------------------------------------------ */
+/* a3 variant: the per-voxel vote of Sec. 3.1.  A brick is non-empty iff one */
+/* of its own voxels (no apron) is visible: alpha > 0 under the renderer's   */
+/* TF lookup.  The lookup decides an integer flag, so it is taken in the     */
+/* device's precision, FP32: s = (v - lo) * scale with scale = 1/255 (u8),   */
+/* 1/65535 (u16) or 1/(hi - lo) (f16, f32), x = clamp(s, 0, 1) * (N - 1),    */
+/* i0 = min(trunc(x), N - 2), alpha = fmaf(x - i0, a[i0+1] - a[i0], a[i0]).  */
+/* ------------------------------------------------------------------------ */
+int64_t orc_vote(const void *vol, int dtype, int nx, int ny, int nz, int B, float lo, float hi,
+                 const float *tf, int N, uint8_t *flags)
+{
+    if (!vol || !tf || !flags || N < 2 || B < 1) return -1;
+    float nlo = 0.0f, nscale;
+    if (dtype == ORC_U8)
+        nscale = 1.0f / 255.0f;
+    else if (dtype == ORC_U16)
+        nscale = 1.0f / 65535.0f;
+    else {
+        nlo = lo;
+        nscale = 1.0f / (hi - lo);
+    }
+    const int64_t nbx = ceil_div(nx, B), nby = ceil_div(ny, B), nbz = ceil_div(nz, B);
+    memset(flags, 0, (size_t)(nbx * nby * nbz));
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const int64_t b = x / B + nbx * (y / B + nby * (int64_t)(z / B));
+                if (flags[b]) continue;
+                const float v = (float)voxel(vol, dtype, (size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * z));
+                float t = (v - nlo) * nscale;
+                t = t < 0.0f ? 0.0f : (t > 1.0f ? 1.0f : t);
+                t = t * (float)(N - 1);
+                int i0 = (int)t;
+                if (i0 > N - 2) i0 = N - 2;
+                const float f = t - (float)i0;
+                const float a0 = tf[4 * i0 + 3], a1 = tf[4 * (i0 + 1) + 3];
+                if (fmaf(f, a1 - a0, a0) > 0.0f) flags[b] = 1;
+            }
+    int64_t count = 0;
+    for (int64_t b = 0; b < nbx * nby * nbz; ++b) count += flags[b];
+    return count;
+}
+
 /* a4: compaction -- ids of the non-empty bricks in ascending linear id (Sec. 3.1). */
 int64_t orc_compact(const uint8_t *flags, int64_t nb, uint32_t *ids)
 {

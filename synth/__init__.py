@@ -298,6 +298,65 @@ def _blob_volume_torch(dims, nb, density, rng, device, dtype="u8"):
     return vol.contiguous()
 
 
+def tubes_torch(dims_xyz, fraction=0.02, seed=3, radius=(2.0, 6.0), n_ctrl=6, spacing=0.75, device="cuda",
+                chunk=2048):
+    """The tubes() recipe for large volumes, generated on `device` with torch:
+    Catmull-Rom curves through random control points, value 1 on the axis
+    falling linearly to 0 at the tube radius (max over overlapping tubes).
+    Curve points are spaced at most `spacing` voxels apart so tubes stay
+    continuous at any size; tubes are added until their estimated volume
+    reaches `fraction` of the voxels.  Returns a float32 [nz, ny, nx] tensor."""
+    import torch
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = dims_xyz
+    dims = np.array([nx, ny, nz], np.float64)
+    target = fraction * float(nx) * ny * nz
+    pts, rad = [], []
+    filled = 0.0
+    while filled < target:
+        ctrl = rng.uniform(0.1, 0.9, size=(n_ctrl, 3)) * dims
+        r = float(rng.uniform(radius[0], radius[1]))
+        for j in range(1, n_ctrl - 2):
+            p0, p1, p2, p3 = ctrl[j - 1], ctrl[j], ctrl[j + 1], ctrl[j + 2]
+            fine = np.linspace(0.0, 1.0, 65)[:, None]
+            def curve(t):
+                t2, t3 = t * t, t * t * t
+                return 0.5 * ((2 * p1) + (-p0 + p2) * t + (2 * p0 - 5 * p1 + 4 * p2 - p3) * t2
+                              + (-p0 + 3 * p1 - 3 * p2 + p3) * t3)
+            length = float(np.linalg.norm(np.diff(curve(fine), axis=0), axis=1).sum())
+            n = max(2, int(np.ceil(length / spacing)))
+            seg = curve(np.linspace(0.0, 1.0, n, endpoint=False)[:, None])
+            pts.append(seg)
+            rad.append(np.full(n, r))
+            filled += np.pi * r * r * length           # non-zero voxels of the tube, overlaps ignored
+    P = torch.from_numpy(np.concatenate(pts)).to(device=device, dtype=torch.float32)
+    Rr = torch.from_numpy(np.concatenate(rad)).to(device=device, dtype=torch.float32)
+    K = int(np.ceil(radius[1])) * 2 + 3
+    off = torch.arange(K, device=device, dtype=torch.int64) - K // 2
+    oz, oy, ox = torch.meshgrid(off, off, off, indexing="ij")
+    offs = torch.stack([ox.reshape(-1), oy.reshape(-1), oz.reshape(-1)], 1)        # [K^3, 3] (x, y, z)
+    vol = torch.zeros(nz * ny * nx, device=device, dtype=torch.float32)
+    n_xyz = torch.tensor([nx, ny, nz], device=device, dtype=torch.int64)
+    for i in range(0, P.shape[0], chunk):
+        p = P[i:i + chunk]
+        r = Rr[i:i + chunk]
+        cell = torch.floor(p).to(torch.int64)[:, None, :] + offs[None]               # [c, K^3, 3]
+        ok = ((cell >= 0) & (cell < n_xyz)).all(-1)
+        d = torch.linalg.norm(cell.to(torch.float32) + 0.5 - p[:, None, :], dim=-1)
+        val = torch.clamp(1.0 - d / r[:, None], 0.0, 1.0)
+        ok &= val > 0
+        idx = cell[..., 0] + nx * (cell[..., 1] + ny * cell[..., 2])
+        vol.scatter_reduce_(0, idx[ok], val[ok], reduce="amax")
+    return vol.view(nz, ny, nx)
+
+
+def c3_workloads():
+    """Large-volume precision cases: 1024^3 tubes (~2 % of voxels) stored as
+    f32 and f16, and 2048^3 tubes stored as u16; 8^3 bricks."""
+    return [dict(name="tubes1024", dims=(1024, 1024, 1024), fraction=0.02, seed=31, storage=("f32", "f16")),
+            dict(name="tubes2048", dims=(2048, 2048, 2048), fraction=0.02, seed=32, storage=("u16",))]
+
+
 def serving_volumes(count=16, seed=5, sizes=(128, 256, 512, 1024), device="cuda"):
     """Resident volumes for the serving workload: cubes of the given edge
     sizes, alternating u8 and f16 storage, blob sums at 1-20 % density."""

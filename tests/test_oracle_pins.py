@@ -131,6 +131,92 @@ def test_classify_spike_between_voxel_values():
     assert np.all(oracle.classify(mn, mx, vol.dtype, tf) == 1)
 
 
+def test_vote_spike_between_voxel_values():
+    # the per-voxel vote (Sec. 3.1) looks at voxel values only: with voxels
+    # alternating 0 / 200 and only entry 100 visible, no voxel votes, so the
+    # vote skips a brick whose interpolated samples are visible -- the reason
+    # the default classification uses min/max with an index window instead
+    vol = np.zeros((16, 16, 16), np.uint8)
+    vol[:, :, 1::2] = 200
+    tf = np.zeros((256, 4), np.float32)
+    tf[100] = (1.0, 1.0, 1.0, 0.5)
+    v = oracle.vote(vol, 8, tf)
+    mn, mx = oracle.brick_minmax(vol, 8)
+    assert v.sum() == 0 and np.all(oracle.classify(mn, mx, vol.dtype, tf) == 1)
+    cam = synth.orthographic((16, 16, 16), 12, 10, (0.3, 0.4, 1.0))
+    full = oracle.render(vol, tf, cam, 12, 10)
+    skipped = oracle.render(vol, tf, cam, 12, 10, mode=1, flags=v, B=8)
+    assert full[..., 3].max() > 0.1 and np.all(skipped == 0)
+
+
+def test_vote_tf_extremes():
+    vol = synth.blobs_u8((30, 20, 25), seed=4, cut=60)
+    zero = np.zeros((256, 4), np.float32)
+    assert oracle.vote(vol, 8, zero).sum() == 0
+    full = np.full((256, 4), 0.5, np.float32)
+    assert np.all(oracle.vote(vol, 8, full) == 1)
+
+
+def test_vote_single_voxel_owns_its_brick_only():
+    # one bright voxel at the corner of brick (1,1,1): the vote flags exactly
+    # that brick; the min/max classification (one-voxel apron) also flags the
+    # seven bricks whose apron reaches the voxel
+    vol = np.zeros((24, 24, 24), np.uint8)
+    vol[8, 8, 8] = 255
+    tf = np.zeros((256, 4), np.float32)
+    tf[200:, 3] = 1.0
+    v = oracle.vote(vol, 8, tf).reshape(3, 3, 3)
+    expect = np.zeros((3, 3, 3), np.uint8)
+    expect[1, 1, 1] = 1
+    assert np.array_equal(v, expect)
+    mn, mx = oracle.brick_minmax(vol, 8)
+    c = oracle.classify(mn, mx, vol.dtype, tf).reshape(3, 3, 3)
+    expect[0:2, 0:2, 0:2] = 1
+    assert np.array_equal(c, expect)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+@pytest.mark.parametrize("B", [4, 8])
+def test_vote_plateau_tf_closed_form(seed, B):
+    # alpha 0 below entry 128, 0.5 from 128 on; voxel values avoid the band
+    # 121..134 around the step, where the FP32 lookup could round either way:
+    # then a brick votes iff one of its own voxels is >= 135
+    rng = np.random.default_rng(seed)
+    dims = (37, 29, 22)
+    vals = np.concatenate([np.arange(0, 121), np.arange(135, 256)]).astype(np.uint8)
+    vol = rng.choice(vals, size=dims[::-1], p=None)
+    vol[rng.random(dims[::-1]) < 0.97] = 0
+    tf = np.zeros((256, 4), np.float32)
+    tf[128:, 3] = 0.5
+    nb = oracle.brick_grid(dims, B)
+    expect = np.zeros(nb[::-1], np.uint8)
+    zz, yy, xx = np.nonzero(vol >= 135)
+    expect[zz // B, yy // B, xx // B] = 1
+    v = oracle.vote(vol, B, tf)
+    assert np.array_equal(v, expect.reshape(-1))
+    mn, mx = oracle.brick_minmax(vol, B)
+    assert np.all(v <= oracle.classify(mn, mx, vol.dtype, tf))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16, np.float16, np.float32])
+def test_vote_is_subset_of_classification(seed, dtype):
+    # a visible voxel reads TF entries inside its brick's index window
+    dims = (33, 26, 19)
+    base = synth.blobs_u8(dims, seed=30 + seed, cut=40)
+    if dtype == np.uint8:
+        vol = base
+    elif dtype == np.uint16:
+        vol = (base.astype(np.uint16) * 257).astype(np.uint16)
+    else:
+        vol = (base.astype(np.float64) / 255.0).astype(dtype)
+    tf = synth.tf_random(seed + 3, 256)
+    mn, mx = oracle.brick_minmax(vol, 8)
+    c = oracle.classify(mn, mx, vol.dtype, tf)
+    v = oracle.vote(vol, 8, tf)
+    assert v.sum() > 0 and np.all(v <= c)
+
+
 @pytest.mark.parametrize("seed", [0, 1, 2])
 @pytest.mark.parametrize("dtype", [np.uint8, np.float32, np.float16])
 def test_classify_conservative_dense_sampling(seed, dtype):
