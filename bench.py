@@ -32,6 +32,29 @@ ACCELS = ("grid", "lbvh", "kd")
 # opacity correction 5, compositing 9)
 FLOP_PER_SAMPLE = 71
 PEAK_FP32_TFLOPS = 157.3
+ACCEL_CODE = {"grid": 1, "lbvh": 2, "kd": 4}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_noise512_1080p.md")
+RENDER_SRC = os.path.join(ROOT, "paper_1912_09596_amd", "csrc", "render.hip")
+
+
+def measured_traffic(accel):
+    """HBM bytes per launch of k_render<accel> (f32 volume) from the committed
+    FETCH_SIZE / WRITE_SIZE summary, or None when there is none or when the
+    render source has changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+        src = hashlib.sha256(open(RENDER_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if f"render.hip sha256: {src}" not in text:
+        return None
+    key = f"`k_render<{ACCEL_CODE[accel]}, float, unsigned int, true>`"
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if cells and cells[0] == key:
+            return int(float(cells[-1]))
+    return None
 
 
 def log(msg):
@@ -149,6 +172,124 @@ def batched_vs_plain(esk, torch, count=64, reps=5):
             "images_identical": bool(same)}
 
 
+def large_volumes(esk, torch, reps=3):
+    """1024^3 tubes (~2 % of voxels) stored as f32 and f16, 2048^3 tubes stored
+    as u16, 8^3 bricks: set_volume, rebuild per structure and 1080p render
+    per structure (perspective).  Errors against the oracle are checked by
+    the test suite on sampled pixels; here only times are taken."""
+    import synth
+
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+
+    def ev_ms(fn):
+        times = []
+        for _ in range(reps):
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        return round(statistics.median(times), 4)
+
+    out = {}
+    kd = esk.Kd(**KD)
+    for w in synth.c3_workloads():
+        dims = w["dims"]
+        src = synth.tubes_torch(dims, w["fraction"], w["seed"])
+        tf = torch.from_numpy(synth.tf_random(w["seed"], 256)).cuda()
+        cam = synth.perspective(dims, W, H, synth.view_direction(w["seed"]))
+        for storage in w["storage"]:
+            if storage == "f32":
+                dv = src
+            elif storage == "f16":
+                dv = src.to(torch.float16)
+            else:
+                q = torch.empty(src.shape, dtype=torch.int16, device=src.device)
+                for z in range(0, src.shape[0], 128):
+                    q[z:z + 128] = torch.floor(src[z:z + 128] * 65535.0 + 0.5).to(torch.int32).to(torch.int16)
+                dv = q.view(torch.uint16)
+            ctx = esk.Context(0)
+            ctx.set_volume(dv, 8, (0.0, 1.0), max_tf=256)
+            rec = {"dims": list(dims), "storage": storage, "brick": 8,
+                   "set_volume_ms": ev_ms(lambda: ctx.set_volume(dv, 8, (0.0, 1.0), max_tf=256,
+                                                                 workspace=ctx._keep["ws"]))}
+            rebuild = {}
+            for a in ACCELS:
+                times = []
+                for _ in range(reps):
+                    torch.cuda.synchronize()
+                    t = time.perf_counter()
+                    ctx.set_tf(tf, build=(a,), kd=kd)
+                    torch.cuda.synchronize()
+                    times.append((time.perf_counter() - t) * 1e3)
+                rebuild[a] = round(statistics.median(times), 4)
+            ctx.set_tf(tf, build=ACCELS, kd=kd)
+            img = torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
+            render = {a: ev_ms(lambda a=a: ctx.render(cam, W, H, accel=a, out=img)) for a in ACCELS + ("none",)}
+            st = ctx.stats()
+            rec.update({"rebuild_ms": rebuild, "render_ms": render,
+                        "render_mrays_per_s": {a: round(W * H / v / 1e3, 1) for a, v in render.items()},
+                        "bricks_nonempty": st["n_nonempty"], "bricks": st["n_bricks"],
+                        "lbvh_nodes": st["lbvh_nodes"], "kd_nodes": st["kd_nodes"], "kd_height": st["kd_height"]})
+            out[f"{w['name']}_{storage}"] = rec
+            ctx.close()
+            del dv, ctx
+            torch.cuda.empty_cache()
+        del src
+        torch.cuda.empty_cache()
+    return out
+
+
+def statistics_table(esk, torch, noise_vol, reps=3):
+    """Node counts, heights and rebuild times of the LBVH and of the k-d
+    variants (shallow, deep, deep + MLS 32, deep + MLS 128; 4 bins) on the
+    synthetic stand-ins, 8^3 bricks, one ramp TF (alpha > 0 above s = 0.02):
+    the quantities of the paper's statistics table (Sec. 4.3)."""
+    import numpy as np
+
+    import synth
+
+    rng = np.random.default_rng(7)
+    tf = torch.from_numpy(synth.tf_ramp(256, start=0.02)).cuda()
+    variants = {"shallow": esk.Kd(0, 0, 4), "deep": esk.Kd(1, 0, 4), "deep_mls32": esk.Kd(1, 32, 4),
+                "deep_mls128": esk.Kd(1, 128, 4)}
+    cases = [("blobs256_u8", lambda: synth._blob_volume_torch((256, 256, 256), 8, 0.1, rng, "cuda", "u8")),
+             ("noise512_f32", lambda: noise_vol),
+             ("tubes1024_f32", lambda: synth.tubes_torch((1024, 1024, 1024), 0.02, 31)),
+             ("menger243_u8", lambda: torch.from_numpy(synth.menger_sponge(4, 3)).cuda())]
+
+    def timed(ctx, build, kd=None):
+        times = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            ctx.set_tf(tf, build=build, kd=kd)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t) * 1e3)
+        return round(statistics.median(times), 4)
+
+    out = {}
+    for name, make in cases:
+        vol = make()
+        ctx = esk.Context(0)
+        ctx.set_volume(vol, 8, (0.0, 1.0), max_tf=256)
+        rec = {"dims": list(vol.shape[::-1]), "grid_ms": timed(ctx, ("grid",))}
+        ms = timed(ctx, ("lbvh",))
+        st = ctx.stats()
+        rec.update({"bricks": st["n_bricks"], "bricks_nonempty": st["n_nonempty"],
+                    "lbvh": {"nodes": st["lbvh_nodes"], "height": st["lbvh_height"], "rebuild_ms": ms}})
+        for vname, kd in variants.items():
+            ms = timed(ctx, ("kd",), kd)
+            st = ctx.stats()
+            rec[f"kd_{vname}"] = {"nodes": st["kd_nodes"], "height": st["kd_height"], "rebuild_ms": ms}
+        out[name] = rec
+        ctx.close()
+        del vol, ctx
+        torch.cuda.empty_cache()
+    return out
+
+
 def serving(esk, torch, n_req=400, rate=200.0, seed=6):
     """A Poisson stream of TF edits and renders over 16 resident volumes
     (128^3..1024^3, u8 and f16), images 256^2..1920x1080: continuous
@@ -232,6 +373,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip the 1024^3 / 2048^3 storage-precision section")
+    ap.add_argument("--no-stats", action="store_true", help="skip the node/height statistics table")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 512 MiB device copy first (reference for HBM counters)")
     ap.add_argument("--cpu-steps", type=int, default=3)
@@ -337,8 +480,10 @@ def main():
 
     mean_ms = {a: statistics.mean(render_ms[a]) for a in ACCELS}
     dominant = max(ACCELS, key=lambda a: mean_ms[a])
-    # the same frame's sample count stands in for every step (same TF sequence position)
-    flops = samples[dominant] * FLOP_PER_SAMPLE
+    # algorithmic work: the samples of the non-empty bricks (what the grid
+    # composites); trees may also march some empty-brick samples, which do
+    # not count.  The same frame stands in for every step.
+    flops = samples["grid"] * FLOP_PER_SAMPLE
     achieved = flops / (statistics.median(render_ms[dominant]) * 1e-3) / 1e12
     result = {
         "metric": "Mrays/s at 1080p + rebuild ms per TF change; batched vs plain, RGBA err≤1e-3",
@@ -371,13 +516,19 @@ def main():
         },
         "roofline": {"kernel": f"k_render<{dominant}>", "bound": "alu", "achieved": round(achieved, 3),
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP32_TFLOPS, 5), "traffic": None},
+                     "frac": round(achieved / PEAK_FP32_TFLOPS, 5), "traffic": measured_traffic(dominant)},
     }
     if not args.no_batch:
         log("batched vs plain")
         result["batched"] = batched_vs_plain(esk, torch)
         log("serving")
         result["serving"] = serving(esk, torch)
+    if not args.no_stats:
+        log("node/height statistics")
+        result["statistics"] = statistics_table(esk, torch, dvol)
+    if not args.no_large:
+        log("large volumes (1024^3 f32/f16, 2048^3 u16)")
+        result["large_volumes"] = large_volumes(esk, torch)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(vol, tfs, args.cpu_steps, args.cpu_stride)

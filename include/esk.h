@@ -14,7 +14,10 @@
  *  - Bricks have edge B (a power of two, 4..32); brick (bx,by,bz) covers the
  *    voxels [B*b, min(B*b+B, n)) on each axis; its linear id is
  *    bx + nbx*(by + nby*bz) with nbx = ceil(nx/B) (likewise y, z).  At most 1024 bricks per
- *    axis (10 bits per axis of the 30-bit Morton code, Sec. 3.1).
+ *    axis (10 bits per axis of the 30-bit Morton code, Sec. 3.1), at most
+ *    2^28 bricks in all, and 64*R*ceil(nx/8)*ceil(ny/8) < 2^32 (R = 9 for
+ *    f32, else 8: the element stride of an 8-voxel z-slab of the renderer's
+ *    blocked copy); beyond these limits calls return ESK_ELIMIT.
  *  - Transfer functions are N x RGBA float32, N in [2, 4096]; entry i sits at
  *    the normalised value i/(N-1).  Normalised value s(v): v/255 (u8),
  *    v/65535 (u16), clamp((v-lo)/(hi-lo), 0, 1) (f16, f32).
@@ -63,6 +66,19 @@ typedef enum {
     ESK_ACCEL_LBVH = 2, /* LBVH over non-empty bricks (Sec. 3.1) */
     ESK_ACCEL_KD = 4    /* binned k-d tree over brick occupancy (Sec. 3.2.2, 4.3) */
 } esk_accel;
+
+/* Classification mode, OR-ed into the build mask of
+ * esk_set_transfer_function.  Default (bit clear): a brick is non-empty iff
+ * the TF has an entry with alpha > 0 inside the index window of its value
+ * range with apron (conservative: the skipped image equals the full march).
+ * ESK_CLASSIFY_VOXEL: the per-voxel vote of Sec. 3.1 -- a brick is non-empty
+ * iff one of its own voxels (no apron) maps to alpha > 0 under the
+ * renderer's TF lookup in FP32 (s = (v - lo) * scale, x = clamp(s, 0, 1) *
+ * (N-1), i0 = min(floor(x), N-2), alpha = fma(x - i0, a[i0+1] - a[i0],
+ * a[i0])).  It reads every voxel per TF change and is not conservative:
+ * interpolated samples between voxels can be visible in a brick whose voxels
+ * are not, and such samples are skipped. */
+enum { ESK_CLASSIFY_VOXEL = 0x100 };
 
 /* k-d build parameters (Sec. 4.3).
  *  halting:  0 = shallow: split only while 10*V(node) > V(root);
@@ -151,13 +167,15 @@ esk_status esk_set_volume(esk_ctx *ctx, const void *d_vox, int dtype, int nx, in
                           void *d_ws, size_t ws_bytes);
 
 /* Sets the TF and rebuilds (Sec. 3.1, 3.2.2): TF prefix count -> brick
- * classification -> grid bitmask -> compaction -> Morton codes -> radix sort
- * -> Karras hierarchy -> AABB refit (if ESK_ACCEL_LBVH in build_mask), and the
- * 3-D occupancy prefix count -> level-synchronous binned k-d build (if
- * ESK_ACCEL_KD).  d_rgba: N x RGBA float32 on the device, copied into the
+ * classification (or the per-voxel vote with ESK_CLASSIFY_VOXEL) -> grid
+ * bitmask -> compaction -> Morton codes -> radix sort -> Karras hierarchy ->
+ * AABB refit (if ESK_ACCEL_LBVH in build_mask), and the 3-D occupancy prefix
+ * count -> level-synchronous binned k-d build (if ESK_ACCEL_KD).  The grid
+ * is always built.  d_rgba: N x RGBA float32 on the device, copied into the
  * workspace (the caller may reuse it once the stream reaches this point).
- * kd may be NULL when ESK_ACCEL_KD is not requested.  Asynchronous, except
- * that a k-d build reads its level counts back to the host. */
+ * kd may be NULL when ESK_ACCEL_KD is not requested.  Asynchronous: the k-d
+ * build runs on an internal stream of the context and is checked for
+ * completion (one synchronisation) when the tree is first used. */
 esk_status esk_set_transfer_function(esk_ctx *ctx, const float *d_rgba, int n_entries,
                                      int build_mask, const esk_kd_params *kd);
 

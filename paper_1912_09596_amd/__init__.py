@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libesk.so")
 OK, EINVAL, ENOSPC, ELIMIT, EDEVICE, ESTATE, EINTERNAL = 0, -1, -2, -3, -4, -5, -6
 U8, U16, F16, F32 = 0, 1, 2, 3
 NONE, GRID, LBVH, KD = 0, 1, 2, 4
+CLASSIFY_VOXEL = 0x100      # build-mask bit: per-voxel vote instead of brick min/max
 ACCEL = {"none": NONE, "grid": GRID, "lbvh": LBVH, "kd": KD}
 LEAF = 0x80000000
 
@@ -192,11 +193,15 @@ class Context:
         self.dtype_code = code
         return self
 
-    def set_tf(self, tf, build=("grid", "lbvh", "kd"), kd: Kd | None = None):
-        """tf: contiguous [N, 4] float32 device tensor; rebuilds the requested structures."""
+    def set_tf(self, tf, build=("grid", "lbvh", "kd"), kd: Kd | None = None, classify: str = "minmax"):
+        """tf: contiguous [N, 4] float32 device tensor; rebuilds the requested
+        structures.  classify: "minmax" (conservative brick value ranges) or
+        "voxel" (the per-voxel vote)."""
         if tf.dtype.is_floating_point is False or tf.dim() != 2 or tf.shape[1] != 4:
             raise ValueError("TF must be an [N, 4] float32 tensor")
-        mask = 0
+        if classify not in ("minmax", "voxel"):
+            raise ValueError("classify must be 'minmax' or 'voxel'")
+        mask = CLASSIFY_VOXEL if classify == "voxel" else 0
         for b in build:
             mask |= ACCEL[b]
         kp = None

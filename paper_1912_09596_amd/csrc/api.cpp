@@ -34,8 +34,7 @@ Layout make_layout(int nx, int ny, int nz, int brick, int elem_bytes, int max_tf
     std::memset(&L, 0, sizeof(L));
     const int nbx = (nx + brick - 1) / brick, nby = (ny + brick - 1) / brick, nbz = (nz + brick - 1) / brick;
     const int64_t nb = (int64_t)nbx * nby * nbz;
-    const int64_t nswz = (int64_t)((nx + kSwzEdge - 1) / kSwzEdge) * ((ny + kSwzEdge - 1) / kSwzEdge) *
-                         ((nz + kSwzEdge - 1) / kSwzEdge) * kSwzEdge * kSwzEdge * kSwzEdge;
+    const int nq[3] = {(nx + kSwzEdge - 1) / kSwzEdge, (ny + kSwzEdge - 1) / kSwzEdge, (nz + kSwzEdge - 1) / kSwzEdge};
     L.nb = nb;
     L.nblk = (nb + kClassifyBlock - 1) / kClassifyBlock;
     L.nsortblk = (nb + kSortBlockKeys - 1) / kSortBlockKeys;
@@ -47,7 +46,7 @@ Layout make_layout(int nx, int ny, int nz, int brick, int elem_bytes, int max_tf
     };
     const size_t n4 = (size_t)nb * 4;
     L.header = take(sizeof(DevHeader));
-    L.swz = take((size_t)nswz * elem_bytes);
+    L.swz = take((size_t)swz_bytes(nq, elem_bytes));
     L.minv = take((size_t)nb * elem_bytes);
     L.maxv = take((size_t)nb * elem_bytes);
     L.tf = take((size_t)max_tf * 16);
@@ -173,6 +172,11 @@ esk_status check_shape(esk_ctx *c, int nx, int ny, int nz, int dtype, int brick,
         return fail(c, ESK_ELIMIT, "more than %d bricks on an axis (%d %d %d)", kMaxBricksPerAxis, nbx, nby, nbz);
     if ((int64_t)nbx * nby * nbz > kMaxBricks)
         return fail(c, ESK_ELIMIT, "more than %lld bricks", (long long)kMaxBricks);
+    // the renderer addresses a z-slab of 8^3 blocks with 32-bit element strides
+    const int64_t slab = (int64_t)64 * swz_row(elem_size(dtype)) * ((nx + kSwzEdge - 1) / kSwzEdge) *
+                         ((ny + kSwzEdge - 1) / kSwzEdge);
+    if (slab > (int64_t)0xffffffffLL)
+        return fail(c, ESK_ELIMIT, "an 8-voxel z-slab of %d x %d voxels exceeds 2^32 elements", nx, ny);
     return ESK_OK;
 }
 
@@ -369,6 +373,14 @@ esk_status esk_set_volume(esk_ctx *c, const void *d_vox, int dtype, int nx, int 
     return ESK_OK;
 }
 
+// s(v) = (v - lo) * scale: the renderer's normalisation of a voxel value
+static void value_norm(const esk_ctx *c, float &lo, float &scale)
+{
+    if (c->vol.dtype == ESK_U8) { lo = 0.0f; scale = 1.0f / 255.0f; }
+    else if (c->vol.dtype == ESK_U16) { lo = 0.0f; scale = 1.0f / 65535.0f; }
+    else { lo = c->vlo; scale = 1.0f / (c->vhi - c->vlo); }
+}
+
 static RebuildArgs rebuild_args(esk_ctx *c)
 {
     RebuildArgs a;
@@ -405,6 +417,7 @@ static RebuildArgs rebuild_args(esk_ctx *c)
     a.nblk = L.nblk;
     a.nsortblk = L.nsortblk;
     a.key_bits = 3 * std::max({bits_for(c->vol.nb[0]), bits_for(c->vol.nb[1]), bits_for(c->vol.nb[2])});
+    value_norm(c, a.nlo, a.nscale);
     return a;
 }
 
@@ -446,7 +459,7 @@ esk_status esk_set_transfer_function(esk_ctx *c, const float *d_rgba, int n_entr
     if (!d_rgba) return fail(c, ESK_EINVAL, "TF pointer is null");
     if ((reinterpret_cast<uintptr_t>(d_rgba) & 15) != 0) return fail(c, ESK_EINVAL, "TF must be 16-byte aligned");
     if (n_entries < 2) return fail(c, ESK_EINVAL, "TF needs at least 2 entries (got %d)", n_entries);
-    if (build_mask & ~(ESK_ACCEL_GRID | ESK_ACCEL_LBVH | ESK_ACCEL_KD))
+    if (build_mask & ~(ESK_ACCEL_GRID | ESK_ACCEL_LBVH | ESK_ACCEL_KD | ESK_CLASSIFY_VOXEL))
         return fail(c, ESK_EINVAL, "unknown bits in build_mask 0x%x", build_mask);
     if (build_mask & ESK_ACCEL_KD) {
         if (!kd) return fail(c, ESK_EINVAL, "k-d build requested without parameters");
@@ -470,6 +483,11 @@ esk_status esk_set_transfer_function(esk_ctx *c, const float *d_rgba, int n_entr
     e = hipMemcpyAsync(c->ws + L.tf, d_rgba, (size_t)n_entries * 16, hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) return hip_check(c, e, "TF copy");
     RebuildArgs a = rebuild_args(c);
+    if (build_mask & ESK_CLASSIFY_VOXEL) {
+        a.vote = 1;
+        e = launch_vote(a, c->stream);
+        if (e != hipSuccess) return hip_check(c, e, "vote launch");
+    }
     e = launch_classify_compact(a, c->stream);
     if (e != hipSuccess) return hip_check(c, e, "classify launch");
     if (build_mask & ESK_ACCEL_LBVH) {
@@ -505,7 +523,7 @@ esk_status esk_set_transfer_function(esk_ctx *c, const float *d_rgba, int n_entr
         c->kd_on_device = true;
         c->kd_joined = false;
     }
-    c->built = build_mask;
+    c->built = build_mask & (ESK_ACCEL_GRID | ESK_ACCEL_LBVH | ESK_ACCEL_KD);
     c->has_tf = true;
     return ESK_OK;
 }
@@ -541,9 +559,7 @@ static esk_status prepare_render(esk_ctx *c, int accel, const esk_camera *cam, i
     const Layout &L = c->L;
     std::memset(&r, 0, sizeof(r));
     r.vol = c->vol;
-    if (c->vol.dtype == ESK_U8) { r.vlo = 0.0f; r.vscale = 1.0f / 255.0f; }
-    else if (c->vol.dtype == ESK_U16) { r.vlo = 0.0f; r.vscale = 1.0f / 65535.0f; }
-    else { r.vlo = c->vlo; r.vscale = 1.0f / (c->vhi - c->vlo); }
+    value_norm(c, r.vlo, r.vscale);
     r.tf = at<float>(c, L.tf);
     r.N = c->N;
     r.cam = *cam;
@@ -642,7 +658,7 @@ esk_status esk_render_batch(esk_ctx *const *ctxs, int n, int accel, const esk_ca
             if (ctxs[i] != c0) fail(c0, st, "request %d: %s", i, ctxs[i]->err.c_str());
             return st;
         }
-        const int64_t nbytes = (int64_t)r.vol.nq[0] * r.vol.nq[1] * r.vol.nq[2] * 512 * elem_size(r.vol.dtype);
+        const int64_t nbytes = swz_bytes(r.vol.nq, elem_size(r.vol.dtype));
         narrow = narrow && nbytes < (int64_t)0xffffffffLL;
         tfl = tfl && r.N <= 1024;
         tx = std::max(tx, (r.W + 15) / 16);

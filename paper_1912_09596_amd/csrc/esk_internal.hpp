@@ -58,10 +58,17 @@ int elem_size(int dtype);
 
 // ---- launchers (each enqueues on `s`; returns hipSuccess or the launch error)
 // The renderer samples a copy of the volume stored in 8^3-voxel blocks
-// (512 voxels contiguous, x fastest inside a block, blocks x-fastest), made
-// at esk_set_volume: the 2x2x2 footprints of the 64 rays of a wave then fall
-// into a few blocks instead of dozens of voxel rows.
+// (one block contiguous: 64 rows of 8 voxels, x fastest, then y, then z;
+// blocks x-fastest), made at esk_set_volume: the 2x2x2 footprints of the 64
+// rays of a wave then fall into a few blocks instead of dozens of voxel rows.
+// FP32 rows hold a ninth element, the first voxel of the next block along x,
+// so both x neighbours of a sample come from one 8-byte load.
 constexpr int kSwzEdge = 8;
+__host__ __device__ constexpr int swz_row(int elem_bytes) { return elem_bytes == 4 ? 9 : 8; }
+inline int64_t swz_bytes(const int nq[3], int elem_bytes)
+{
+    return (int64_t)nq[0] * nq[1] * nq[2] * 64 * swz_row(elem_bytes) * elem_bytes;
+}
 
 struct VolumeDesc {
     const void *vox;
@@ -92,8 +99,11 @@ struct RebuildArgs {
     DevHeader *hdr;
     int64_t nb, nblk, nsortblk;
     int key_bits;          // Morton bits that can be non-zero
+    int vote;              // 1: flags come from the per-voxel vote (k_vote), not min/max
+    float nlo, nscale;     // the renderer's value normalisation s = (v - nlo) * nscale
 };
 
+hipError_t launch_vote(const RebuildArgs &a, hipStream_t s);
 hipError_t launch_classify_compact(const RebuildArgs &a, hipStream_t s);
 hipError_t launch_sort(const RebuildArgs &a, hipStream_t s);
 hipError_t launch_lbvh(const RebuildArgs &a, hipStream_t s);

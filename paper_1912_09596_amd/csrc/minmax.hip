@@ -256,17 +256,21 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_swizzle(const T *__restrict__ vol, int nx, int ny, int nz, int nqx,
                                                  int nqy, T *__restrict__ swz)
 {
+    constexpr int ROW = swz_row((int)sizeof(T));
     const int qy = blockIdx.x % nqy, qz = blockIdx.x / nqy;
-    const int px = nqx * 8;
+    const int slots = nqx * ROW;
     const size_t row_blocks = ((size_t)qz * nqy + qy) * nqx;
     for (int r = 0; r < 64; ++r) {
         const int zl = r >> 3, yl = r & 7;
         const int y = qy * 8 + yl, z = qz * 8 + zl;
         const bool in = (y < ny) && (z < nz);
         const T *src = vol + ((size_t)z * ny + y) * (size_t)nx;
-        for (int x = threadIdx.x; x < px; x += 256) {
+        for (int i = threadIdx.x; i < slots; i += 256) {
+            // slot i: element xi of the row in block qx (xi == 8: the apron voxel)
+            const int qx = i / ROW, xi = i - qx * ROW;
+            const int x = qx * 8 + xi;
             const T val = (in && x < nx) ? src[x] : (T)0;
-            swz[(row_blocks + (size_t)(x >> 3)) * 512 + zl * 64 + yl * 8 + (x & 7)] = val;
+            swz[(row_blocks + (size_t)qx) * (64 * ROW) + r * ROW + xi] = val;
         }
     }
 }

@@ -7,6 +7,8 @@
 // TF prefix count (each block rebuilds it in LDS from the TF copy), the grid
 // bitmask (wave ballots) and the per-block non-empty counts; compaction fuses
 // the Morton encoding; one workgroup sorts up to 32K keys entirely in LDS.
+#include <algorithm>
+
 #include "esk_internal.hpp"
 #include "device_util.hpp"
 
@@ -75,6 +77,65 @@ __device__ inline float load_minmax(const void *p, int dtype, int64_t i)
     }
 }
 
+// ---------------------------------------------------------------------------
+// per-voxel vote (Sec. 3.1's classification, an alternative to min/max): a
+// brick is non-empty iff one of its own voxels maps to alpha > 0 under the
+// renderer's TF lookup.  One workgroup per (256-voxel x run, brick row, brick
+// slab); each lane tests its column of the brick's y-z cross-section, the
+// lanes of one brick meet in a ballot, and one lane per brick raises the flag.
+// Every voxel is read once: an HBM-bound pass per TF change.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_fill_u8(uint8_t *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_vote(RebuildArgs a)
+{
+    __shared__ float alpha[kMaxTF];
+    const int N = a.N;
+    for (int i = threadIdx.x; i < N; i += 256) alpha[i] = a.tf[4 * i + 3];
+    __syncthreads();
+    const int B = a.vol.B, sh = a.vol.log2B;
+    const int nx = a.vol.nx, ny = a.vol.ny, nz = a.vol.nz;
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    const int by = blockIdx.y, bz = blockIdx.z;
+    const T *vol = static_cast<const T *>(a.vol.vox);
+    bool vis = false;
+    if (x < nx) {
+        const int y1 = min(by * B + B, ny), z1 = min(bz * B + B, nz);
+        for (int z = bz * B; z < z1 && !vis; ++z)
+            for (int y = by * B; y < y1 && !vis; ++y) {
+                const float v = (float)vol[((size_t)z * ny + y) * (size_t)nx + x];
+                // the lookup of the renderer: s, x = s (N-1), lerp of alpha
+                float t = (v - a.nlo) * a.nscale;
+                t = fminf(fmaxf(t, 0.0f), 1.0f) * (float)(N - 1);
+                const int i0 = min((int)t, N - 2);
+                const float f = t - (float)i0;
+                const float al = fmaf(f, alpha[i0 + 1] - alpha[i0], alpha[i0]);
+                vis = al > 0.0f;
+            }
+    }
+    // lanes x .. x+B-1 of one brick are consecutive within a wave (B divides 64)
+    const uint64_t m = __ballot(vis);
+    const int lane = threadIdx.x & 63;
+    if ((lane & (B - 1)) == 0 && x < nx) {
+        const uint64_t seg = (m >> lane) & (B == 64 ? ~0ull : ((1ull << B) - 1ull));
+        if (seg) a.flags[(x >> sh) + (int64_t)a.vol.nb[0] * (by + (int64_t)a.vol.nb[1] * bz)] = 1;
+    }
+}
+
+template <typename T> hipError_t launch_vote_typed(const RebuildArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)std::min<int64_t>((a.nb + 255) / 256, 4096)), dim3(256), 0, s,
+                       a.flags, a.nb);
+    const dim3 grid((unsigned)((a.vol.nx + 255) / 256), (unsigned)a.vol.nb[1], (unsigned)a.vol.nb[2]);
+    hipLaunchKernelGGL((k_vote<T>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void k_classify(RebuildArgs a)
 {
     __shared__ int32_t P[kMaxTF + 1];
@@ -103,7 +164,9 @@ __global__ __launch_bounds__(256) void k_classify(RebuildArgs a)
     for (int j = 0; j < 4; ++j) {
         const int64_t b = base + 256 * j + threadIdx.x;
         int flag = 0;
-        if (b < a.nb) {
+        if (b < a.nb && a.vote) {
+            flag = a.flags[b];
+        } else if (b < a.nb) {
             float mn = load_minmax(a.minv, a.vol.dtype, b);
             float mx = load_minmax(a.maxv, a.vol.dtype, b);
             int lo = tf_floor_index(mn, a.vol.dtype, a.vlo, a.vhi, N) - 1;
@@ -454,6 +517,17 @@ __global__ __launch_bounds__(256) void k_lbvh_height(RebuildArgs a)
 }
 
 }  // namespace
+
+hipError_t launch_vote(const RebuildArgs &a, hipStream_t s)
+{
+    switch (a.vol.dtype) {
+    case ESK_U8: return launch_vote_typed<uint8_t>(a, s);
+    case ESK_U16: return launch_vote_typed<uint16_t>(a, s);
+    case ESK_F16: return launch_vote_typed<_Float16>(a, s);
+    case ESK_F32: return launch_vote_typed<float>(a, s);
+    }
+    return hipErrorInvalidValue;
+}
 
 hipError_t launch_classify_compact(const RebuildArgs &a, hipStream_t s)
 {

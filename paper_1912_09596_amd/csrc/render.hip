@@ -28,6 +28,10 @@ namespace esk {
 namespace {
 
 constexpr float kBoxEps = 1.0f / 32.0f;   // voxel-space slack of the culling tests
+#ifndef ESK_MARCH_GROUP
+#define ESK_MARCH_GROUP 4
+#endif
+constexpr int kGroup = ESK_MARCH_GROUP;   // samples gathered before compositing
 
 struct Ray {
     float o[3], d[3];
@@ -118,17 +122,31 @@ struct Accum {
 struct Vol {
     int n[3];
     float fn[3];
-    uint32_t sy, sz;   // elements between block rows / block slabs of the blocked copy
+    uint32_t sy;       // elements between block rows of the blocked copy (a slab is nq1 rows)
+    uint32_t nq1;      // blocks along y
 };
 
 // cell-centred trilinear interpolation (clamp to edge) from the blocked copy:
-// element (x, y, z) sits at (z>>3)*sz + (z&7)*64 + (y>>3)*sy + (y&7)*8 + (x>>3)*512 + (x&7)
+// with R elements per block row (R = 8, or 9 for FP32 rows carrying the next
+// block's first voxel), element (x, y, z) sits at
+// ((z>>3)*nq1 + (y>>3))*sy + (x>>3)*64R + ((z&7)*8 + (y&7))*R + (x&7), sy = 64R*nq0.
+// Split in two so a group of samples can issue all its gathers before the
+// first interpolation: gather() loads the 8 corners and the weights, lerp3()
+// combines them.
+struct Corners {
+    float c[8];
+    float w[3];
+};
+
 template <typename T, typename IDX>
-__device__ inline float trilinear(const T *__restrict__ vol, const Vol &v, const float p[3])
+__device__ inline void gather(const T *__restrict__ vol, const Vol &v, const float p[3], Corners &g)
 {
+    constexpr int R = swz_row((int)sizeof(T));
     const float ux = p[0] - 0.5f, uy = p[1] - 0.5f, uz = p[2] - 0.5f;
     const float fx = floorf(ux), fy = floorf(uy), fz = floorf(uz);
-    const float wx = ux - fx, wy = uy - fy, wz = uz - fz;
+    g.w[0] = ux - fx;
+    g.w[1] = uy - fy;
+    g.w[2] = uz - fz;
     const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
     const int x0 = min(max(ix, 0), v.n[0] - 1), x1 = min(max(ix + 1, 0), v.n[0] - 1);
     const int y0 = min(max(iy, 0), v.n[1] - 1), y1 = min(max(iy + 1, 0), v.n[1] - 1);
@@ -136,23 +154,72 @@ __device__ inline float trilinear(const T *__restrict__ vol, const Vol &v, const
     // IDX = uint32_t: the copy is < 4 GiB, so byte offsets are 32-bit and every
     // load is a scalar base plus one 32-bit vector offset
     constexpr IDX E = (IDX)sizeof(T);
-    auto ox = [&](int x) { return ((IDX)(x >> 3) * 512 + (IDX)(x & 7)) * E; };
-    auto oy = [&](int y) { return ((IDX)(y >> 3) * v.sy + (IDX)(y & 7) * 8) * E; };
-    auto oz = [&](int z) { return ((IDX)(z >> 3) * v.sz + (IDX)(z & 7) * 64) * E; };
-    const IDX bx0 = ox(x0), bx1 = ox(x1);
+    // block strides: (y>>3)*sy and (z>>3)*sz = ((z>>3)*nq1)*sy.  With 32-bit
+    // offsets every factor is below 2^24 (sy = 64R*nq0 with nq0 <= 4096,
+    // z>>3 and nq1 <= 4096), so the full-rate 24-bit multiply is exact in
+    // the low 32 bits; 64-bit offsets multiply in 64 bits
+    // (the masks only state known ranges: block indices and nq1 are below
+    // 4096 -- at most 32768 voxels per axis -- and sy <= 576 * 4096 < 2^22)
+    const uint32_t sy = v.sy & 0x3fffffu, nq1 = v.nq1 & 0xfffu;
+    auto mul = [&](uint32_t a, uint32_t b) -> IDX {
+        if constexpr (sizeof(IDX) == 4) return (IDX)__umul24(a, b);
+        else return (IDX)a * (IDX)b;
+    };
+    auto q = [](int c) { return (uint32_t)(c >> 3) & 0xfffu; };
+    auto ox = [&](int x) { return ((IDX)__umul24(q(x), 64 * R) + (IDX)(x & 7)) * E; };
+    auto oy = [&](int y) { return (mul(q(y), sy) + (IDX)(y & 7) * R) * E; };
+    auto oz = [&](int z) { return (mul(__umul24(q(z), nq1), sy) + (IDX)(z & 7) * (8 * R)) * E; };
     const IDX r00 = oz(z0) + oy(y0), r10 = oz(z0) + oy(y1);
     const IDX r01 = oz(z1) + oy(y0), r11 = oz(z1) + oy(y1);
     const char *__restrict__ base = reinterpret_cast<const char *>(vol);
-    auto ld = [&](IDX off) { return (float)*reinterpret_cast<const T *>(base + off); };
-    const float v000 = ld(r00 + bx0), v100 = ld(r00 + bx1);
-    const float v010 = ld(r10 + bx0), v110 = ld(r10 + bx1);
-    const float v001 = ld(r01 + bx0), v101 = ld(r01 + bx1);
-    const float v011 = ld(r11 + bx0), v111 = ld(r11 + bx1);
-    const float c00 = fmaf(wx, v100 - v000, v000), c10 = fmaf(wx, v110 - v010, v010);
-    const float c01 = fmaf(wx, v101 - v001, v001), c11 = fmaf(wx, v111 - v011, v011);
+    if constexpr (R == 9) {
+        // x0 and x0 + 1 are adjacent in every row: one 8-byte (dword-aligned)
+        // load per row; a clamped x1 (== x0) takes the first value twice
+        const IDX bx = ox(x0);
+        const bool same = x1 == x0;
+        auto ld2 = [&](IDX off, float &a, float &b) {
+            float q[2];
+            __builtin_memcpy(q, base + off, 8);
+            a = q[0];
+            b = same ? q[0] : q[1];
+        };
+        ld2(r00 + bx, g.c[0], g.c[1]);
+        ld2(r10 + bx, g.c[2], g.c[3]);
+        ld2(r01 + bx, g.c[4], g.c[5]);
+        ld2(r11 + bx, g.c[6], g.c[7]);
+    } else {
+        const IDX bx0 = ox(x0), bx1 = ox(x1);
+        auto ld = [&](IDX off) { return (float)*reinterpret_cast<const T *>(base + off); };
+        g.c[0] = ld(r00 + bx0);
+        g.c[1] = ld(r00 + bx1);
+        g.c[2] = ld(r10 + bx0);
+        g.c[3] = ld(r10 + bx1);
+        g.c[4] = ld(r01 + bx0);
+        g.c[5] = ld(r01 + bx1);
+        g.c[6] = ld(r11 + bx0);
+        g.c[7] = ld(r11 + bx1);
+    }
+}
+
+__device__ inline float lerp3(const Corners &g)
+{
+    const float wx = g.w[0], wy = g.w[1], wz = g.w[2];
+    const float c00 = fmaf(wx, g.c[1] - g.c[0], g.c[0]), c10 = fmaf(wx, g.c[3] - g.c[2], g.c[2]);
+    const float c01 = fmaf(wx, g.c[5] - g.c[4], g.c[4]), c11 = fmaf(wx, g.c[7] - g.c[6], g.c[6]);
     const float c0 = fmaf(wy, c10 - c00, c00), c1 = fmaf(wy, c11 - c01, c01);
     return fmaf(wz, c1 - c0, c0);
 }
+
+template <typename T, typename IDX>
+__device__ inline float trilinear(const T *__restrict__ vol, const Vol &v, const float p[3])
+{
+    Corners g;
+    gather<T, IDX>(vol, v, p, g);
+    return lerp3(g);
+}
+
+// keeps the scheduler from interleaving a group's gathers with its arithmetic
+__device__ inline void group_fence() { __builtin_amdgcn_sched_barrier(0); }
 
 struct Shade {
     const float4 *tf;
@@ -161,8 +228,11 @@ struct Shade {
     int correct;
 };
 
-// post-classification + opacity correction + front-to-back "over"
-__device__ inline void composite(const Shade &s, float v, Accum &acc)
+// post-classification + opacity correction + front-to-back "over".  With
+// ok == false the sample contributes nothing (opacity 0: colour and alpha
+// stay bit-identical) and is not counted, so callers can run a fixed group
+// of samples without branching per sample.
+__device__ inline void composite(const Shade &s, float v, bool ok, Accum &acc)
 {
     float x = (v - s.vlo) * s.vscale;
     x = fminf(fmaxf(x, 0.0f), 1.0f) * (float)(s.N - 1);
@@ -179,12 +249,13 @@ __device__ inline void composite(const Shade &s, float v, Accum &acc)
         const float e = __builtin_amdgcn_exp2f(s.expo * l);
         al = al > 0.0f ? 1.0f - e : 0.0f;
     }
+    al = ok ? al : 0.0f;
     const float w = (1.0f - acc.a) * al;
     acc.c[0] = fmaf(w, r, acc.c[0]);
     acc.c[1] = fmaf(w, g, acc.c[1]);
     acc.c[2] = fmaf(w, bl, acc.c[2]);
     acc.a = acc.a + w;
-    acc.n += 1;
+    acc.n += ok ? 1 : 0;
 }
 
 __device__ inline bool inside(const Vol &v, const float p[3])
@@ -229,14 +300,28 @@ __device__ inline void march_leaf(const Ray &r, float dt, const int lo[3], const
     fb = fminf(fmaxf(fb, -4.0f), 1.0e9f);
     const int ka = max(0, (int)floorf(fa) - 1);
     const int kb = (int)floorf(fb) + 2;
-    for (int k = ka; k < kb; ++k) {
-        const float t = lattice_t(r, dt, k);
-        if (!(t < r.tx)) break;
-        float p[3];
-        point_at(r, t, p);
-        if ((p[0] >= bl[0]) & (p[0] < bh[0]) & (p[1] >= bl[1]) & (p[1] < bh[1]) & (p[2] >= bl[2]) &
-            (p[2] < bh[2]))
-            composite(s, trilinear<T, IDX>(vol, v, p), acc);
+    for (int k = ka; k < kb; k += kGroup) {
+        // a group of consecutive samples: every gather is issued before the
+        // first value is composited (the clamped addresses are valid for
+        // any point), then the group is composited in k order
+        Corners g[kGroup];
+        bool ok[kGroup];
+        bool more = true;
+#pragma unroll
+        for (int j = 0; j < kGroup; ++j) {
+            const float t = lattice_t(r, dt, k + j);
+            float p[3];
+            point_at(r, t, p);
+            const bool live = t < r.tx;
+            ok[j] = (k + j < kb) & live & (p[0] >= bl[0]) & (p[0] < bh[0]) & (p[1] >= bl[1]) &
+                    (p[1] < bh[1]) & (p[2] >= bl[2]) & (p[2] < bh[2]);
+            gather<T, IDX>(vol, v, p, g[j]);
+            more = live;
+        }
+        group_fence();
+#pragma unroll
+        for (int j = 0; j < kGroup; ++j) composite(s, lerp3(g[j]), ok[j], acc);
+        if (!more) break;
     }
 }
 
@@ -334,8 +419,9 @@ __device__ inline void render_tile(const RenderArgs &ra, int tbx, int tby)
     Vol v;
     v.n[0] = ra.vol.nx; v.n[1] = ra.vol.ny; v.n[2] = ra.vol.nz;
     for (int a = 0; a < 3; ++a) v.fn[a] = (float)v.n[a];
-    v.sy = 512u * (uint32_t)ra.vol.nq[0];
-    v.sz = 512u * (uint32_t)ra.vol.nq[0] * (uint32_t)ra.vol.nq[1];
+    constexpr uint32_t R = (uint32_t)swz_row((int)sizeof(T));
+    v.sy = 64u * R * (uint32_t)ra.vol.nq[0];
+    v.nq1 = (uint32_t)ra.vol.nq[1];
     Shade s;
     s.tf = tf_lds ? lds : reinterpret_cast<const float4 *>(ra.tf);
     s.N = ra.N;
@@ -354,16 +440,28 @@ __device__ inline void render_tile(const RenderArgs &ra, int tbx, int tby)
         r.t0 = tn > 0.0f ? tn : 0.0f;
         r.tx = tx;
         if (ACCEL == ESK_ACCEL_NONE) {
-            for (int k = 0;; ++k) {
-                const float t = lattice_t(r, dt, k);
-                if (!(t < r.tx)) break;
-                float p[3];
-                point_at(r, t, p);
-                if (inside(v, p)) composite(s, trilinear<T, IDX>(vol, v, p), acc);
+            for (int k = 0;; k += kGroup) {
+                Corners g[kGroup];
+                bool ok[kGroup];
+                bool more = true;
+#pragma unroll
+                for (int j = 0; j < kGroup; ++j) {
+                    const float t = lattice_t(r, dt, k + j);
+                    float p[3];
+                    point_at(r, t, p);
+                    const bool live = t < r.tx;
+                    ok[j] = live & inside(v, p);
+                    gather<T, IDX>(vol, v, p, g[j]);
+                    more = live;
+                }
+                group_fence();
+#pragma unroll
+                for (int j = 0; j < kGroup; ++j) composite(s, lerp3(g[j]), ok[j], acc);
+                if (!more) break;
             }
         } else if (ACCEL == ESK_ACCEL_GRID) {
             const int sh = ra.vol.log2B, B = ra.vol.B;
-            const int nbx = ra.vol.nb[0], nby = ra.vol.nb[1];
+            const uint32_t nbx = (uint32_t)ra.vol.nb[0] & 0x7ffu, nby = (uint32_t)ra.vol.nb[1] & 0x7ffu;
             int k = 0;
             while (true) {
                 const float t = lattice_t(r, dt, k);
@@ -372,16 +470,35 @@ __device__ inline void render_tile(const RenderArgs &ra, int tbx, int tby)
                 point_at(r, t, p);
                 if (!inside(v, p)) { ++k; continue; }
                 const int bx = (int)p[0] >> sh, by = (int)p[1] >> sh, bz = (int)p[2] >> sh;
-                const int64_t b = (int64_t)bx + (int64_t)nbx * ((int64_t)by + (int64_t)nby * bz);
+                // < 2^28 bricks, at most 1024 per axis: 32-bit, 24-bit multiplies
+                const uint32_t b = (uint32_t)bx + __umul24(nbx, (uint32_t)by + __umul24(nby, (uint32_t)bz));
+                const float blo[3] = {(float)(bx << sh), (float)(by << sh), (float)(bz << sh)};
+                const float bhi[3] = {(float)min((bx << sh) + B, v.n[0]), (float)min((by << sh) + B, v.n[1]),
+                                      (float)min((bz << sh) + B, v.n[2])};
                 if ((ra.grid[b >> 5] >> (b & 31)) & 1u) {
-                    composite(s, trilinear<T, IDX>(vol, v, p), acc);
-                    ++k;
+                    // non-empty macrocell: a group of samples from k; those in
+                    // the cell are consecutive (sample points are monotone per
+                    // component) and start with k, so k advances by their count
+                    Corners g[kGroup];
+                    bool ok[kGroup];
+                    int taken = 0;
+#pragma unroll
+                    for (int j = 0; j < kGroup; ++j) {
+                        const float tj = lattice_t(r, dt, k + j);
+                        float q[3];
+                        point_at(r, tj, q);
+                        ok[j] = (tj < r.tx) & (q[0] >= blo[0]) & (q[0] < bhi[0]) & (q[1] >= blo[1]) &
+                                (q[1] < bhi[1]) & (q[2] >= blo[2]) & (q[2] < bhi[2]);
+                        gather<T, IDX>(vol, v, q, g[j]);
+                        taken += ok[j] ? 1 : 0;
+                    }
+                    group_fence();
+#pragma unroll
+                    for (int j = 0; j < kGroup; ++j) composite(s, lerp3(g[j]), ok[j], acc);
+                    k += taken;
                     continue;
                 }
                 // empty macrocell: jump to the last sample inside it
-                const float blo[3] = {(float)(bx * B), (float)(by * B), (float)(bz * B)};
-                const float bhi[3] = {(float)min(bx * B + B, v.n[0]), (float)min(by * B + B, v.n[1]),
-                                      (float)min(bz * B + B, v.n[2])};
                 float cn, cx;
                 int next = k + 1;
                 slab_fast(r, blo, bhi, cn, cx);
@@ -487,7 +604,7 @@ hipError_t launch_accel(const RenderArgs &r, hipStream_t s)
     const dim3 grid((r.W + 15) / 16, (r.H + 15) / 16);
     const size_t lds = (r.N <= 1024 ? (size_t)r.N * sizeof(float4) : 0) +
                        (size_t)r.stack_cap * 256 * sizeof(int);
-    const int64_t nbytes = (int64_t)r.vol.nq[0] * r.vol.nq[1] * r.vol.nq[2] * 512 * (int64_t)sizeof(T);
+    const int64_t nbytes = swz_bytes(r.vol.nq, (int)sizeof(T));
     const bool narrow = nbytes < (int64_t)0xffffffffLL;
     const bool tfl = r.N <= 1024;
     const void *fn;

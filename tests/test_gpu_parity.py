@@ -287,3 +287,55 @@ def test_c2_full_size_sampled():
                 full = img
             else:
                 assert np.array_equal(img, full), (i, accel)
+
+
+@pytest.mark.parametrize("dims,B,dtype,seed", [
+    ((45, 38, 29), 8, np.uint8, 0),
+    ((52, 33, 41), 4, np.float32, 1),
+    ((70, 64, 36), 16, np.float16, 2),
+])
+def test_per_voxel_vote(dims, B, dtype, seed):
+    """The per-voxel vote (Sec. 3.1): flags bit-exact against the oracle's
+    vote, hierarchies built from them exact, and skipped renders equal to the
+    oracle's render that skips the same bricks (the vote is not conservative,
+    so they may differ from the full march)."""
+    torch = _torch()
+    log(f"case: vote {dims} B={B} {np.dtype(dtype).name}")
+    base = synth.blobs_u8(dims, seed=90 + seed, n_blobs=6, cut=40)
+    vol = base if dtype == np.uint8 else (base.astype(np.float64) / 255.0).astype(dtype)
+    tf = synth.tf_random(seed + 40, 256)
+    esk, ctx = make_ctx()
+    ctx.set_volume(to_dev(vol), B, max_tf=256)
+    ctx.set_tf(to_dev(tf), build=("grid", "lbvh", "kd"), kd=esk.Kd(1, 0, 4), classify="voxel")
+    torch.cuda.synchronize()
+    v = oracle.vote(vol, B, tf)
+    assert np.array_equal(ctx.export("flags"), v)
+    mn, mx = oracle.brick_minmax(vol, B)
+    assert np.all(v <= oracle.classify(mn, mx, vol.dtype, tf))
+    ids = oracle.compact(v)
+    assert np.array_equal(ctx.export("ids"), ids)
+    nb = oracle.brick_grid(dims, B)
+    sk, si = oracle.sort_pairs(oracle.morton_keys(ids, nb[0], nb[1]), ids)
+    t = oracle.lbvh(sk, si, B, dims)
+    for name in ("left", "right", "lo", "hi"):
+        assert np.array_equal(ctx.export("lbvh_" + name), t[name]), name
+    k = oracle.kd(v, B, dims, 1, 0)
+    for name in ("lo", "hi", "axis", "plane"):
+        assert np.array_equal(ctx.export("kd_" + name), k[name]), name
+    W, H = 64, 48
+    cam = synth.perspective(dims, W, H, synth.view_direction(seed + 7))
+    ref, ref_cnt = oracle.render(vol, tf, cam, W, H, mode=1, flags=v, B=B, with_counts=True)
+    full = oracle.render(vol, tf, cam, W, H)
+    for accel in ("grid", "lbvh", "kd"):
+        cnt = torch.empty((H, W), dtype=torch.int32, device="cuda")
+        img = ctx.render(cam, W, H, accel=accel, counts=cnt)
+        torch.cuda.synchronize()
+        img, cnt = img.cpu().numpy().astype(np.float64), cnt.cpu().numpy()
+        assert np.abs(img - ref).max() <= TOL, accel
+        if accel == "grid":
+            assert np.array_equal(cnt, ref_cnt)
+        else:
+            assert np.all(cnt >= ref_cnt)
+    log(f"  vote flags {int(v.sum())} of {v.size} bricks (min/max: "
+        f"{int(oracle.classify(mn, mx, vol.dtype, tf).sum())}); max|vote render - full march| "
+        f"{np.abs(ref - full).max():.2e}")
