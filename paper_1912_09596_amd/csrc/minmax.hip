@@ -252,35 +252,42 @@ hipError_t launch_typed(const VolumeDesc &v, void *minv, void *maxv, hipStream_t
 // (fixed qy, qz); threads stream voxel rows of the 8 x 8 slab coalesced and
 // write each voxel to its block.  Padding voxels (past the volume) are zero
 // and never sampled (the sampler clamps indices to the volume).
+// The blocked copy, one workgroup per run of up to 8 blocks along x of one
+// (block row, block slab): the 64 voxel rows of the run (plus the apron
+// voxel) are read with coalesced loads into LDS, then the blocks are written
+// out as one contiguous stretch, so every cache line of the copy is written
+// whole.
+constexpr int kSwzRun = 8;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_swizzle(const T *__restrict__ vol, int nx, int ny, int nz, int nqx,
                                                  int nqy, T *__restrict__ swz)
 {
     constexpr int ROW = swz_row((int)sizeof(T));
-    const int qy = blockIdx.x % nqy, qz = blockIdx.x / nqy;
-    const int slots = nqx * ROW;
-    const size_t row_blocks = ((size_t)qz * nqy + qy) * nqx;
-    for (int r = 0; r < 64; ++r) {
-        const int zl = r >> 3, yl = r & 7;
-        const int y = qy * 8 + yl, z = qz * 8 + zl;
-        const bool in = (y < ny) && (z < nz);
-        const T *src = vol + ((size_t)z * ny + y) * (size_t)nx;
-        for (int i = threadIdx.x; i < slots; i += 256) {
-            // slot i: element xi of the row in block qx (xi == 8: the apron voxel)
-            const int qx = i / ROW, xi = i - qx * ROW;
-            const int x = qx * 8 + xi;
-            const T val = (in && x < nx) ? src[x] : (T)0;
-            swz[(row_blocks + (size_t)qx) * (64 * ROW) + r * ROW + xi] = val;
-        }
+    constexpr int W = kSwzRun * 8 + 1;   // staged voxels per row
+    __shared__ T tile[64 * W];
+    const int qx0 = blockIdx.x * kSwzRun, qy = blockIdx.y, qz = blockIdx.z;
+    const int nblk = min(kSwzRun, nqx - qx0);
+    for (int i = threadIdx.x; i < 64 * W; i += 256) {
+        const int r = i / W, xi = i - r * W;
+        const int x = qx0 * 8 + xi, y = qy * 8 + (r & 7), z = qz * 8 + (r >> 3);
+        tile[i] = (x < nx && y < ny && z < nz) ? vol[((size_t)z * ny + y) * (size_t)nx + x] : (T)0;
+    }
+    __syncthreads();
+    T *out = swz + (((size_t)qz * nqy + qy) * nqx + qx0) * (64 * ROW);
+    for (int i = threadIdx.x; i < nblk * 64 * ROW; i += 256) {
+        const int b = i / (64 * ROW), rem = i - b * (64 * ROW);
+        const int r = rem / ROW, xi = rem - r * ROW;
+        out[i] = tile[r * W + b * 8 + xi];
     }
 }
 
 template <typename T>
 hipError_t launch_swz_typed(const VolumeDesc &v, void *swz, hipStream_t s)
 {
-    const int64_t blocks = (int64_t)v.nq[1] * v.nq[2];
-    hipLaunchKernelGGL((k_swizzle<T>), dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const T *>(v.vox), v.nx,
-                       v.ny, v.nz, v.nq[0], v.nq[1], static_cast<T *>(swz));
+    const dim3 grid((unsigned)((v.nq[0] + kSwzRun - 1) / kSwzRun), (unsigned)v.nq[1], (unsigned)v.nq[2]);
+    hipLaunchKernelGGL((k_swizzle<T>), grid, dim3(256), 0, s, static_cast<const T *>(v.vox), v.nx, v.ny, v.nz,
+                       v.nq[0], v.nq[1], static_cast<T *>(swz));
     return hipGetLastError();
 }
 
