@@ -366,6 +366,78 @@ def serving(esk, torch, n_req=400, rate=200.0, seed=6):
     return out
 
 
+# --------------------------------------------------------------------------
+# profile summaries (no GPU): markdown tables from rocprofv3 result databases
+# --------------------------------------------------------------------------
+
+def _short_kernel(name):
+    short = name.replace("esk::(anonymous namespace)::", "").replace("void ", "")
+    short = short.split("(esk::")[0].split("(float const*")[0].split("(unsigned int*")[0]
+    if "at::native" in short:
+        short = short.split("<")[0] + " (torch)"
+    return short
+
+
+def trace_markdown(db, command):
+    """Kernel-trace table (calls, total and average duration, resources)."""
+    import sqlite3
+    c = sqlite3.connect(db)
+    rows = list(c.execute("select name, total_calls, total_duration, average, percentage from top_kernels"))
+    regs = {r[0]: r[1:] for r in c.execute("select name, vgpr_count, sgpr_count, lds_size, scratch_size from kernels")}
+    out = ["# Kernel trace: 512^3 f32 noise volume, 1920x1080, grid + LBVH + k-d per TF", "",
+           "Command (from the repository root on the MI355X box):", "", "```", command, "```", "",
+           "| kernel | calls | total ms | avg us | % | VGPR | SGPR | LDS B | scratch B |",
+           "|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for name, n, tot, avg, pct in rows:
+        if pct < 0.05:
+            continue
+        r = regs.get(name, ("", "", "", ""))
+        # the view reports durations in microseconds
+        out.append(f"| `{_short_kernel(name)[:70]}` | {n} | {tot / 1e3:.2f} | {avg:.1f} | {pct:.1f} | "
+                   f"{r[0]} | {r[1]} | {r[2]} | {r[3]} |")
+    return "\n".join(out)
+
+
+def counters_markdown(fetch_db, write_db, command):
+    """HBM traffic per launch from FETCH_SIZE and WRITE_SIZE runs (KiB per
+    dispatch), each scaled by what the counter reads for the 512 MiB device
+    copy the runs start with (--copy-probe)."""
+    import collections
+    import hashlib
+    import sqlite3
+
+    def load(db, counter):
+        c = sqlite3.connect(db)
+        per = collections.defaultdict(list)
+        for k, v in c.execute("select kernel_name, value from counters_collection where counter_name = ?",
+                              (counter,)):
+            per[k].append(v)
+        return per
+
+    fetch, write = load(fetch_db, "FETCH_SIZE"), load(write_db, "WRITE_SIZE")
+    probe_kib = float(512 * 1024)
+    copy_f = max(v for k, vs in fetch.items() if "copyBuffer" in k for v in vs)
+    copy_w = max(v for k, vs in write.items() if "copyBuffer" in k for v in vs)
+    sf, sw = probe_kib / copy_f, probe_kib / copy_w
+    src = hashlib.sha256(open(RENDER_SRC, "rb").read()).hexdigest()
+    out = ["# HBM traffic per launch: 512^3 f32 noise volume, 1920x1080, grid + LBVH + k-d per TF", "",
+           "Commands (from the repository root on the MI355X box; one counter per run):", "", "```", command, "```",
+           "", f"render.hip sha256: {src}", "",
+           f"Copy probe (one plain 512 MiB device copy): FETCH_SIZE reads {copy_f:.0f} KiB, WRITE_SIZE "
+           f"{copy_w:.0f} KiB of 524288 KiB moved, so FETCH_SIZE is scaled by {sf:.3f} and WRITE_SIZE by "
+           f"{sw:.3f}.", "",
+           "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes per launch |",
+           "|---|---:|---:|---:|---:|"]
+    for k in fetch:
+        if k not in write or "copyBuffer" in k or "fillBuffer" in k:
+            continue
+        f = statistics.mean(fetch[k])
+        w = statistics.mean(write[k])
+        out.append(f"| `{_short_kernel(k)[:70]}` | {len(fetch[k])} | {f:.0f} | {w:.0f} | "
+                   f"{int(round((f * sf + w * sw) * 1024))} |")
+    return "\n".join(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -377,9 +449,19 @@ def main():
     ap.add_argument("--no-stats", action="store_true", help="skip the node/height statistics table")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 512 MiB device copy first (reference for HBM counters)")
+    ap.add_argument("--trace-md", nargs=2, metavar=("DB", "COMMAND"),
+                    help="print the kernel-trace summary of a rocprofv3 database and exit")
+    ap.add_argument("--counters-md", nargs=3, metavar=("FETCH_DB", "WRITE_DB", "COMMAND"),
+                    help="print the HBM traffic summary of two rocprofv3 --pmc databases and exit")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--cpu-stride", type=int, default=1)
     args = ap.parse_args()
+    if args.trace_md:
+        print(trace_markdown(*args.trace_md))
+        return
+    if args.counters_md:
+        print(counters_markdown(*args.counters_md))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (run with --gpus 1)",
               file=sys.stderr)
