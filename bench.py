@@ -228,6 +228,9 @@ def large_volumes(esk, torch, reps=3):
             img = torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
             render = {a: ev_ms(lambda a=a: ctx.render(cam, W, H, accel=a, out=img)) for a in ACCELS + ("none",)}
             st = ctx.stats()
+            ctx.set_tf(tf, build=("kd",), kd=esk.Kd(0, 0, 4))
+            for a in ("kd", "hybrid"):
+                render[a + "_shallow"] = ev_ms(lambda a=a: ctx.render(cam, W, H, accel=a, out=img))
             rec.update({"rebuild_ms": rebuild, "render_ms": render,
                         "render_mrays_per_s": {a: round(W * H / v / 1e3, 1) for a, v in render.items()},
                         "bricks_nonempty": st["n_nonempty"], "bricks": st["n_bricks"],
@@ -559,6 +562,19 @@ def main():
         torch.cuda.synchronize()
         naive.append(e0.elapsed_time(e1))
     st = ctx.stats()
+    # the hybrid grid (Sec. 3.3): a shallow k-d tree, the macrocell grid inside its leaves
+    shallow = {}
+    ctx.set_tf(dtfs[j], build=("kd",), kd=esk.Kd(0, 0, 4))
+    for a in ("kd", "hybrid"):
+        times = []
+        for _ in range(3):
+            e0.record(stream)
+            ctx.render(cams[j], W, H, accel=a, out=outs["lbvh"])
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        shallow[a + "_render_ms"] = round(statistics.median(times), 4)
+    shallow["kd_nodes"] = ctx.stats()["kd_nodes"]
 
     mean_ms = {a: statistics.mean(render_ms[a]) for a in ACCELS}
     dominant = max(ACCELS, key=lambda a: mean_ms[a])
@@ -595,6 +611,7 @@ def main():
             "samples_per_frame": samples,
             "bricks_nonempty": st["n_nonempty"], "lbvh_nodes": st["lbvh_nodes"],
             "lbvh_height": st["lbvh_height"], "kd_nodes": st["kd_nodes"], "kd_height": st["kd_height"],
+            "shallow_kd_and_hybrid": shallow,
         },
         "roofline": {"kernel": f"k_render<{dominant}>", "bound": "alu", "achieved": round(achieved, 3),
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",

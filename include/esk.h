@@ -64,7 +64,10 @@ typedef enum {
     ESK_ACCEL_NONE = 0, /* full march, no skipping (the paper's "naive" column) */
     ESK_ACCEL_GRID = 1, /* uniform macrocell grid, macrocell = brick (Sec. 1) */
     ESK_ACCEL_LBVH = 2, /* LBVH over non-empty bricks (Sec. 3.1) */
-    ESK_ACCEL_KD = 4    /* binned k-d tree over brick occupancy (Sec. 3.2.2, 4.3) */
+    ESK_ACCEL_KD = 4,   /* binned k-d tree over brick occupancy (Sec. 3.2.2, 4.3) */
+    ESK_ACCEL_HYBRID = 8 /* render only: traverse the k-d tree (built with ESK_ACCEL_KD,
+                            typically shallow) and march each leaf with the macrocell
+                            grid, skipping its empty bricks (the hybrid grid, Sec. 3.3) */
 } esk_accel;
 
 /* Classification mode, OR-ed into the build mask of

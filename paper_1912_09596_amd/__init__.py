@@ -22,9 +22,11 @@ LIB_PATH = os.path.join(_HERE, "libesk.so")
 
 OK, EINVAL, ENOSPC, ELIMIT, EDEVICE, ESTATE, EINTERNAL = 0, -1, -2, -3, -4, -5, -6
 U8, U16, F16, F32 = 0, 1, 2, 3
-NONE, GRID, LBVH, KD = 0, 1, 2, 4
+NONE, GRID, LBVH, KD, HYBRID = 0, 1, 2, 4, 8
 CLASSIFY_VOXEL = 0x100      # build-mask bit: per-voxel vote instead of brick min/max
-ACCEL = {"none": NONE, "grid": GRID, "lbvh": LBVH, "kd": KD}
+ACCEL = {"none": NONE, "grid": GRID, "lbvh": LBVH, "kd": KD, "hybrid": HYBRID}
+# what a rebuild must build for each render mode (the hybrid grid renders the k-d tree + grid)
+BUILD = {"grid": GRID, "lbvh": LBVH, "kd": KD, "hybrid": KD}
 LEAF = 0x80000000
 
 EXPORTS = {
@@ -203,7 +205,7 @@ class Context:
             raise ValueError("classify must be 'minmax' or 'voxel'")
         mask = CLASSIFY_VOXEL if classify == "voxel" else 0
         for b in build:
-            mask |= ACCEL[b]
+            mask |= BUILD[b]
         kp = None
         if mask & KD:
             kd = kd or Kd()

@@ -523,7 +523,8 @@ esk_status esk_set_transfer_function(esk_ctx *c, const float *d_rgba, int n_entr
         c->kd_on_device = true;
         c->kd_joined = false;
     }
-    c->built = build_mask & (ESK_ACCEL_GRID | ESK_ACCEL_LBVH | ESK_ACCEL_KD);
+    // classification always writes the grid bitmask
+    c->built = (build_mask & (ESK_ACCEL_LBVH | ESK_ACCEL_KD)) | ESK_ACCEL_GRID;
     c->has_tf = true;
     return ESK_OK;
 }
@@ -537,7 +538,8 @@ static esk_status prepare_render(esk_ctx *c, int accel, const esk_camera *cam, i
 {
     if (!c) return ESK_EINVAL;
     if (!cam) return fail(c, ESK_EINVAL, "camera is null");
-    if (accel != ESK_ACCEL_NONE && accel != ESK_ACCEL_GRID && accel != ESK_ACCEL_LBVH && accel != ESK_ACCEL_KD)
+    if (accel != ESK_ACCEL_NONE && accel != ESK_ACCEL_GRID && accel != ESK_ACCEL_LBVH && accel != ESK_ACCEL_KD &&
+        accel != ESK_ACCEL_HYBRID)
         return fail(c, ESK_EINVAL, "unknown accel %d", accel);
     if (width < 1 || height < 1 || width > 32768 || height > 32768)
         return fail(c, ESK_EINVAL, "image size %d x %d out of range", width, height);
@@ -552,7 +554,9 @@ static esk_status prepare_render(esk_ctx *c, int accel, const esk_camera *cam, i
         return fail(c, ESK_EINVAL, "count output must be 4-byte aligned");
     if (c->device < 0) return fail(c, ESK_ESTATE, "validation-only context");
     if (!c->has_volume || !c->has_tf) return fail(c, ESK_ESTATE, "render before set_volume/set_transfer_function");
-    if (accel != ESK_ACCEL_NONE && !(c->built & accel))
+    // the hybrid mode traverses the k-d tree and reads the grid (always built)
+    const int needs = accel == ESK_ACCEL_HYBRID ? (int)ESK_ACCEL_KD : accel;
+    if (accel != ESK_ACCEL_NONE && !(c->built & needs))
         return fail(c, ESK_ESTATE, "accel %d was not built by the last rebuild", accel);
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_check(c, e, "hipSetDevice");
@@ -584,7 +588,7 @@ static esk_status prepare_render(esk_ctx *c, int accel, const esk_camera *cam, i
     if (accel == ESK_ACCEL_LBVH)
         r.stack_cap = std::max(1, 3 * std::max({bits_for(c->vol.nb[0]), bits_for(c->vol.nb[1]),
                                                 bits_for(c->vol.nb[2])}));
-    if (accel == ESK_ACCEL_KD) {
+    if (accel == ESK_ACCEL_KD || accel == ESK_ACCEL_HYBRID) {
         esk_status st = kd_finish(c);
         if (st != ESK_OK) return st;
         if ((int)c->kd_height > kMaxKdStack)

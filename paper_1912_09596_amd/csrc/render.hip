@@ -18,6 +18,9 @@
 //    plane, so leaves come out in sample order).  For each leaf, a
 //    conservative k range comes from an expanded slab test and each sample is
 //    kept iff its point lies inside the leaf's box (half-open).
+//  - HYBRID (Sec. 3.3): the KD traversal, but inside each leaf the samples
+//    are marched with the GRID rule restricted to the leaf's box and k range,
+//    so exactly the samples of non-empty bricks are composited.
 //
 // Geometry (ray set-up, slabs, t_k, p_k, membership) is FP32 without
 // contraction: the whole file is compiled with -ffp-contract=off, and the
@@ -278,9 +281,103 @@ __device__ inline bool hit_box(const Ray &r, float dt, const int lo[3], const in
     return tn <= tf + dt && tf >= r.t0 - dt && tn <= r.tx + dt;
 }
 
-// samples of the lattice that fall in the leaf box [lo, hi)
+struct GridRef {
+    const uint32_t *bits;   // one bit per brick, linear brick id
+    int sh, B;              // log2 of the brick edge, brick edge
+    uint32_t nbx, nby;      // bricks along x and y
+    int n[3];
+};
+
+__device__ inline GridRef grid_ref(const RenderArgs &ra)
+{
+    GridRef g;
+    g.bits = ra.grid;
+    g.sh = ra.vol.log2B;
+    g.B = ra.vol.B;
+    // < 2^28 bricks, at most 1024 per axis: 32-bit ids, 24-bit multiplies
+    g.nbx = (uint32_t)ra.vol.nb[0] & 0x7ffu;
+    g.nby = (uint32_t)ra.vol.nb[1] & 0x7ffu;
+    g.n[0] = ra.vol.nx;
+    g.n[1] = ra.vol.ny;
+    g.n[2] = ra.vol.nz;
+    return g;
+}
+
+// Macrocell-grid march (macrocell = brick) over the samples k in [k, k_end)
+// whose points lie in the box [lo, hi) of the volume: a sample in an empty
+// brick jumps to the last sample inside that brick (sample points are
+// monotone per component, so every sample between lies in the brick too);
+// in a non-empty brick a group of samples from k is composited, and those
+// in the brick (and the box) are consecutive and start with k, so k
+// advances by their count.  The whole ray with the volume as the box is the
+// grid accelerator; a k-d leaf's sample range and box is the hybrid grid.
 template <typename T, typename IDX>
-__device__ inline void march_leaf(const Ray &r, float dt, const int lo[3], const int hi[3],
+__device__ inline void march_grid(const Ray &r, float dt, int k, int k_end, const float lo[3], const float hi[3],
+                                  const GridRef &gr, const T *__restrict__ vol, const Vol &v, const Shade &s,
+                                  Accum &acc)
+{
+    const int sh = gr.sh, B = gr.B;
+    while (k < k_end) {
+        const float t = lattice_t(r, dt, k);
+        if (!(t < r.tx)) break;
+        float p[3];
+        point_at(r, t, p);
+        if (!((p[0] >= lo[0]) & (p[0] < hi[0]) & (p[1] >= lo[1]) & (p[1] < hi[1]) & (p[2] >= lo[2]) &
+              (p[2] < hi[2]))) {
+            ++k;
+            continue;
+        }
+        const int bx = (int)p[0] >> sh, by = (int)p[1] >> sh, bz = (int)p[2] >> sh;
+        const uint32_t b = (uint32_t)bx + __umul24(gr.nbx, (uint32_t)by + __umul24(gr.nby, (uint32_t)bz));
+        const float blo[3] = {(float)(bx << sh), (float)(by << sh), (float)(bz << sh)};
+        const float bhi[3] = {(float)min((bx << sh) + B, gr.n[0]), (float)min((by << sh) + B, gr.n[1]),
+                              (float)min((bz << sh) + B, gr.n[2])};
+        if ((gr.bits[b >> 5] >> (b & 31)) & 1u) {
+            const float ml[3] = {fmaxf(blo[0], lo[0]), fmaxf(blo[1], lo[1]), fmaxf(blo[2], lo[2])};
+            const float mh[3] = {fminf(bhi[0], hi[0]), fminf(bhi[1], hi[1]), fminf(bhi[2], hi[2])};
+            Corners g[kGroup];
+            bool ok[kGroup];
+            int taken = 0;
+#pragma unroll
+            for (int j = 0; j < kGroup; ++j) {
+                const float tj = lattice_t(r, dt, k + j);
+                float q[3];
+                point_at(r, tj, q);
+                ok[j] = (k + j < k_end) & (tj < r.tx) & (q[0] >= ml[0]) & (q[0] < mh[0]) & (q[1] >= ml[1]) &
+                        (q[1] < mh[1]) & (q[2] >= ml[2]) & (q[2] < mh[2]);
+                gather<T, IDX>(vol, v, q, g[j]);
+                taken += ok[j] ? 1 : 0;
+            }
+            group_fence();
+#pragma unroll
+            for (int j = 0; j < kGroup; ++j) composite(s, lerp3(g[j]), ok[j], acc);
+            k += taken;
+            continue;
+        }
+        // empty macrocell: jump to the last sample inside it
+        float cn, cx;
+        int next = k + 1;
+        slab_fast(r, blo, bhi, cn, cx);
+        float fj = (cx - r.t0) * __builtin_amdgcn_rcpf(dt) - 0.5f;
+        fj = fminf(fmaxf(fj, -4.0f), 1.0e9f);
+        const int kj = (int)floorf(fj);
+        for (int c = kj; c >= kj - 1; --c) {
+            if (c <= k) break;
+            float q[3];
+            point_at(r, lattice_t(r, dt, c), q);
+            if (inside(v, q) && ((int)q[0] >> sh) == bx && ((int)q[1] >> sh) == by && ((int)q[2] >> sh) == bz) {
+                next = c + 1;
+                break;
+            }
+        }
+        k = next;
+    }
+}
+
+// samples of the lattice that fall in the leaf box [lo, hi); HYB: only
+// those in non-empty bricks, found with the macrocell grid (hybrid grid)
+template <typename T, typename IDX, bool HYB>
+__device__ inline void march_leaf(const Ray &r, float dt, const int lo[3], const int hi[3], const GridRef &gr,
                                   const T *__restrict__ vol, const Vol &v, const Shade &s, Accum &acc)
 {
     float l[3], h[3], bl[3], bh[3];
@@ -300,6 +397,10 @@ __device__ inline void march_leaf(const Ray &r, float dt, const int lo[3], const
     fb = fminf(fmaxf(fb, -4.0f), 1.0e9f);
     const int ka = max(0, (int)floorf(fa) - 1);
     const int kb = (int)floorf(fb) + 2;
+    if constexpr (HYB) {
+        march_grid<T, IDX>(r, dt, ka, kb, bl, bh, gr, vol, v, s, acc);
+        return;
+    }
     for (int k = ka; k < kb; k += kGroup) {
         // a group of consecutive samples: every gather is issued before the
         // first value is composited (the clamped addresses are valid for
@@ -339,9 +440,9 @@ __device__ inline void unpack_box(uint32_t w0, uint32_t w1, uint32_t w2, int lo[
 // k-d): near child first by the sign of the direction along the node's
 // split axis, far child on an LDS stack (lane-interleaved), leaves marched
 // in the order they are reached.  Popped leaves fetch their packed box.
-template <typename T, typename IDX>
+template <typename T, typename IDX, bool HYB>
 __device__ inline void traverse(const Ray &r, float dt, const RNode *__restrict__ nodes,
-                                const uint4 *__restrict__ leafbox, uint32_t root, int lo[3], int hi[3],
+                                const uint4 *__restrict__ leafbox, const GridRef &gr, uint32_t root, int lo[3], int hi[3],
                                 int *stk, int cap, const T *__restrict__ vol, const Vol &v, const Shade &s,
                                 Accum &acc)
 {
@@ -350,7 +451,7 @@ __device__ inline void traverse(const Ray &r, float dt, const RNode *__restrict_
     int sp = 0;
     while (true) {
         if (cur & kLeaf) {
-            march_leaf<T, IDX>(r, dt, lo, hi, vol, v, s, acc);
+            march_leaf<T, IDX, HYB>(r, dt, lo, hi, gr, vol, v, s, acc);
         } else {
             const uint4 *q = reinterpret_cast<const uint4 *>(&nodes[cur & kIndexMask]);
             const uint4 A = q[0], Q = q[1];
@@ -460,80 +561,24 @@ __device__ inline void render_tile(const RenderArgs &ra, int tbx, int tby)
                 if (!more) break;
             }
         } else if (ACCEL == ESK_ACCEL_GRID) {
-            const int sh = ra.vol.log2B, B = ra.vol.B;
-            const uint32_t nbx = (uint32_t)ra.vol.nb[0] & 0x7ffu, nby = (uint32_t)ra.vol.nb[1] & 0x7ffu;
-            int k = 0;
-            while (true) {
-                const float t = lattice_t(r, dt, k);
-                if (!(t < r.tx)) break;
-                float p[3];
-                point_at(r, t, p);
-                if (!inside(v, p)) { ++k; continue; }
-                const int bx = (int)p[0] >> sh, by = (int)p[1] >> sh, bz = (int)p[2] >> sh;
-                // < 2^28 bricks, at most 1024 per axis: 32-bit, 24-bit multiplies
-                const uint32_t b = (uint32_t)bx + __umul24(nbx, (uint32_t)by + __umul24(nby, (uint32_t)bz));
-                const float blo[3] = {(float)(bx << sh), (float)(by << sh), (float)(bz << sh)};
-                const float bhi[3] = {(float)min((bx << sh) + B, v.n[0]), (float)min((by << sh) + B, v.n[1]),
-                                      (float)min((bz << sh) + B, v.n[2])};
-                if ((ra.grid[b >> 5] >> (b & 31)) & 1u) {
-                    // non-empty macrocell: a group of samples from k; those in
-                    // the cell are consecutive (sample points are monotone per
-                    // component) and start with k, so k advances by their count
-                    Corners g[kGroup];
-                    bool ok[kGroup];
-                    int taken = 0;
-#pragma unroll
-                    for (int j = 0; j < kGroup; ++j) {
-                        const float tj = lattice_t(r, dt, k + j);
-                        float q[3];
-                        point_at(r, tj, q);
-                        ok[j] = (tj < r.tx) & (q[0] >= blo[0]) & (q[0] < bhi[0]) & (q[1] >= blo[1]) &
-                                (q[1] < bhi[1]) & (q[2] >= blo[2]) & (q[2] < bhi[2]);
-                        gather<T, IDX>(vol, v, q, g[j]);
-                        taken += ok[j] ? 1 : 0;
-                    }
-                    group_fence();
-#pragma unroll
-                    for (int j = 0; j < kGroup; ++j) composite(s, lerp3(g[j]), ok[j], acc);
-                    k += taken;
-                    continue;
-                }
-                // empty macrocell: jump to the last sample inside it
-                float cn, cx;
-                int next = k + 1;
-                slab_fast(r, blo, bhi, cn, cx);
-                {
-                    float fj = (cx - r.t0) * __builtin_amdgcn_rcpf(dt) - 0.5f;
-                    fj = fminf(fmaxf(fj, -4.0f), 1.0e9f);
-                    const int kj = (int)floorf(fj);
-                    for (int c = kj; c >= kj - 1; --c) {
-                        if (c <= k) break;
-                        float q[3];
-                        point_at(r, lattice_t(r, dt, c), q);
-                        if (inside(v, q) && ((int)q[0] >> sh) == bx && ((int)q[1] >> sh) == by &&
-                            ((int)q[2] >> sh) == bz) {
-                            next = c + 1;
-                            break;
-                        }
-                    }
-                }
-                k = next;
-            }
+            const float zero3[3] = {0.0f, 0.0f, 0.0f};
+            march_grid<T, IDX>(r, dt, 0, 1 << 30, zero3, v.fn, grid_ref(ra), vol, v, s, acc);
         } else if (ACCEL == ESK_ACCEL_LBVH) {
             const int N = (int)ra.hdr->n;
             if (N > 0) {
                 int lo[3], hi[3];
                 for (int a = 0; a < 3; ++a) { lo[a] = ra.lb_lo[a]; hi[a] = ra.lb_hi[a]; }
-                traverse<T, IDX>(r, dt, ra.lb_rnode, ra.lb_leafbox, N == 1 ? kLeaf : 0u, lo, hi, stk,
+                traverse<T, IDX, false>(r, dt, ra.lb_rnode, ra.lb_leafbox, grid_ref(ra), N == 1 ? kLeaf : 0u, lo, hi, stk,
                                  ra.stack_cap, vol, v, s, acc);
             }
-        } else if (ACCEL == ESK_ACCEL_KD) {
+        } else if (ACCEL == ESK_ACCEL_KD || ACCEL == ESK_ACCEL_HYBRID) {
             const int M = (int)ra.hdr->kd_count;
             if (M > 0) {
                 int lo[3], hi[3];
                 const uint4 b = ra.kd_box[0];
                 unpack_box(b.x, b.y, b.z, lo, hi);
-                traverse<T, IDX>(r, dt, ra.kd_rnode, ra.kd_box, M == 1 ? kLeaf : 0u, lo, hi, stk,
+                traverse<T, IDX, ACCEL == ESK_ACCEL_HYBRID>(r, dt, ra.kd_rnode, ra.kd_box, grid_ref(ra),
+                                                            M == 1 ? kLeaf : 0u, lo, hi, stk,
                                  ra.stack_cap, vol, v, s, acc);
             }
         }
@@ -594,6 +639,7 @@ hipError_t launch_batch_typed(int accel, const RenderArgs *d_args, const dim3 &g
     case ESK_ACCEL_GRID: return launch_batch_accel<ESK_ACCEL_GRID, T>(d_args, grid, lds, narrow, tfl, s);
     case ESK_ACCEL_LBVH: return launch_batch_accel<ESK_ACCEL_LBVH, T>(d_args, grid, lds, narrow, tfl, s);
     case ESK_ACCEL_KD: return launch_batch_accel<ESK_ACCEL_KD, T>(d_args, grid, lds, narrow, tfl, s);
+    case ESK_ACCEL_HYBRID: return launch_batch_accel<ESK_ACCEL_HYBRID, T>(d_args, grid, lds, narrow, tfl, s);
     }
     return hipErrorInvalidValue;
 }
@@ -636,6 +682,7 @@ hipError_t launch_typed(int accel, const RenderArgs &r, hipStream_t s)
     case ESK_ACCEL_GRID: return launch_accel<ESK_ACCEL_GRID, T>(r, s);
     case ESK_ACCEL_LBVH: return launch_accel<ESK_ACCEL_LBVH, T>(r, s);
     case ESK_ACCEL_KD: return launch_accel<ESK_ACCEL_KD, T>(r, s);
+    case ESK_ACCEL_HYBRID: return launch_accel<ESK_ACCEL_HYBRID, T>(r, s);
     }
     return hipErrorInvalidValue;
 }

@@ -31,7 +31,7 @@ def make_requests(count, seed):
     return reqs
 
 
-@pytest.mark.parametrize("accel", ["lbvh", "grid", "kd", "none"])
+@pytest.mark.parametrize("accel", ["lbvh", "grid", "kd", "hybrid", "none"])
 def test_batched_equals_alone(accel):
     torch = _torch()
     import paper_1912_09596_amd as esk

@@ -98,7 +98,7 @@ def check_images(ctx, vol, tf, cam, W, H, flags, B, lo=0.0, hi=1.0, dt=0.5, ref=
     _, skip_cnt = oracle.render(vol, tf, cam, W, H, dt, ref, lo, hi, mode=1, flags=flags, B=B,
                                 with_counts=True)
     imgs = {}
-    for accel in ("none", "grid", "lbvh", "kd"):
+    for accel in ("none", "grid", "lbvh", "kd", "hybrid"):
         cnt = torch.empty((H, W), dtype=torch.int32, device="cuda")
         img = ctx.render(cam, W, H, accel=accel, step=dt, ref=ref, counts=cnt)
         torch.cuda.synchronize()
@@ -107,12 +107,14 @@ def check_images(ctx, vol, tf, cam, W, H, flags, B, lo=0.0, hi=1.0, dt=0.5, ref=
         assert err <= TOL, (label, accel, err)
         if accel == "none":
             assert np.array_equal(cnt, ref_cnt), (label, "sample set differs from the oracle")
-        elif accel in ("grid", "lbvh"):
+        elif accel in ("grid", "lbvh", "hybrid"):
+            # exactly the samples of non-empty bricks: the grid (also inside
+            # the hybrid's k-d leaves) and the LBVH, whose leaves are bricks
             assert np.array_equal(cnt, skip_cnt), (label, accel)
         else:
             assert np.all(cnt >= skip_cnt) and np.all(cnt <= ref_cnt), label
         imgs[accel] = img
-    for accel in ("grid", "lbvh", "kd"):
+    for accel in ("grid", "lbvh", "kd", "hybrid"):
         assert np.array_equal(imgs[accel], imgs["none"]), (label, accel, "skip != full march")
     return imgs
 
@@ -276,7 +278,7 @@ def test_c2_full_size_sampled():
         pix = np.stack([rng.integers(0, W, 400), rng.integers(0, H, 400)], 1).astype(np.int32)
         ref_img, ref_cnt = oracle.render(vol, tf, cam, W, H, pixels=pix, with_counts=True)
         full = None
-        for accel in ("none", "grid", "lbvh", "kd"):
+        for accel in ("none", "grid", "lbvh", "kd", "hybrid"):
             cnt = torch.empty((H, W), dtype=torch.int32, device="cuda")
             img = ctx.render(cam, W, H, accel=accel, counts=cnt).cpu().numpy()
             cnt = cnt.cpu().numpy()
