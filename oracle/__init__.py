@@ -80,7 +80,9 @@ def lib():
         _lib.orc_kd.restype = i64
         _lib.orc_render.argtypes = [P, i32, i32, i32, i32, f32, f32, P, i32,
                                     ctypes.POINTER(Camera), i32, i32, f32, f32, i32, P, i32,
-                                    P, i64, P, P]
+                                    P, i64, P, P, P]
+        _lib.orc_tight_boxes.argtypes = [P, i32, i32, i32, i32, f32, f32, P, i32, i32, P, P]
+        _lib.orc_tight_boxes.restype = i64
         _lib.orc_ray.argtypes = [ctypes.POINTER(Camera), i32, i32, P, P]
         _lib.orc_sample.argtypes = [P, i32, i32, i32, i32, f32, f32, P, i32, P, i64, P]
         _lib.orc_threads.argtypes = []
@@ -149,6 +151,22 @@ def vote(vol, B, tf, lo=0.0, hi=1.0) -> np.ndarray:
     if r < 0:
         raise ValueError("orc_vote failed")
     return flags
+
+
+def tight_boxes(vol, B, tf, flags, lo=0.0, hi=1.0) -> np.ndarray:
+    """Voxel-tight box of every brick, (nb, 6) int32 in half-voxel units
+    (lo2 x, y, z, hi2 x, y, z; the box is [lo2/2, hi2/2)): the bounding box
+    of its potentially visible trilinear cells; all zero when empty."""
+    vol = np.ascontiguousarray(vol)
+    tf = np.ascontiguousarray(tf, dtype=np.float32)
+    flags = np.ascontiguousarray(flags, np.uint8)
+    nz, ny, nx = vol.shape
+    boxes = np.empty((flags.shape[0], 6), np.int32)
+    r = lib().orc_tight_boxes(_p(vol), DTYPE_CODE[vol.dtype], nx, ny, nz, lo, hi, _p(tf), tf.shape[0], B,
+                              _p(flags), _p(boxes))
+    if r < 0:
+        raise ValueError("orc_tight_boxes failed")
+    return boxes
 
 
 def compact(flags) -> np.ndarray:
@@ -222,10 +240,12 @@ def kd(flags, B, dims_xyz, halting=1, max_leaf=0, bins=4):
 
 
 def render(vol, tf, cam: dict, W, H, dt=0.5, ref=1.0, lo=0.0, hi=1.0, mode=0, flags=None, B=0,
-           pixels=None, with_counts=False):
-    """a11-a14: FP64 image of the full march (mode 0) or of the brick-skipping
-    march (mode 1).  pixels: optional (n,2) int array of (x,y) to render one
-    by one; returns (n,4) then, else (H,W,4)."""
+           pixels=None, with_counts=False, boxes=None):
+    """a11-a14: FP64 image of the full march (mode 0), of the brick-skipping
+    march (mode 1: samples of flagged bricks) or of the tight-box march
+    (mode 2: samples inside their flagged brick's tight box, `boxes` as
+    returned by tight_boxes).  pixels: optional (n,2) int array of (x,y) to
+    render one by one; returns (n,4) then, else (H,W,4)."""
     vol = _check_vol(vol)
     nz, ny, nx = vol.shape
     tf = np.ascontiguousarray(tf, dtype=np.float32)
@@ -243,7 +263,8 @@ def render(vol, tf, cam: dict, W, H, dt=0.5, ref=1.0, lo=0.0, hi=1.0, mode=0, fl
     fl = np.ascontiguousarray(flags, np.uint8) if flags is not None else None
     rc = lib().orc_render(_p(vol), DTYPE_CODE[vol.dtype], nx, ny, nz, lo, hi, _p(tf), tf.shape[0],
                           ctypes.byref(c), W, H, dt, ref, mode, _p(fl) if fl is not None else None,
-                          B, pp, npix, _p(out), _p(counts))
+                          B, pp, npix, _p(out), _p(counts),
+                          _p(np.ascontiguousarray(boxes, np.int32)) if boxes is not None else None)
     if rc:
         raise ValueError("orc_render failed")
     return (out, counts) if with_counts else out

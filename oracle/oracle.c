@@ -202,6 +202,82 @@ int64_t orc_vote(const void *vol, int dtype, int nx, int ny, int nz, int B, floa
     return count;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Voxel-tight brick boxes (the GPU k-d variant of Sec. 3.2.2 keeps a tight  */
+/* box per macro cell, recomputed when the TF changes).  A sample point p    */
+/* reads the trilinear cell c = floor(p - 1/2) per axis (its 8 corner voxels */
+/* clamped to the volume), whose region is [c + 1/2, c + 3/2).  A cell is    */
+/* potentially visible iff the classification window of its 8 values holds  */
+/* an entry with alpha > 0 (the brick test above, on the cell's own min/max).*/
+/* A brick's tight box is the bounding box of the regions of its potentially */
+/* visible cells, clipped to the brick, in half-voxel units (lo2, hi2 per    */
+/* axis, the box being [lo2/2, hi2/2)).  Samples outside it read only        */
+/* invisible cells: alpha exactly 0.  Unflagged bricks and bricks without a  */
+/* visible cell get the empty box (all zero).                                */
+/* ------------------------------------------------------------------------ */
+int64_t orc_tight_boxes(const void *vol, int dtype, int nx, int ny, int nz, float lo, float hi, const float *tf,
+                        int N, int B, const uint8_t *flags, int32_t *boxes)
+{
+    if (!vol || !tf || !flags || !boxes || N < 2 || B < 1) return -1;
+    int32_t *P = (int32_t *)malloc(sizeof(int32_t) * (size_t)(N + 1));
+    if (!P) return -1;
+    orc_tf_prefix(tf, N, P);
+    const int n[3] = {nx, ny, nz};
+    const int64_t nb[3] = {ceil_div(nx, B), ceil_div(ny, B), ceil_div(nz, B)};
+    const int64_t total = nb[0] * nb[1] * nb[2];
+    int64_t nonempty = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : nonempty)
+    for (int64_t b = 0; b < total; ++b) {
+        int32_t *box = boxes + 6 * b;
+        for (int a = 0; a < 6; ++a) box[a] = 0;
+        if (!flags[b]) continue;
+        const int bc[3] = {(int)(b % nb[0]), (int)((b / nb[0]) % nb[1]), (int)(b / (nb[0] * nb[1]))};
+        int blo[3], bhi[3], tlo[3], thi[3];
+        for (int a = 0; a < 3; ++a) {
+            blo[a] = bc[a] * B;
+            bhi[a] = blo[a] + B < n[a] ? blo[a] + B : n[a];
+            tlo[a] = 2 * bhi[a];
+            thi[a] = 2 * blo[a];
+        }
+        int any = 0;
+        /* cells whose region [c + 1/2, c + 3/2) meets the brick [blo, bhi) */
+        for (int cz = blo[2] - 1; cz <= bhi[2] - 1; ++cz)
+            for (int cy = blo[1] - 1; cy <= bhi[1] - 1; ++cy)
+                for (int cx = blo[0] - 1; cx <= bhi[0] - 1; ++cx) {
+                    const int c[3] = {cx, cy, cz};
+                    double mn = INFINITY, mx = -INFINITY;
+                    for (int corner = 0; corner < 8; ++corner) {
+                        int q[3];
+                        for (int a = 0; a < 3; ++a) q[a] = clampi(c[a] + ((corner >> a) & 1), 0, n[a] - 1);
+                        const double v =
+                            voxel(vol, dtype, (size_t)q[0] + (size_t)nx * ((size_t)q[1] + (size_t)ny * q[2]));
+                        if (v < mn) mn = v;
+                        if (v > mx) mx = v;
+                    }
+                    int64_t wlo = tf_floor_index(mn, dtype, lo, hi, N) - 1;
+                    int64_t whi = tf_floor_index(mx, dtype, lo, hi, N) + 2;
+                    if (wlo < 0) wlo = 0;
+                    if (whi > N - 1) whi = N - 1;
+                    if (P[whi + 1] - P[wlo] <= 0) continue;
+                    any = 1;
+                    for (int a = 0; a < 3; ++a) {
+                        const int l2 = 2 * c[a] + 1 > 2 * blo[a] ? 2 * c[a] + 1 : 2 * blo[a];
+                        const int h2 = 2 * c[a] + 3 < 2 * bhi[a] ? 2 * c[a] + 3 : 2 * bhi[a];
+                        if (l2 < tlo[a]) tlo[a] = l2;
+                        if (h2 > thi[a]) thi[a] = h2;
+                    }
+                }
+        if (!any) continue;
+        for (int a = 0; a < 3; ++a) {
+            box[a] = tlo[a];
+            box[3 + a] = thi[a];
+        }
+        nonempty += 1;
+    }
+    free(P);
+    return nonempty;
+}
+
 /* a4: compaction -- ids of the non-empty bricks in ascending linear id (Sec. 3.1). */
 int64_t orc_compact(const uint8_t *flags, int64_t nb, uint32_t *ids)
 {
@@ -584,6 +660,7 @@ typedef struct {
     int mode;
     const uint8_t *flags;
     int B, nb[3];
+    const int32_t *boxes;   /* mode 2: tight box per brick, half-voxel units */
 } render_ctx;
 
 /* one pixel: writes RGBA (premultiplied) and returns the number of samples
@@ -614,11 +691,19 @@ static int64_t march_pixel(const render_ctx *r, const orc_camera *cam, int px, i
             if (!(p[a] >= 0.0f && p[a] < bhi[a])) inside = 0;
         }
         if (!inside) continue;
-        if (r->mode == 1) {
+        if (r->mode == 1 || r->mode == 2) {
             int b[3];
             for (int a = 0; a < 3; ++a) b[a] = (int)floorf(p[a]) / r->B;
-            if (!r->flags[(size_t)b[0] + (size_t)r->nb[0] * ((size_t)b[1] + (size_t)r->nb[1] * b[2])])
-                continue;
+            const size_t id = (size_t)b[0] + (size_t)r->nb[0] * ((size_t)b[1] + (size_t)r->nb[1] * b[2]);
+            if (!r->flags[id]) continue;
+            if (r->mode == 2) {
+                /* only samples inside the brick's tight box (half-voxel units) */
+                const int32_t *box = r->boxes + 6 * id;
+                int in = 1;
+                for (int a = 0; a < 3; ++a)
+                    if (!(p[a] >= (float)box[a] * 0.5f && p[a] < (float)box[3 + a] * 0.5f)) in = 0;
+                if (!in) continue;
+            }
         }
         double s = normalise(trilinear(r->vol, r->dtype, r->n, p), r->dtype, r->vlo, r->vhi);
         double x = s * (double)(r->N - 1);
@@ -646,15 +731,18 @@ static int64_t march_pixel(const render_ctx *r, const orc_camera *cam, int px, i
 /* Renders either every pixel (pixels == NULL; out is [H][W][4], row 0 at the
  * top) or the listed pixels (pixels = npix (x,y) pairs; out is [npix][4]).
  * counts (optional) receives the number of composited samples per output
- * pixel.  flags/B/nb are used by mode 1 only. */
+ * pixel.  mode 0: full march; mode 1: only samples of flagged bricks
+ * (flags, B); mode 2: only samples inside the tight box of a flagged brick
+ * (boxes, half-voxel units, 6 per brick). */
 int orc_render(const void *vol, int dtype, int nx, int ny, int nz, float vlo, float vhi,
                const float *tf, int N, const orc_camera *cam, int W, int H, float dt, float ref,
                int mode, const uint8_t *flags, int B, const int32_t *pixels, int64_t npix,
-               double *out, int64_t *counts)
+               double *out, int64_t *counts, const int32_t *boxes)
 {
     if (!vol || !tf || !cam || !out || N < 2 || W < 1 || H < 1 || !(dt > 0.0f)) return -1;
-    render_ctx r = {vol, dtype, {nx, ny, nz}, vlo, vhi, tf, N, dt, ref, mode, flags, B, {0, 0, 0}};
-    if (mode == 1) {
+    render_ctx r = {vol, dtype, {nx, ny, nz}, vlo, vhi, tf, N, dt, ref, mode, flags, B, {0, 0, 0}, boxes};
+    if (mode == 2 && !boxes) return -1;
+    if (mode == 1 || mode == 2) {
         if (!flags || B < 1) return -1;
         r.nb[0] = (int)ceil_div(nx, B);
         r.nb[1] = (int)ceil_div(ny, B);

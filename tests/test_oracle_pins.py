@@ -217,6 +217,119 @@ def test_vote_is_subset_of_classification(seed, dtype):
     assert v.sum() > 0 and np.all(v <= c)
 
 
+def test_tight_boxes_single_voxel_closed_form():
+    # one bright voxel at x = 8 (first voxel of brick 1 along x, B = 8), y = 12,
+    # z = 3: the cells that read it are c = v - 1 and c = v per axis, whose
+    # regions cover [v - 1/2, v + 3/2); each brick gets that range clipped to
+    # itself, in half-voxel units [2v - 1, 2v + 3)
+    vol = np.zeros((16, 24, 24), np.uint8)            # (z, y, x)
+    vol[3, 12, 8] = 255
+    tf = np.zeros((256, 4), np.float32)
+    tf[128:, 3] = 1.0
+    mn, mx = oracle.brick_minmax(vol, 8)
+    fl = oracle.classify(mn, mx, vol.dtype, tf)
+    bx = oracle.tight_boxes(vol, 8, tf, fl).reshape(2, 3, 3, 6)   # (bz, by, bx)
+    assert np.array_equal(bx[0, 1, 1], [16, 23, 5, 19, 27, 9])
+    assert np.array_equal(bx[0, 1, 0], [15, 23, 5, 16, 27, 9])
+    # every other brick is empty (flagged or not)
+    nonzero = {tuple(i) for i in np.argwhere(np.any(bx != 0, axis=-1))}
+    assert nonzero == {(0, 1, 1), (0, 1, 0)}
+
+
+@pytest.mark.parametrize("v", [7, 8])
+def test_tight_boxes_voxel_on_brick_corner(v):
+    # a bright voxel at (v, v, v) next to the corner shared by 8 bricks (B = 8):
+    # the cells reading it, c in {v-1, v} per axis, cover [v - 1/2, v + 3/2),
+    # and each brick gets that cube clipped to itself.  With v = 7 brick
+    # (1,1,1) holds only cell (7,7,7), of which the voxel is the first corner;
+    # with v = 8 brick (0,0,0) holds only cell (7,7,7), of which it is the last
+    vol = np.zeros((16, 16, 16), np.uint8)
+    vol[v, v, v] = 255
+    tf = np.zeros((256, 4), np.float32)
+    tf[128:, 3] = 1.0
+    mn, mx = oracle.brick_minmax(vol, 8)
+    fl = oracle.classify(mn, mx, vol.dtype, tf)
+    bx = oracle.tight_boxes(vol, 8, tf, fl)
+    for b in range(8):
+        c = (b & 1, (b >> 1) & 1, b >> 2)
+        lo = [max(2 * v - 1, 16 * c[a]) for a in range(3)]
+        hi = [min(2 * v + 3, 16 * c[a] + 16) for a in range(3)]
+        assert list(bx[b]) == lo + hi, (b, bx[b])
+
+
+@pytest.mark.parametrize("entry,visible", [(97, False), (98, True), (99, True), (101, True), (102, False)])
+def test_tight_boxes_cell_index_window(entry, visible):
+    # constant u8 value 99 (x = 99 exactly for N = 256): a cell's window has
+    # the brick test's margins, [99 - 1, 99 + 2], so entries 98..101 light it
+    vol = np.full((12, 12, 12), 99, np.uint8)
+    tf = np.zeros((256, 4), np.float32)
+    tf[entry, 3] = 1.0
+    fl = np.ones(8, np.uint8)
+    bx = oracle.tight_boxes(vol, 8, tf, fl)
+    assert np.any(bx != 0) == visible
+
+
+def test_tight_boxes_full_tf_are_brick_boxes():
+    dims = (27, 20, 13)
+    vol = synth.blobs_u8(dims, seed=6, cut=0)
+    tf = np.full((256, 4), 0.5, np.float32)
+    mn, mx = oracle.brick_minmax(vol, 8)
+    fl = oracle.classify(mn, mx, vol.dtype, tf)
+    assert np.all(fl == 1)
+    bx = oracle.tight_boxes(vol, 8, tf, fl)
+    nb = oracle.brick_grid(dims, 8)
+    for b in range(fl.size):
+        c = (b % nb[0], (b // nb[0]) % nb[1], b // (nb[0] * nb[1]))
+        lo = [2 * 8 * c[a] for a in range(3)]
+        hi = [2 * min(8 * c[a] + 8, dims[a]) for a in range(3)]
+        assert list(bx[b]) == lo + hi, b
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+@pytest.mark.parametrize("dtype", [np.uint8, np.float32, np.float16])
+def test_tight_boxes_conservative_dense_sampling(seed, dtype):
+    # every sample point with alpha > 0 lies inside its brick's tight box,
+    # and every tight box lies inside its brick
+    dims = (29, 23, 26)
+    B = 8
+    base = synth.blobs_u8(dims, seed=60 + seed, cut=40)
+    vol = base if dtype == np.uint8 else (base.astype(np.float64) / 255.0).astype(dtype)
+    tf = synth.tf_random(seed + 20, 256)
+    mn, mx = oracle.brick_minmax(vol, B)
+    fl = oracle.classify(mn, mx, vol.dtype, tf)
+    bx = oracle.tight_boxes(vol, B, tf, fl)
+    nb = oracle.brick_grid(dims, B)
+    rng = np.random.default_rng(seed)
+    pts = (rng.random((60000, 3)) * np.array(dims)).astype(np.float32)
+    alpha = oracle.sample(vol, tf, pts)[:, 3]
+    bid = (np.floor(pts).astype(np.int64) // B)
+    lin = bid[:, 0] + nb[0] * (bid[:, 1] + nb[1] * bid[:, 2])
+    box = bx[lin]
+    inside = np.all((pts >= box[:, :3] * 0.5) & (pts < box[:, 3:] * 0.5), axis=1)
+    assert np.all(inside[alpha > 0])
+    assert inside[alpha > 0].size > 100 and (~inside).sum() > 100
+    for b in np.flatnonzero(np.any(bx != 0, axis=1)):
+        c = (b % nb[0], (b // nb[0]) % nb[1], b // (nb[0] * nb[1]))
+        for a in range(3):
+            assert 2 * B * c[a] <= bx[b, a] < bx[b, 3 + a] <= 2 * min(B * c[a] + B, dims[a])
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_render_tight_boxes_equal_full_march(seed):
+    dims = (33, 28, 25)
+    vol = synth.blobs_u8(dims, seed=70 + seed, n_blobs=5, cut=45)
+    tf = synth.tf_random(seed + 30, 256)
+    mn, mx = oracle.brick_minmax(vol, 8)
+    fl = oracle.classify(mn, mx, vol.dtype, tf)
+    bx = oracle.tight_boxes(vol, 8, tf, fl)
+    cam = synth.perspective(dims, 40, 30, synth.view_direction(seed + 3))
+    full, c0 = oracle.render(vol, tf, cam, 40, 30, with_counts=True)
+    brick, c1 = oracle.render(vol, tf, cam, 40, 30, mode=1, flags=fl, B=8, with_counts=True)
+    tight, c2 = oracle.render(vol, tf, cam, 40, 30, mode=2, flags=fl, B=8, boxes=bx, with_counts=True)
+    assert np.array_equal(full, tight) and np.array_equal(full, brick)
+    assert np.all(c2 <= c1) and np.all(c1 <= c0) and c2.sum() < c1.sum()
+
+
 @pytest.mark.parametrize("seed", [0, 1, 2])
 @pytest.mark.parametrize("dtype", [np.uint8, np.float32, np.float16])
 def test_classify_conservative_dense_sampling(seed, dtype):
