@@ -575,6 +575,28 @@ def main():
             times.append(e0.elapsed_time(e1))
         shallow[a + "_render_ms"] = round(statistics.median(times), 4)
     shallow["kd_nodes"] = ctx.stats()["kd_nodes"]
+    # voxel-tight boxes (ESK_TIGHT_BOXES): rebuild of all three structures and
+    # the tree renders with leaves marched inside the bricks' tight boxes
+    tight = {}
+    times = []
+    for i in range(5):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ctx.set_tf(dtfs[j], build=ACCELS, kd=kd, tight=True)
+        ctx.sync()
+        times.append((time.perf_counter() - t) * 1e3)
+    tight["rebuild_all_ms"] = round(statistics.median(times), 4)
+    for a in ("lbvh", "kd"):
+        rt = []
+        for _ in range(3):
+            e0.record(stream)
+            ctx.render(cams[j], W, H, accel=a, out=outs["lbvh"])
+            e1.record(stream)
+            torch.cuda.synchronize()
+            rt.append(e0.elapsed_time(e1))
+        tight[a + "_render_ms"] = round(statistics.median(rt), 4)
+        ctx.render(cams[j], W, H, accel=a, out=outs["lbvh"], counts=cnt)
+        tight[a + "_samples"] = int(cnt.sum().item())
 
     mean_ms = {a: statistics.mean(render_ms[a]) for a in ACCELS}
     dominant = max(ACCELS, key=lambda a: mean_ms[a])
@@ -612,6 +634,7 @@ def main():
             "bricks_nonempty": st["n_nonempty"], "lbvh_nodes": st["lbvh_nodes"],
             "lbvh_height": st["lbvh_height"], "kd_nodes": st["kd_nodes"], "kd_height": st["kd_height"],
             "shallow_kd_and_hybrid": shallow,
+            "voxel_tight": tight,
         },
         "roofline": {"kernel": f"k_render<{dominant}>", "bound": "alu", "achieved": round(achieved, 3),
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",

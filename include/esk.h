@@ -83,6 +83,18 @@ typedef enum {
  * are not, and such samples are skipped. */
 enum { ESK_CLASSIFY_VOXEL = 0x100 };
 
+/* Voxel-tight boxes, OR-ed into the build mask: after classification every
+ * non-empty brick gets the bounding box of its potentially visible trilinear
+ * cells (a cell -- the 8 voxels a sample reads -- is potentially visible iff
+ * the classification window of its own min/max holds an entry with alpha > 0;
+ * cell c covers [c + 1/2, c + 3/2) per axis), clipped to the brick, and the
+ * LBVH leaves and the k-d leaves (union over their non-empty bricks) are
+ * marched inside these boxes instead of whole bricks: the tight per-macro-
+ * cell boxes of the GPU k-d builder of Sec. 3.2.2.  Samples outside read only
+ * invisible cells, so every image still equals the full march.  Reads every
+ * voxel of the non-empty bricks per TF change. */
+enum { ESK_TIGHT_BOXES = 0x200 };
+
 /* k-d build parameters (Sec. 4.3).
  *  halting:  0 = shallow: split only while 10*V(node) > V(root);
  *            1 = deep:    split only while V(node) > 8^3 voxels.
@@ -141,7 +153,10 @@ typedef enum {
     ESK_X_KD_AXIS = 14,   /* int32[M]: split axis, -1 = leaf */
     ESK_X_KD_PLANE = 15,  /* int32[M]: split plane in bricks (0 for leaves) */
     ESK_X_KD_FIRST = 16,  /* int32[M]: index of the left child (right = +1), -1 for leaves */
-    ESK_X_GRID = 17       /* uint32[ceil(nb/32)]: bit (i%32) of word i/32 = flag of brick i */
+    ESK_X_GRID = 17,      /* uint32[ceil(nb/32)]: bit (i%32) of word i/32 = flag of brick i */
+    ESK_X_TIGHT = 18      /* int32[nb][6]: voxel-tight box per brick in half-voxel units
+                             (lo x,y,z, hi x,y,z; the box is [lo/2, hi/2)), zero for empty
+                             bricks and bricks without a visible cell; needs ESK_TIGHT_BOXES */
 } esk_export_what;
 
 /* Creates a context on HIP device `device` that enqueues on `hip_stream`

@@ -24,6 +24,7 @@ OK, EINVAL, ENOSPC, ELIMIT, EDEVICE, ESTATE, EINTERNAL = 0, -1, -2, -3, -4, -5, 
 U8, U16, F16, F32 = 0, 1, 2, 3
 NONE, GRID, LBVH, KD, HYBRID = 0, 1, 2, 4, 8
 CLASSIFY_VOXEL = 0x100      # build-mask bit: per-voxel vote instead of brick min/max
+TIGHT_BOXES = 0x200         # build-mask bit: march LBVH/k-d leaves inside voxel-tight boxes
 ACCEL = {"none": NONE, "grid": GRID, "lbvh": LBVH, "kd": KD, "hybrid": HYBRID}
 # what a rebuild must build for each render mode (the hybrid grid renders the k-d tree + grid)
 BUILD = {"grid": GRID, "lbvh": LBVH, "kd": KD, "hybrid": KD}
@@ -32,14 +33,14 @@ LEAF = 0x80000000
 EXPORTS = {
     "minmax": 0, "tf_prefix": 1, "flags": 2, "ids": 3, "keys": 4, "sorted_keys": 5, "sorted_ids": 6,
     "lbvh_left": 7, "lbvh_right": 8, "lbvh_axis": 9, "lbvh_lo": 10, "lbvh_hi": 11,
-    "kd_lo": 12, "kd_hi": 13, "kd_axis": 14, "kd_plane": 15, "kd_first": 16, "grid": 17,
+    "kd_lo": 12, "kd_hi": 13, "kd_axis": 14, "kd_plane": 15, "kd_first": 16, "grid": 17, "tight": 18,
 }
 _EXPORT_DTYPE = {
     "tf_prefix": (np.int32, 1), "flags": (np.uint8, 1), "ids": (np.uint32, 1), "keys": (np.uint32, 1),
     "sorted_keys": (np.uint32, 1), "sorted_ids": (np.uint32, 1), "lbvh_left": (np.uint32, 1),
     "lbvh_right": (np.uint32, 1), "lbvh_axis": (np.int32, 1), "lbvh_lo": (np.int32, 3),
     "lbvh_hi": (np.int32, 3), "kd_lo": (np.int32, 3), "kd_hi": (np.int32, 3), "kd_axis": (np.int32, 1),
-    "kd_plane": (np.int32, 1), "kd_first": (np.int32, 1), "grid": (np.uint32, 1),
+    "kd_plane": (np.int32, 1), "kd_first": (np.int32, 1), "grid": (np.uint32, 1), "tight": (np.int32, 6),
 }
 
 
@@ -195,15 +196,17 @@ class Context:
         self.dtype_code = code
         return self
 
-    def set_tf(self, tf, build=("grid", "lbvh", "kd"), kd: Kd | None = None, classify: str = "minmax"):
+    def set_tf(self, tf, build=("grid", "lbvh", "kd"), kd: Kd | None = None, classify: str = "minmax",
+               tight: bool = False):
         """tf: contiguous [N, 4] float32 device tensor; rebuilds the requested
         structures.  classify: "minmax" (conservative brick value ranges) or
-        "voxel" (the per-voxel vote)."""
+        "voxel" (the per-voxel vote).  tight: march LBVH and k-d leaves inside
+        voxel-tight boxes."""
         if tf.dtype.is_floating_point is False or tf.dim() != 2 or tf.shape[1] != 4:
             raise ValueError("TF must be an [N, 4] float32 tensor")
         if classify not in ("minmax", "voxel"):
             raise ValueError("classify must be 'minmax' or 'voxel'")
-        mask = CLASSIFY_VOXEL if classify == "voxel" else 0
+        mask = (CLASSIFY_VOXEL if classify == "voxel" else 0) | (TIGHT_BOXES if tight else 0)
         for b in build:
             mask |= BUILD[b]
         kp = None
@@ -259,8 +262,8 @@ class Context:
         if what == "minmax":
             h = buf.size // 2
             return buf[:h].copy(), buf[h:].copy()
-        if what in ("lbvh_lo", "lbvh_hi", "kd_lo", "kd_hi"):
-            return buf.reshape(-1, 3)
+        if width > 1:
+            return buf.reshape(-1, width)
         return buf
 
 

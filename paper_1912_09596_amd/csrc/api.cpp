@@ -10,6 +10,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "esk_internal.hpp"
 
@@ -69,6 +70,8 @@ Layout make_layout(int nx, int ny, int nz, int brick, int elem_bytes, int max_tf
     L.lb_range = take(2 * n4);
     L.lb_rnode = take((size_t)nb * sizeof(RNode));
     L.lb_leafbox = take((size_t)nb * 16);
+    L.lb_root = take(16);
+    L.tbox = take((size_t)nb * 16);
     L.kd_S = take(n4);
     L.kd_lo = take(2 * n4 * 3);
     L.kd_hi = take(2 * n4 * 3);
@@ -104,6 +107,7 @@ struct esk_ctx {
     bool has_tf = false;
     int N = 0;
     int built = 0;
+    bool tight = false;         // render boxes are voxel-tight (ESK_TIGHT_BOXES)
     uint32_t kd_height = 0;
     uint32_t kd_count = 0;
     bool kd_on_device = false;  // k-d build enqueued; completion and height not yet read back
@@ -163,6 +167,8 @@ int bits_for(int n)  // bits to index [0, n)
 esk_status check_shape(esk_ctx *c, int nx, int ny, int nz, int dtype, int brick, int max_tf)
 {
     if (nx < 1 || ny < 1 || nz < 1) return fail(c, ESK_EINVAL, "dims must be >= 1 (got %d %d %d)", nx, ny, nz);
+    if (nx > kMaxVoxelsPerAxis || ny > kMaxVoxelsPerAxis || nz > kMaxVoxelsPerAxis)
+        return fail(c, ESK_ELIMIT, "more than %d voxels on an axis (%d %d %d)", kMaxVoxelsPerAxis, nx, ny, nz);
     if (elem_size(dtype) == 0) return fail(c, ESK_EINVAL, "unknown dtype %d", dtype);
     if (!valid_brick(brick)) return fail(c, ESK_EINVAL, "brick must be 4, 8, 16 or 32 (got %d)", brick);
     if (max_tf < 2 || max_tf > kMaxTF)
@@ -418,6 +424,8 @@ static RebuildArgs rebuild_args(esk_ctx *c)
     a.nsortblk = L.nsortblk;
     a.key_bits = 3 * std::max({bits_for(c->vol.nb[0]), bits_for(c->vol.nb[1]), bits_for(c->vol.nb[2])});
     value_norm(c, a.nlo, a.nscale);
+    a.tbox = at<uint4>(c, L.tbox);
+    a.lb_root = at<uint4>(c, L.lb_root);
     return a;
 }
 
@@ -444,6 +452,8 @@ static KdArgs kd_args(esk_ctx *c, const esk_kd_params *p)
     k.box = at<uint4>(c, L.kd_box);
     k.hdr = at<DevHeader>(c, L.header);
     k.cap = 2 * L.nb;
+    k.tight = c->tight ? 1 : 0;
+    k.tbox = at<uint4>(c, L.tbox);
     if (p) {
         k.halting = p->halting;
         k.max_leaf = p->max_leaf;
@@ -459,7 +469,7 @@ esk_status esk_set_transfer_function(esk_ctx *c, const float *d_rgba, int n_entr
     if (!d_rgba) return fail(c, ESK_EINVAL, "TF pointer is null");
     if ((reinterpret_cast<uintptr_t>(d_rgba) & 15) != 0) return fail(c, ESK_EINVAL, "TF must be 16-byte aligned");
     if (n_entries < 2) return fail(c, ESK_EINVAL, "TF needs at least 2 entries (got %d)", n_entries);
-    if (build_mask & ~(ESK_ACCEL_GRID | ESK_ACCEL_LBVH | ESK_ACCEL_KD | ESK_CLASSIFY_VOXEL))
+    if (build_mask & ~(ESK_ACCEL_GRID | ESK_ACCEL_LBVH | ESK_ACCEL_KD | ESK_CLASSIFY_VOXEL | ESK_TIGHT_BOXES))
         return fail(c, ESK_EINVAL, "unknown bits in build_mask 0x%x", build_mask);
     if (build_mask & ESK_ACCEL_KD) {
         if (!kd) return fail(c, ESK_EINVAL, "k-d build requested without parameters");
@@ -490,6 +500,12 @@ esk_status esk_set_transfer_function(esk_ctx *c, const float *d_rgba, int n_entr
     }
     e = launch_classify_compact(a, c->stream);
     if (e != hipSuccess) return hip_check(c, e, "classify launch");
+    c->tight = (build_mask & ESK_TIGHT_BOXES) != 0;
+    if (c->tight) {
+        a.tight = 1;
+        e = launch_tight(a, c->stream);
+        if (e != hipSuccess) return hip_check(c, e, "tight-box launch");
+    }
     if (build_mask & ESK_ACCEL_LBVH) {
         e = launch_sort(a, c->stream);
         if (e == hipSuccess) e = launch_lbvh(a, c->stream);
@@ -575,8 +591,7 @@ static esk_status prepare_render(esk_ctx *c, int accel, const esk_camera *cam, i
     r.out = d_rgba_out;
     r.count = d_count_out;
     r.grid = at<uint32_t>(c, L.grid);
-    r.lb_lo = at<int32_t>(c, L.lb_lo);
-    r.lb_hi = at<int32_t>(c, L.lb_hi);
+    r.lb_root = at<uint4>(c, L.lb_root);
     r.lb_rnode = at<RNode>(c, L.lb_rnode);
     r.lb_leafbox = at<uint4>(c, L.lb_leafbox);
     r.kd_rnode = at<RNode>(c, L.kd_rnode);
@@ -767,6 +782,27 @@ esk_status esk_export(esk_ctx *c, int what, void *host, size_t cap, size_t *used
     case ESK_X_KD_PLANE: if (!(c->built & ESK_ACCEL_KD)) goto notbuilt; off = L.kd_plane; bytes = (size_t)m * 4; break;
     case ESK_X_KD_FIRST: if (!(c->built & ESK_ACCEL_KD)) goto notbuilt; off = L.kd_first; bytes = (size_t)m * 4; break;
     case ESK_X_GRID: off = L.grid; bytes = (size_t)((nb + 31) / 32) * 4; break;
+    case ESK_X_TIGHT: {
+        if (!c->tight) goto notbuilt;
+        // packed half-voxel boxes of the non-empty bricks -> int32[nb][6],
+        // zero for empty bricks and for bricks without a visible cell
+        *used = (size_t)nb * 24;
+        if (cap < *used || !host) return fail(c, ESK_ENOSPC, "export needs %zu bytes", *used);
+        std::vector<uint32_t> packed((size_t)nb * 4);
+        std::vector<uint8_t> flags((size_t)nb);
+        e = hipMemcpy(packed.data(), c->ws + L.tbox, (size_t)nb * 16, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(flags.data(), c->ws + L.flags, (size_t)nb, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_check(c, e, "export copy");
+        int32_t *out = static_cast<int32_t *>(host);
+        for (int64_t b = 0; b < nb; ++b) {
+            const uint32_t *w = &packed[(size_t)b * 4];
+            const int32_t box[6] = {(int32_t)(w[0] & 0xffffu), (int32_t)(w[0] >> 16), (int32_t)(w[1] & 0xffffu),
+                                    (int32_t)(w[1] >> 16),     (int32_t)(w[2] & 0xffffu), (int32_t)(w[2] >> 16)};
+            const bool any = flags[(size_t)b] && box[3] > box[0] && box[4] > box[1] && box[5] > box[2];
+            for (int q = 0; q < 6; ++q) out[6 * b + q] = any ? box[q] : 0;
+        }
+        return ESK_OK;
+    }
     default: return fail(c, ESK_EINVAL, "unknown export %d", what);
     }
     *used = bytes;

@@ -54,4 +54,14 @@ __device__ inline void pack_box(const int lo[3], const int hi[3], uint32_t w[3])
     w[2] = (uint32_t)hi[1] | ((uint32_t)hi[2] << 16);
 }
 
+__device__ inline void unpack_box_u(uint32_t w0, uint32_t w1, uint32_t w2, int lo[3], int hi[3])
+{
+    lo[0] = (int)(w0 & 0xffffu);
+    lo[1] = (int)(w0 >> 16);
+    lo[2] = (int)(w1 & 0xffffu);
+    hi[0] = (int)(w1 >> 16);
+    hi[1] = (int)(w2 & 0xffffu);
+    hi[2] = (int)(w2 >> 16);
+}
+
 }  // namespace esk

@@ -12,6 +12,7 @@ namespace esk {
 
 constexpr int kMaxTF = 4096;          // TF entries the ABI accepts
 constexpr int kMaxBricksPerAxis = 1024;  // 10 bits per axis of the 30-bit Morton code
+constexpr int kMaxVoxelsPerAxis = 32767; // render boxes are uint16 in half-voxel units
 constexpr uint32_t kLeaf = 0x80000000u;
 constexpr int kClassifyBlock = 1024;  // bricks per classification / compaction block
 constexpr int kSortSingleMax = 32768; // keys one workgroup sorts in LDS
@@ -21,8 +22,11 @@ constexpr int64_t kMaxBricks = (int64_t)1 << 28;  // node indices fit the 29-bit
 constexpr uint32_t kIndexMask = 0x1fffffffu;
 
 // Traversal record of one internal node (32 bytes, two 16-byte loads): the
-// boxes of both children in voxels (uint16, half-open) and the children,
-// each with bit 31 = leaf; bits 29..30 of c0 hold this node's split axis.
+// boxes of both children in half-voxel units (uint16, half-open: the box is
+// [lo/2, hi/2), so voxel-tight boxes with bounds on cell boundaries fit; at
+// most 32767 voxels per axis) and the children, each with bit 31 = leaf;
+// bits 29..30 of c0 hold this node's split axis.  Packed leaf and root boxes
+// (uint4: the same three words and a zero) use the same units.
 struct RNode {
     uint32_t w[8];  // lo0.x|lo0.y, lo0.z|hi0.x, hi0.y|hi0.z, lo1.x|lo1.y, lo1.z|hi1.x, hi1.y|hi1.z, c0, c1
 };
@@ -47,7 +51,8 @@ struct Layout {
     int64_t nsortblk;      // multi-block sort blocks
     size_t header, swz, minv, maxv, tf, tfP, flags, grid, blkcnt;
     size_t ids, keys, skeys, tmpkeys, sids, hist;
-    size_t lb_left, lb_right, lb_axis, lb_parent, lb_lo, lb_hi, lb_range, lb_rnode, lb_leafbox;
+    size_t tbox;           // voxel-tight box per brick (half-voxel units, packed)
+    size_t lb_left, lb_right, lb_axis, lb_parent, lb_lo, lb_hi, lb_range, lb_rnode, lb_leafbox, lb_root;
     size_t kd_S, kd_lo, kd_hi, kd_axis, kd_plane, kd_first, kd_split, kd_clo, kd_rnode, kd_box;
     size_t total;
 };
@@ -101,9 +106,13 @@ struct RebuildArgs {
     int key_bits;          // Morton bits that can be non-zero
     int vote;              // 1: flags come from the per-voxel vote (k_vote), not min/max
     float nlo, nscale;     // the renderer's value normalisation s = (v - nlo) * nscale
+    int tight;             // 1: render boxes of LBVH leaves are the voxel-tight boxes
+    uint4 *tbox;           // per brick: packed voxel-tight box (written by k_tight)
+    uint4 *lb_root;        // packed render box of the LBVH root
 };
 
 hipError_t launch_vote(const RebuildArgs &a, hipStream_t s);
+hipError_t launch_tight(const RebuildArgs &a, hipStream_t s);
 hipError_t launch_classify_compact(const RebuildArgs &a, hipStream_t s);
 hipError_t launch_sort(const RebuildArgs &a, hipStream_t s);
 hipError_t launch_lbvh(const RebuildArgs &a, hipStream_t s);
@@ -118,6 +127,8 @@ struct KdArgs {
     DevHeader *hdr;
     int halting, max_leaf, bins;
     int64_t cap;           // node capacity of the k-d arrays (2 nb)
+    int tight;             // 1: leaf render boxes are unions of the bricks' voxel-tight boxes
+    const uint4 *tbox;     // per brick: packed voxel-tight box
 };
 
 bool kd_small(const KdArgs &k);
@@ -139,7 +150,7 @@ struct RenderArgs {
     float *out;
     int32_t *count;
     const uint32_t *grid;
-    const int32_t *lb_lo, *lb_hi;
+    const uint4 *lb_root;
     const RNode *lb_rnode;
     const uint4 *lb_leafbox;
     const RNode *kd_rnode;

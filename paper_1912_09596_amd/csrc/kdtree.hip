@@ -9,6 +9,8 @@
 // node at once: lanes take (candidate, side, face) tasks.  One launch
 // evaluates a whole level; a single-workgroup launch numbers the children in
 // breadth-first order (left child first) with a block scan.
+#include <algorithm>
+
 #include "esk_internal.hpp"
 #include "device_util.hpp"
 
@@ -401,19 +403,80 @@ __global__ __launch_bounds__(256) void k_kd_level(KdArgs k)
     }
 }
 
-// voxel box of node m (bricks -> voxels, clipped to the volume)
-__device__ inline void kd_voxel_box(const KdArgs &k, int64_t m, int lo[3], int hi[3])
+// render box of node m from its brick box: voxels clipped to the volume, in
+// half-voxel units
+__device__ inline void kd_half_box(const KdArgs &k, int64_t m, int lo[3], int hi[3])
 {
     for (int q = 0; q < 3; ++q) {
-        lo[q] = k.B * k.lo[3 * m + q];
-        hi[q] = min(k.B * k.hi[3 * m + q], k.n[q]);
+        lo[q] = 2 * (k.B * k.lo[3 * m + q]);
+        hi[q] = 2 * min(k.B * k.hi[3 * m + q], k.n[q]);
     }
 }
 
-// traversal records: every node's own voxel box, and an RNode per internal
+// voxel-tight leaves: the render box of a leaf is the union of the
+// voxel-tight boxes of the non-empty bricks in it (one workgroup per leaf,
+// grid-stride over the nodes).  Finished trees only, like k_kd_pack, which
+// runs after it and takes the leaves' boxes from k.box.
+__global__ __launch_bounds__(256) void k_kd_tight(KdArgs k)
+{
+    __shared__ int red[6];
+    const uint32_t count = k.hdr->kd_count;
+    if (k.hdr->kd_begin != k.hdr->kd_end || (int64_t)count > k.cap) return;
+    for (int64_t m = blockIdx.x; m < (int64_t)count; m += gridDim.x) {
+        if (k.axis[m] >= 0) continue;   // uniform per workgroup
+        if (threadIdx.x < 6) red[threadIdx.x] = threadIdx.x < 3 ? 0x7fffffff : -1;
+        __syncthreads();
+        const int lo[3] = {k.lo[3 * m], k.lo[3 * m + 1], k.lo[3 * m + 2]};
+        const int e[3] = {k.hi[3 * m] - lo[0], k.hi[3 * m + 1] - lo[1], k.hi[3 * m + 2] - lo[2]};
+        const int64_t total = (int64_t)e[0] * e[1] * e[2];
+        int tl[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, th[3] = {-1, -1, -1};
+        for (int64_t t = threadIdx.x; t < total; t += 256) {
+            const int bx = lo[0] + (int)(t % e[0]), by = lo[1] + (int)((t / e[0]) % e[1]),
+                      bz = lo[2] + (int)(t / ((int64_t)e[0] * e[1]));
+            const int64_t b = bx + (int64_t)k.nb[0] * (by + (int64_t)k.nb[1] * bz);
+            if (!k.flags[b]) continue;
+            const uint4 w = k.tbox[b];
+            int l2[3], h2[3];
+            unpack_box_u(w.x, w.y, w.z, l2, h2);
+            for (int q = 0; q < 3; ++q) {
+                tl[q] = min(tl[q], l2[q]);
+                th[q] = max(th[q], h2[q]);
+            }
+        }
+        for (int o = 32; o >= 1; o >>= 1)
+            for (int q = 0; q < 3; ++q) {
+                tl[q] = min(tl[q], __shfl_xor(tl[q], o, 64));
+                th[q] = max(th[q], __shfl_xor(th[q], o, 64));
+            }
+        if ((threadIdx.x & 63) == 0)
+            for (int q = 0; q < 3; ++q) {
+                atomicMin(&red[q], tl[q]);
+                atomicMax(&red[3 + q], th[q]);
+            }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            // a leaf of a tight tree holds a non-empty brick; without one the
+            // brick box stays (never the case for a finished tree)
+            int l2[3], h2[3];
+            kd_half_box(k, m, l2, h2);
+            if (red[3] >= 0)
+                for (int q = 0; q < 3; ++q) {
+                    l2[q] = red[q];
+                    h2[q] = red[3 + q];
+                }
+            uint32_t w[3];
+            pack_box(l2, h2, w);
+            k.box[m] = make_uint4(w[0], w[1], w[2], 0u);
+        }
+        __syncthreads();
+    }
+}
+
+// traversal records: every node's render box, and an RNode per internal
 // node.  Runs only on a finished tree: while levels remain (begin != end) the
 // nodes of the pending level have not been evaluated, and their axis/first
 // entries are stale workspace contents that must not be used as indices.
+// With voxel-tight leaves, the leaves' boxes come from k_kd_tight.
 __global__ __launch_bounds__(256) void k_kd_pack(KdArgs k)
 {
     const uint32_t count = k.hdr->kd_count;
@@ -422,18 +485,27 @@ __global__ __launch_bounds__(256) void k_kd_pack(KdArgs k)
     if (m >= (int64_t)count) return;
     int lo[3], hi[3];
     uint32_t w[3];
-    kd_voxel_box(k, m, lo, hi);
-    pack_box(lo, hi, w);
-    k.box[m] = make_uint4(w[0], w[1], w[2], 0u);
     const int a = k.axis[m];
+    if (!(k.tight && a < 0)) {
+        kd_half_box(k, m, lo, hi);
+        pack_box(lo, hi, w);
+        k.box[m] = make_uint4(w[0], w[1], w[2], 0u);
+    }
     if (a < 0) return;
     const int c = k.first[m];
     if (c <= m || (int64_t)c + 1 >= (int64_t)count || a > 2) return;  // never true for a finished tree
     RNode rec;
-    kd_voxel_box(k, c, lo, hi);
-    pack_box(lo, hi, &rec.w[0]);
-    kd_voxel_box(k, c + 1, lo, hi);
-    pack_box(lo, hi, &rec.w[3]);
+    for (int side = 0; side < 2; ++side) {
+        if (k.tight && k.axis[c + side] < 0) {
+            const uint4 t = k.box[c + side];
+            rec.w[3 * side] = t.x;
+            rec.w[3 * side + 1] = t.y;
+            rec.w[3 * side + 2] = t.z;
+        } else {
+            kd_half_box(k, c + side, lo, hi);
+            pack_box(lo, hi, &rec.w[3 * side]);
+        }
+    }
     rec.w[6] = (uint32_t)c | ((uint32_t)a << 29) | (k.axis[c] < 0 ? kLeaf : 0u);
     rec.w[7] = (uint32_t)(c + 1) | (k.axis[c + 1] < 0 ? kLeaf : 0u);
     uint4 *dst = reinterpret_cast<uint4 *>(&k.rnode[m]);
@@ -446,6 +518,8 @@ __global__ __launch_bounds__(256) void k_kd_pack(KdArgs k)
 hipError_t launch_kd_pack(const KdArgs &k, int64_t max_nodes, hipStream_t s)
 {
     if (max_nodes <= 0) return hipSuccess;
+    if (k.tight)
+        hipLaunchKernelGGL(k_kd_tight, dim3((unsigned)std::min<int64_t>(max_nodes, 2048)), dim3(256), 0, s, k);
     hipLaunchKernelGGL(k_kd_pack, dim3((unsigned)((max_nodes + 255) / 256)), dim3(256), 0, s, k);
     return hipGetLastError();
 }

@@ -136,6 +136,100 @@ template <typename T> hipError_t launch_vote_typed(const RebuildArgs &a, hipStre
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// voxel-tight brick boxes (the GPU k-d variant's per-macro-cell tight boxes,
+// Sec. 3.2.2): a sample point p reads the trilinear cell c = floor(p - 1/2)
+// (8 corner voxels, clamped), whose region is [c + 1/2, c + 3/2).  A cell is
+// potentially visible iff the classification window of its own min/max holds
+// an entry with alpha > 0; a brick's tight box is the bounding box of its
+// potentially visible cells' regions, clipped to the brick, in half-voxel
+// units.  Samples outside it read only invisible cells (alpha exactly 0).
+// One workgroup per non-empty brick (grid-stride over the compacted ids); a
+// brick without a visible cell gets a zero-volume box at its low corner.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_tight(RebuildArgs a)
+{
+    __shared__ int32_t P[kMaxTF + 1];
+    __shared__ int red[6];
+    const int N = a.N;
+    for (int i = threadIdx.x; i <= N; i += 256) P[i] = a.tfP[i];
+    const int n = (int)a.hdr->n;
+    const int B = a.vol.B;
+    const int nn[3] = {a.vol.nx, a.vol.ny, a.vol.nz};
+    const uint32_t nbx = (uint32_t)a.vol.nb[0], nby = (uint32_t)a.vol.nb[1];
+    const T *vol = static_cast<const T *>(a.vol.vox);
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
+        const uint32_t id = a.ids[i];
+        const int bc[3] = {(int)(id % nbx), (int)((id / nbx) % nby), (int)(id / (nbx * nby))};
+        int blo[3], bhi[3], ex[3];
+        for (int q = 0; q < 3; ++q) {
+            blo[q] = bc[q] * B;
+            bhi[q] = min(blo[q] + B, nn[q]);
+            ex[q] = bhi[q] - blo[q] + 1;   // cells blo-1 .. bhi-1
+        }
+        if (threadIdx.x < 6) red[threadIdx.x] = threadIdx.x < 3 ? 0x7fffffff : -1;
+        __syncthreads();
+        int tl[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, th[3] = {-1, -1, -1};
+        const int cells = ex[0] * ex[1] * ex[2];
+        for (int t = threadIdx.x; t < cells; t += 256) {
+            const int c[3] = {blo[0] - 1 + t % ex[0], blo[1] - 1 + (t / ex[0]) % ex[1],
+                              blo[2] - 1 + t / (ex[0] * ex[1])};
+            int x0[3], x1[3];
+            for (int q = 0; q < 3; ++q) {
+                x0[q] = min(max(c[q], 0), nn[q] - 1);
+                x1[q] = min(max(c[q] + 1, 0), nn[q] - 1);
+            }
+            float mn = 3.402823466e+38f, mx = -3.402823466e+38f;
+            for (int corner = 0; corner < 8; ++corner) {
+                const int x = (corner & 1) ? x1[0] : x0[0];
+                const int y = (corner & 2) ? x1[1] : x0[1];
+                const int z = (corner & 4) ? x1[2] : x0[2];
+                const float v = (float)vol[((size_t)z * nn[1] + y) * (size_t)nn[0] + x];
+                mn = fminf(mn, v);
+                mx = fmaxf(mx, v);
+            }
+            const int lo = max(tf_floor_index(mn, a.vol.dtype, a.vlo, a.vhi, N) - 1, 0);
+            const int hi = min(tf_floor_index(mx, a.vol.dtype, a.vlo, a.vhi, N) + 2, N - 1);
+            if (P[hi + 1] - P[lo] <= 0) continue;
+            for (int q = 0; q < 3; ++q) {
+                tl[q] = min(tl[q], max(2 * c[q] + 1, 2 * blo[q]));
+                th[q] = max(th[q], min(2 * c[q] + 3, 2 * bhi[q]));
+            }
+        }
+        for (int o = 32; o >= 1; o >>= 1)
+            for (int q = 0; q < 3; ++q) {
+                tl[q] = min(tl[q], __shfl_xor(tl[q], o, 64));
+                th[q] = max(th[q], __shfl_xor(th[q], o, 64));
+            }
+        if ((threadIdx.x & 63) == 0)
+            for (int q = 0; q < 3; ++q) {
+                atomicMin(&red[q], tl[q]);
+                atomicMax(&red[3 + q], th[q]);
+            }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int l2[3], h2[3];
+            const bool any = red[3] >= 0;
+            for (int q = 0; q < 3; ++q) {
+                l2[q] = any ? red[q] : 2 * blo[q];
+                h2[q] = any ? red[3 + q] : 2 * blo[q];
+            }
+            uint32_t w[3];
+            pack_box(l2, h2, w);
+            a.tbox[id] = make_uint4(w[0], w[1], w[2], 0u);
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T> hipError_t launch_tight_typed(const RebuildArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_tight<T>), dim3((unsigned)std::min<int64_t>(a.nb, 4096)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void k_classify(RebuildArgs a)
 {
     __shared__ int32_t P[kMaxTF + 1];
@@ -409,10 +503,24 @@ __global__ __launch_bounds__(256) void k_karras(RebuildArgs a)
         const int node = (n - 1) + i;
         const int b[3] = {(int)bx, (int)by, (int)bz};
         const int nn[3] = {a.vol.nx, a.vol.ny, a.vol.nz};
+        int lo2[3], hi2[3];
         for (int q = 0; q < 3; ++q) {
             a.lb_lo[3 * node + q] = a.vol.B * b[q];
             a.lb_hi[3 * node + q] = min(a.vol.B * b[q] + a.vol.B, nn[q]);
+            lo2[q] = 2 * a.lb_lo[3 * node + q];
+            hi2[q] = 2 * a.lb_hi[3 * node + q];
         }
+        // the leaf's render box: its brick, or the brick's voxel-tight box
+        uint4 box;
+        if (a.tight) {
+            box = a.tbox[a.sids[i]];
+        } else {
+            uint32_t w[3];
+            pack_box(lo2, hi2, w);
+            box = make_uint4(w[0], w[1], w[2], 0u);
+        }
+        a.lb_leafbox[i] = box;
+        if (n == 1) a.lb_root[0] = box;
     }
     if (i >= n - 1) return;
     const int d = (delta(k, n, i, i + 1) - delta(k, n, i, i - 1)) > 0 ? 1 : -1;
@@ -456,32 +564,57 @@ __global__ __launch_bounds__(256) void k_lbvh_boxes(RebuildArgs a)
     const int2 rg = a.lb_range[i];
     const uint32_t l = a.lb_left[i], r = a.lb_right[i];
     const int g = (int)(l & ~kLeaf);
-    int box[2][6];
+    int box[2][6], rbox[2][6];
     for (int side = 0; side < 2; ++side) {
         const int j0 = side == 0 ? rg.x : g + 1, j1 = side == 0 ? g : rg.y;
+        // b: the union of the bricks (exported AABB, voxels); r: the union of
+        // the leaves' render boxes (half-voxel units)
         int b[6] = {0x7fffffff, 0x7fffffff, 0x7fffffff, -1, -1, -1};
+        int r6[6] = {0x7fffffff, 0x7fffffff, 0x7fffffff, -1, -1, -1};
         for (int j = j0 + lane; j <= j1; j += 64) {
             const int u = (n - 1) + j;
             for (int q = 0; q < 3; ++q) {
                 b[q] = min(b[q], a.lb_lo[3 * u + q]);
                 b[3 + q] = max(b[3 + q], a.lb_hi[3 * u + q]);
             }
+            int l2[3], h2[3];
+            const uint4 w = a.lb_leafbox[j];
+            unpack_box_u(w.x, w.y, w.z, l2, h2);
+            for (int q = 0; q < 3; ++q) {
+                r6[q] = min(r6[q], l2[q]);
+                r6[3 + q] = max(r6[3 + q], h2[q]);
+            }
         }
         for (int o = 32; o >= 1; o >>= 1)
             for (int q = 0; q < 3; ++q) {
                 b[q] = min(b[q], __shfl_xor(b[q], o, 64));
                 b[3 + q] = max(b[3 + q], __shfl_xor(b[3 + q], o, 64));
+                r6[q] = min(r6[q], __shfl_xor(r6[q], o, 64));
+                r6[3 + q] = max(r6[3 + q], __shfl_xor(r6[3 + q], o, 64));
             }
-        for (int q = 0; q < 6; ++q) box[side][q] = b[q];
+        for (int q = 0; q < 6; ++q) {
+            box[side][q] = b[q];
+            rbox[side][q] = r6[q];
+        }
     }
     if (lane == 0) {
         for (int q = 0; q < 3; ++q) {
             a.lb_lo[3 * i + q] = min(box[0][q], box[1][q]);
             a.lb_hi[3 * i + q] = max(box[0][3 + q], box[1][3 + q]);
         }
+        if (i == 0) {
+            int l2[3], h2[3];
+            uint32_t w[3];
+            for (int q = 0; q < 3; ++q) {
+                l2[q] = min(rbox[0][q], rbox[1][q]);
+                h2[q] = max(rbox[0][3 + q], rbox[1][3 + q]);
+            }
+            pack_box(l2, h2, w);
+            a.lb_root[0] = make_uint4(w[0], w[1], w[2], 0u);
+        }
         RNode rec;
-        pack_box(&box[0][0], &box[0][3], &rec.w[0]);
-        pack_box(&box[1][0], &box[1][3], &rec.w[3]);
+        pack_box(&rbox[0][0], &rbox[0][3], &rec.w[0]);
+        pack_box(&rbox[1][0], &rbox[1][3], &rec.w[3]);
         rec.w[6] = l | ((uint32_t)a.lb_axis[i] << 29);
         rec.w[7] = r;
         uint4 *dst = reinterpret_cast<uint4 *>(&a.lb_rnode[i]);
@@ -490,8 +623,7 @@ __global__ __launch_bounds__(256) void k_lbvh_boxes(RebuildArgs a)
     }
 }
 
-// height in levels = 1 + the deepest leaf's number of ancestors; also packs
-// every leaf's box for the traversal
+// height in levels = 1 + the deepest leaf's number of ancestors
 __global__ __launch_bounds__(256) void k_lbvh_height(RebuildArgs a)
 {
     const int n = (int)a.hdr->n;
@@ -499,9 +631,6 @@ __global__ __launch_bounds__(256) void k_lbvh_height(RebuildArgs a)
     uint32_t depth = 0;
     if (j < n) {
         const int u = (n - 1) + j;
-        uint32_t w[3];
-        pack_box(&a.lb_lo[3 * u], &a.lb_hi[3 * u], w);
-        a.lb_leafbox[j] = make_uint4(w[0], w[1], w[2], 0u);
         if (n > 1) {
             uint32_t cur = a.lb_parent[u];
             depth = 1;
@@ -525,6 +654,17 @@ hipError_t launch_vote(const RebuildArgs &a, hipStream_t s)
     case ESK_U16: return launch_vote_typed<uint16_t>(a, s);
     case ESK_F16: return launch_vote_typed<_Float16>(a, s);
     case ESK_F32: return launch_vote_typed<float>(a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_tight(const RebuildArgs &a, hipStream_t s)
+{
+    switch (a.vol.dtype) {
+    case ESK_U8: return launch_tight_typed<uint8_t>(a, s);
+    case ESK_U16: return launch_tight_typed<uint16_t>(a, s);
+    case ESK_F16: return launch_tight_typed<_Float16>(a, s);
+    case ESK_F32: return launch_tight_typed<float>(a, s);
     }
     return hipErrorInvalidValue;
 }

@@ -268,13 +268,13 @@ __device__ inline bool inside(const Vol &v, const float p[3])
            (p[2] < v.fn[2]);
 }
 
-// conservative hit of a box [lo, hi) (integer voxel bounds) by the ray segment
+// conservative hit of a box [lo/2, hi/2) (bounds in half-voxel units) by the ray segment
 __device__ inline bool hit_box(const Ray &r, float dt, const int lo[3], const int hi[3])
 {
     float l[3], h[3];
     for (int a = 0; a < 3; ++a) {
-        l[a] = (float)lo[a] - kBoxEps;
-        h[a] = (float)hi[a] + kBoxEps;
+        l[a] = (float)lo[a] * 0.5f - kBoxEps;
+        h[a] = (float)hi[a] * 0.5f + kBoxEps;
     }
     float tn, tf;
     slab_fast(r, l, h, tn, tf);
@@ -374,7 +374,7 @@ __device__ inline void march_grid(const Ray &r, float dt, int k, int k_end, cons
     }
 }
 
-// samples of the lattice that fall in the leaf box [lo, hi); HYB: only
+// samples of the lattice that fall in the leaf box [lo/2, hi/2); HYB: only
 // those in non-empty bricks, found with the macrocell grid (hybrid grid)
 template <typename T, typename IDX, bool HYB>
 __device__ inline void march_leaf(const Ray &r, float dt, const int lo[3], const int hi[3], const GridRef &gr,
@@ -382,8 +382,8 @@ __device__ inline void march_leaf(const Ray &r, float dt, const int lo[3], const
 {
     float l[3], h[3], bl[3], bh[3];
     for (int a = 0; a < 3; ++a) {
-        bl[a] = (float)lo[a];
-        bh[a] = (float)hi[a];
+        bl[a] = (float)lo[a] * 0.5f;   // half-voxel units: exact
+        bh[a] = (float)hi[a] * 0.5f;
         l[a] = bl[a] - kBoxEps;
         h[a] = bh[a] + kBoxEps;
     }
@@ -567,7 +567,8 @@ __device__ inline void render_tile(const RenderArgs &ra, int tbx, int tby)
             const int N = (int)ra.hdr->n;
             if (N > 0) {
                 int lo[3], hi[3];
-                for (int a = 0; a < 3; ++a) { lo[a] = ra.lb_lo[a]; hi[a] = ra.lb_hi[a]; }
+                const uint4 b = ra.lb_root[0];
+                unpack_box(b.x, b.y, b.z, lo, hi);
                 traverse<T, IDX, false>(r, dt, ra.lb_rnode, ra.lb_leafbox, grid_ref(ra), N == 1 ? kLeaf : 0u, lo, hi, stk,
                                  ra.stack_cap, vol, v, s, acc);
             }

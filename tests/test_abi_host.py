@@ -44,6 +44,9 @@ def test_workspace_bytes_and_limits():
     # 1024 bricks per axis is the Morton limit
     assert L.esk_workspace_bytes(8192, 8, 8, esk.U8, 8, 256, ctypes.byref(out)) == esk.OK
     assert L.esk_workspace_bytes(8193, 8, 8, esk.U8, 8, 256, ctypes.byref(out)) == esk.ELIMIT
+    # render boxes are uint16 in half-voxel units: at most 32767 voxels per axis
+    assert L.esk_workspace_bytes(32767, 8, 8, esk.U8, 32, 256, ctypes.byref(out)) == esk.OK
+    assert L.esk_workspace_bytes(32768, 8, 8, esk.U8, 32, 256, ctypes.byref(out)) == esk.ELIMIT
     # the renderer's blocked copy needs 64*R*ceil(nx/8)*ceil(ny/8) < 2^32 (R = 9 for f32, else 8)
     assert L.esk_workspace_bytes(22528, 22528, 32, esk.U8, 32, 256, ctypes.byref(out)) == esk.OK
     assert L.esk_workspace_bytes(22528, 22528, 32, esk.F32, 32, 256, ctypes.byref(out)) == esk.ELIMIT

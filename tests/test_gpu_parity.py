@@ -341,3 +341,64 @@ def test_per_voxel_vote(dims, B, dtype, seed):
     log(f"  vote flags {int(v.sum())} of {v.size} bricks (min/max: "
         f"{int(oracle.classify(mn, mx, vol.dtype, tf).sum())}); max|vote render - full march| "
         f"{np.abs(ref - full).max():.2e}")
+
+
+@pytest.mark.parametrize("dims,B,dtype,seed", [
+    ((45, 38, 29), 8, np.uint8, 0),
+    ((52, 33, 41), 4, np.float32, 1),
+    ((70, 64, 36), 16, np.float16, 2),
+    ((61, 40, 47), 8, np.uint16, 3),
+])
+def test_voxel_tight_boxes(dims, B, dtype, seed):
+    """Voxel-tight boxes: the per-brick boxes bit-exact against the oracle;
+    every mode still reproduces the full march bit for bit; the LBVH (leaves
+    = bricks) composites exactly the samples inside their bricks' tight boxes,
+    the k-d tree and the hybrid grid at least those and at most the full or
+    the brick-skipping sets."""
+    torch = _torch()
+    log(f"case: tight boxes {dims} B={B} {np.dtype(dtype).name}")
+    base = synth.blobs_u8(dims, seed=110 + seed, n_blobs=6, cut=40)
+    if dtype == np.uint8:
+        vol = base
+    elif dtype == np.uint16:
+        vol = (base.astype(np.uint16) * 257).astype(np.uint16)
+    else:
+        vol = (base.astype(np.float64) / 255.0).astype(dtype)
+    tf = synth.tf_random(seed + 50, 256)
+    esk, ctx = make_ctx()
+    ctx.set_volume(to_dev(vol), B, max_tf=256)
+    for kd in ((1, 0), (0, 0)):
+        ctx.set_tf(to_dev(tf), build=("grid", "lbvh", "kd"), kd=esk.Kd(kd[0], kd[1], 4), tight=True)
+        torch.cuda.synchronize()
+        mn, mx = oracle.brick_minmax(vol, B)
+        flags = oracle.classify(mn, mx, vol.dtype, tf)
+        assert np.array_equal(ctx.export("flags"), flags)
+        boxes = oracle.tight_boxes(vol, B, tf, flags)
+        assert np.array_equal(ctx.export("tight"), boxes)
+        # the exported hierarchies are those of the brick flags, unchanged
+        k = oracle.kd(flags, B, dims, kd[0], kd[1])
+        assert np.array_equal(ctx.export("kd_lo"), k["lo"]) and np.array_equal(ctx.export("kd_axis"), k["axis"])
+        W, H = 64, 48
+        cam = synth.perspective(dims, W, H, synth.view_direction(seed + 11))
+        ref, _ = oracle.render(vol, tf, cam, W, H, with_counts=True)
+        _, c_brick = oracle.render(vol, tf, cam, W, H, mode=1, flags=flags, B=B, with_counts=True)
+        _, c_tight = oracle.render(vol, tf, cam, W, H, mode=2, flags=flags, B=B, boxes=boxes, with_counts=True)
+        imgs = {}
+        for accel in ("none", "grid", "lbvh", "kd", "hybrid"):
+            cnt = torch.empty((H, W), dtype=torch.int32, device="cuda")
+            img = ctx.render(cam, W, H, accel=accel, counts=cnt)
+            torch.cuda.synchronize()
+            img, cnt = img.cpu().numpy(), cnt.cpu().numpy()
+            assert np.abs(img.astype(np.float64) - ref).max() <= TOL, accel
+            imgs[accel] = img
+            if accel == "lbvh":
+                assert np.array_equal(cnt, c_tight), (kd, accel)
+            elif accel == "grid":
+                assert np.array_equal(cnt, c_brick), (kd, accel)
+            elif accel == "hybrid":
+                assert np.all(cnt >= c_tight) and np.all(cnt <= c_brick), (kd, accel)
+            elif accel == "kd":
+                assert np.all(cnt >= c_tight), (kd, accel)
+        for accel in ("grid", "lbvh", "kd", "hybrid"):
+            assert np.array_equal(imgs[accel], imgs["none"]), (kd, accel)
+        log(f"  kd={kd}: samples full {int(ref.shape[0])}x, brick {int(c_brick.sum())}, tight {int(c_tight.sum())}")
