@@ -309,13 +309,11 @@ __global__ __launch_bounds__(1024) void k_kd_prefix_root_small(KdArgs k)
 // breadth-first order and publishes the next level.
 constexpr int kKdLevelBlocks = 128;
 
-// LDS_S: the grid is small enough (<= 32768 bricks) for every block that has
-// nodes to stage the whole prefix count in LDS first, so the binary searches
-// read LDS instead of L2
-template <bool LDS_S>
+// The binary searches read the prefix count through L2 (staging the whole
+// table in LDS per workgroup was measured slower: every busy workgroup of a
+// level copies it again).
 __global__ __launch_bounds__(256) void k_kd_level(KdArgs k)
 {
-    extern __shared__ int32_t Sl[];
     __shared__ int16_t tb[4][kMaxCand + 1][2][6];
     __shared__ uint32_t scratch[5];
     __shared__ uint32_t last;
@@ -323,36 +321,9 @@ __global__ __launch_bounds__(256) void k_kd_level(KdArgs k)
     if (begin == end) return;
     const int wave = threadIdx.x >> 6;
     const int64_t vroot = root_volume(k);
-    const bool busy = (int64_t)begin + (int64_t)blockIdx.x * 4 < (int64_t)end;  // uniform per block
-    if (LDS_S && busy) {
-        const int nb = k.nb[0] * k.nb[1] * k.nb[2];
-        const int n4 = nb >> 2;
-        const int4 *src = reinterpret_cast<const int4 *>(k.S);
-        int4 *dst = reinterpret_cast<int4 *>(Sl);
-        // eight 16-byte loads in flight per thread before the LDS writes
-        constexpr int U = 8;
-        for (int i0 = threadIdx.x; i0 < n4; i0 += 256 * U) {
-            int4 buf[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int i = i0 + u * 256;
-                buf[u] = i < n4 ? src[i] : make_int4(0, 0, 0, 0);
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int i = i0 + u * 256;
-                if (i < n4) dst[i] = buf[u];
-            }
-        }
-        for (int i = 4 * n4 + threadIdx.x; i < nb; i += 256) Sl[i] = k.S[i];
-        __syncthreads();
-    }
     for (int64_t node = (int64_t)begin + (int64_t)blockIdx.x * 4 + wave; node < end;
          node += (int64_t)gridDim.x * 4) {
-        if (LDS_S)
-            eval_node(k, (const int32_t *)Sl, node, vroot, tb[wave]);
-        else
-            eval_node(k, (const int32_t *)k.S, node, vroot, tb[wave]);
+        eval_node(k, (const int32_t *)k.S, node, vroot, tb[wave]);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -541,17 +512,7 @@ hipError_t launch_kd_prefix_root_small(const KdArgs &k, hipStream_t s)
 
 hipError_t launch_kd_levels(const KdArgs &k, int count, hipStream_t s)
 {
-    if (kd_small(k)) {
-        const size_t lds = sizeof(int32_t) * (size_t)k.nb[0] * k.nb[1] * k.nb[2];
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_kd_level<true>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        for (int i = 0; i < count; ++i)
-            hipLaunchKernelGGL(k_kd_level<true>, dim3(kKdLevelBlocks), dim3(256), lds, s, k);
-    } else {
-        for (int i = 0; i < count; ++i)
-            hipLaunchKernelGGL(k_kd_level<false>, dim3(kKdLevelBlocks), dim3(256), 0, s, k);
-    }
+    for (int i = 0; i < count; ++i) hipLaunchKernelGGL(k_kd_level, dim3(kKdLevelBlocks), dim3(256), 0, s, k);
     return hipGetLastError();
 }
 
