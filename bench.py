@@ -163,13 +163,40 @@ def batched_vs_plain(esk, torch, count=64, reps=5):
     same = all(np.array_equal(a.cpu().numpy(), b.cpu().numpy()) for a, b in zip(outs_p, outs_b))
     for c in ctxs:
         c.close()
+
+    # the same batch with brick sizes chosen per volume by the autotuner
+    # (rebuild + one frame, on each request's own TF and camera); images do
+    # not depend on the brick size, so they must equal the plain ones
+    from paper_1912_09596_amd.tune import tune_brick
+    t_tune = time.perf_counter()
+    chosen = [tune_brick(r["vol"], tf, r["cam"], (r["W"], r["H"]), accel="lbvh", reps=2)[0]
+              for r, tf in zip(reqs, tfs)]
+    tune_s = time.perf_counter() - t_tune
+    ctxs = []
+    for r, B in zip(reqs, chosen):
+        c = esk.Context(0)
+        c.set_volume(r["vol"], B, (0.0, 1.0), max_tf=256)
+        ctxs.append(c)
+    args = None
+    tt = timed(batched)
+    rt = timed(render_batched)
+    same_tuned = all(np.array_equal(a.cpu().numpy(), b.cpu().numpy()) for a, b in zip(outs_p, outs_b))
+    for c in ctxs:
+        c.close()
     return {"requests": count, "image": list(sizes[0]), "accel": "lbvh",
             "volumes": "axis sizes from {32..512}, u8 blobs at 1-20% density, own TF and camera each",
             "plain_mrays_per_s": round(rays / tp / 1e6, 1), "batched_mrays_per_s": round(rays / tb / 1e6, 1),
             "speedup": round(tp / tb, 3),
             "render_only": {"plain_mrays_per_s": round(rays / rp / 1e6, 1),
                             "batched_mrays_per_s": round(rays / rb / 1e6, 1), "speedup": round(rp / rb, 3)},
-            "images_identical": bool(same)}
+            "images_identical": bool(same),
+            "tuned_bricks": {"rule": "8^3 up to 128 voxels per axis, else 16^3 (above); tuned: per volume, "
+                                     "the brick of {8,16,32} minimising rebuild + one frame",
+                             "chosen": {str(b): chosen.count(b) for b in sorted(set(chosen))},
+                             "tuning_s": round(tune_s, 2),
+                             "batched_mrays_per_s": round(rays / tt / 1e6, 1),
+                             "render_only_batched_mrays_per_s": round(rays / rt / 1e6, 1),
+                             "images_identical": bool(same_tuned)}}
 
 
 def large_volumes(esk, torch, reps=3):
@@ -428,7 +455,9 @@ def counters_markdown(fetch_db, write_db, command):
            "", f"render.hip sha256: {src}", "",
            f"Copy probe (one plain 512 MiB device copy): FETCH_SIZE reads {copy_f:.0f} KiB, WRITE_SIZE "
            f"{copy_w:.0f} KiB of 524288 KiB moved, so FETCH_SIZE is scaled by {sf:.3f} and WRITE_SIZE by "
-           f"{sw:.3f}.", "",
+           f"{sw:.3f}.  Each row averages every dispatch of the kernel in the run: the timed steps, the "
+           f"warm-up and the phase-breakdown renders (for the k-d and LBVH renders these include the shallow "
+           f"tree and the voxel-tight variants).", "",
            "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes per launch |",
            "|---|---:|---:|---:|---:|"]
     for k in fetch:

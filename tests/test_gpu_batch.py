@@ -56,3 +56,29 @@ def test_batched_equals_alone(accel):
     one = esk.render_batch(ctxs[:1], [reqs[0]["cam"]], [(reqs[0]["W"], reqs[0]["H"])], accel=accel)
     torch.cuda.synchronize()
     assert np.array_equal(one[0].cpu().numpy(), alone[0].cpu().numpy())
+
+
+def test_brick_autotuner_choice_renders_the_same_image():
+    """The autotuner measures every candidate brick size and returns the
+    cheapest; the image does not depend on the brick size (every mode equals
+    the full march), so a render with the chosen size equals one with any
+    other size bit for bit."""
+    torch = _torch()
+    import paper_1912_09596_amd as esk
+    from paper_1912_09596_amd.tune import tune_brick
+    r = make_requests(1, 9)[0]
+    vol = torch.from_numpy(r["vol"]).cuda()
+    tf = torch.from_numpy(r["tf"]).cuda()
+    best, res = tune_brick(vol, tf, r["cam"], (r["W"], r["H"]), accel="lbvh", reps=2)
+    print(f"case: autotune {r['dims']}: {res}", flush=True)
+    assert best in res and set(res) <= {8, 16, 32}
+    assert res[best]["cost_ms"] == min(v["cost_ms"] for v in res.values())
+    imgs = []
+    for B in sorted(res):
+        c = esk.Context(0)
+        c.set_volume(vol, B, max_tf=256)
+        c.set_tf(tf, build=("lbvh",))
+        imgs.append(c.render(r["cam"], r["W"], r["H"], accel="lbvh").cpu().numpy())
+        c.close()
+    for im in imgs[1:]:
+        assert np.array_equal(im, imgs[0])
