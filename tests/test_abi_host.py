@@ -103,6 +103,10 @@ def test_tf_and_render_validation():
     assert st(v.c, FAKE, 256, esk.KD, ctypes.byref(esk.KdParams(1, 0, 1))) == esk.EINVAL
     assert st(v.c, FAKE, 256, esk.KD, ctypes.byref(esk.KdParams(1, 0, 17))) == esk.EINVAL
     assert st(v.c, FAKE, 256, esk.KD | esk.LBVH, ctypes.byref(kd)) == esk.ESTATE
+    # option bits: per-voxel vote and voxel-tight boxes are accepted, others not
+    assert st(v.c, FAKE, 256, esk.LBVH | esk.CLASSIFY_VOXEL | esk.TIGHT_BOXES, None) == esk.ESTATE
+    assert st(v.c, FAKE, 256, esk.LBVH | 0x400, None) == esk.EINVAL
+    assert st(v.c, FAKE, 256, esk.HYBRID, None) == esk.EINVAL      # a render mode, not a structure
     cam = esk.camera_struct(dict(ortho=0, eye=[0, 0, -10], dir00=[0, 0, 1], du=[0.01, 0, 0], dv=[0, -0.01, 0]))
     r = L.esk_render
     assert r(v.c, esk.LBVH, None, 64, 64, 0.5, 1.0, FAKE, None) == esk.EINVAL
@@ -115,6 +119,8 @@ def test_tf_and_render_validation():
     bad = esk.camera_struct(dict(ortho=0, eye=[0, math.inf, 0], dir00=[0, 0, 1], du=[1, 0, 0], dv=[0, 1, 0]))
     assert r(v.c, esk.LBVH, ctypes.byref(bad), 64, 64, 0.5, 1.0, FAKE, None) == esk.EINVAL
     assert r(v.c, esk.LBVH, ctypes.byref(cam), 64, 64, 0.5, 1.0, FAKE, None) == esk.ESTATE
+    assert r(v.c, esk.HYBRID, ctypes.byref(cam), 64, 64, 0.5, 1.0, FAKE, None) == esk.ESTATE
+    assert r(v.c, 16, ctypes.byref(cam), 64, 64, 0.5, 1.0, FAKE, None) == esk.EINVAL
     assert L.esk_sync(v.c) == esk.ESTATE
     s = esk.Stats()
     assert L.esk_get_stats(v.c, ctypes.byref(s)) == esk.ESTATE
