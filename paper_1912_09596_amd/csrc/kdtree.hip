@@ -307,7 +307,15 @@ __global__ __launch_bounds__(1024) void k_kd_prefix_root_small(KdArgs k)
 // Waves of a fixed grid evaluate the level's nodes; the last block to finish
 // (ticket counter, agent-scope release/acquire) numbers the children in
 // breadth-first order and publishes the next level.
-constexpr int kKdLevelBlocks = 128;
+// Workgroups per level launch, from the brick count (nb / 1024, clamped to
+// [32, 1024]): small grids have narrow levels, and the build runs beside the
+// first renders, so it should hold few CUs; wide levels of large grids need
+// the whole device.
+inline int kd_level_blocks(const KdArgs &k)
+{
+    const int64_t nb = (int64_t)k.nb[0] * k.nb[1] * k.nb[2];
+    return (int)std::min<int64_t>(1024, std::max<int64_t>(32, nb / 1024));
+}
 
 // The binary searches read the prefix count through L2 (staging the whole
 // table in LDS per workgroup was measured slower: every busy workgroup of a
@@ -512,7 +520,8 @@ hipError_t launch_kd_prefix_root_small(const KdArgs &k, hipStream_t s)
 
 hipError_t launch_kd_levels(const KdArgs &k, int count, hipStream_t s)
 {
-    for (int i = 0; i < count; ++i) hipLaunchKernelGGL(k_kd_level, dim3(kKdLevelBlocks), dim3(256), 0, s, k);
+    const int blocks = kd_level_blocks(k);
+    for (int i = 0; i < count; ++i) hipLaunchKernelGGL(k_kd_level, dim3(blocks), dim3(256), 0, s, k);
     return hipGetLastError();
 }
 
