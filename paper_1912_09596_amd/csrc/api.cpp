@@ -71,6 +71,7 @@ Layout make_layout(int nx, int ny, int nz, int brick, int elem_bytes, int max_tf
     L.lb_rnode = take((size_t)nb * sizeof(RNode));
     L.lb_leafbox = take((size_t)nb * 16);
     L.lb_root = take(16);
+    L.lb_chunk = take((size_t)((nb + 255) / 256) * 48);
     L.tbox = take((size_t)nb * 16);
     L.kd_S = take(n4);
     L.kd_lo = take(2 * n4 * 3);
@@ -426,6 +427,7 @@ static RebuildArgs rebuild_args(esk_ctx *c)
     value_norm(c, a.nlo, a.nscale);
     a.tbox = at<uint4>(c, L.tbox);
     a.lb_root = at<uint4>(c, L.lb_root);
+    a.lb_chunk = at<int32_t>(c, L.lb_chunk);
     return a;
 }
 

@@ -52,7 +52,7 @@ struct Layout {
     size_t header, swz, minv, maxv, tf, tfP, flags, grid, blkcnt;
     size_t ids, keys, skeys, tmpkeys, sids, hist;
     size_t tbox;           // voxel-tight box per brick (half-voxel units, packed)
-    size_t lb_left, lb_right, lb_axis, lb_parent, lb_lo, lb_hi, lb_range, lb_rnode, lb_leafbox, lb_root;
+    size_t lb_left, lb_right, lb_axis, lb_parent, lb_lo, lb_hi, lb_range, lb_rnode, lb_leafbox, lb_root, lb_chunk;
     size_t kd_S, kd_lo, kd_hi, kd_axis, kd_plane, kd_first, kd_split, kd_clo, kd_rnode, kd_box;
     size_t total;
 };
@@ -109,6 +109,7 @@ struct RebuildArgs {
     int tight;             // 1: render boxes of LBVH leaves are the voxel-tight boxes
     uint4 *tbox;           // per brick: packed voxel-tight box (written by k_tight)
     uint4 *lb_root;        // packed render box of the LBVH root
+    int32_t *lb_chunk;     // per chunk of 256 sorted leaves: union boxes (6 voxel + 6 half-voxel ints)
 };
 
 hipError_t launch_vote(const RebuildArgs &a, hipStream_t s);

@@ -247,6 +247,10 @@ __global__ __launch_bounds__(256) void k_warm(RebuildArgs a, int row_bytes, uint
     const int nq0 = a.vol.nq[0], nq1 = a.vol.nq[1], nq2 = a.vol.nq[2];
     const int blk16 = 64 * row_bytes / 16;   // 16-byte words per block
     const uint4 *swz = static_cast<const uint4 *>(a.vol.swz);
+    // only when the blocks fit the last-level cache (256 MB; budget 192 MB):
+    // beyond that the warm-up would evict its own lines before the render
+    const int64_t per_brick = B >= 8 ? (int64_t)(B >> 3) * (B >> 3) * (B >> 3) : 1;
+    if ((int64_t)n * per_brick * 64 * row_bytes > ((int64_t)192 << 20)) return;
     uint32_t acc = 0;
     for (int i = blockIdx.x; i < n; i += gridDim.x) {
         const uint32_t id = a.ids[i];
@@ -468,19 +472,26 @@ __global__ __launch_bounds__(256) void k_sort_hist(const uint32_t *in, const Dev
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// exclusive scan over the digit-major histogram (single workgroup)
-__global__ __launch_bounds__(1024) void k_sort_scan(uint32_t *hist, int64_t len)
+// exclusive scan over the digit-major histogram (single workgroup), over the
+// blocks that hold keys only: entry j of the scan is digit j / used of block
+// j % used (blocks past the key count have empty histograms and no keys)
+__global__ __launch_bounds__(1024) void k_sort_scan(uint32_t *hist, const DevHeader *hdr, int64_t nblocks)
 {
     __shared__ uint32_t scratch[17];
+    const int64_t used = min(nblocks, ((int64_t)hdr->n + kSortBlockKeys - 1) / kSortBlockKeys);
+    const int64_t len = 256 * used;
     const int64_t per = (len + 1023) / 1024;
     const int64_t i0 = threadIdx.x * per;
+    const int64_t i1 = min(len, i0 + per);
+    auto at = [&](int64_t j) -> uint32_t & { return hist[(j / used) * nblocks + j % used]; };
     uint32_t c = 0;
-    for (int64_t i = i0; i < min(len, i0 + per); ++i) c += hist[i];
+    for (int64_t j = i0; j < i1; ++j) c += at(j);
     uint32_t tot;
     uint32_t run = block_exclusive_scan<1024>(c, scratch, &tot);
-    for (int64_t i = i0; i < min(len, i0 + per); ++i) {
-        uint32_t t = hist[i];
-        hist[i] = run;
+    for (int64_t j = i0; j < i1; ++j) {
+        uint32_t &h = at(j);
+        const uint32_t t = h;
+        h = run;
         run += t;
     }
 }
@@ -595,7 +606,65 @@ __global__ __launch_bounds__(256) void k_karras(RebuildArgs a)
 // a8: AABBs.  Every internal node covers a contiguous range of sorted keys,
 // so its children's boxes are unions over two leaf ranges: one wave per
 // internal node reduces both ranges (no cross-node dependency, no atomics),
-// writes the node's own box (the union) and its traversal record.
+// writes the node's own box (the union) and its traversal record.  Ranges
+// longer than a few chunks read the per-chunk unions of k_lbvh_chunks for
+// their whole chunks, so the few nodes near the root do not each stream
+// every leaf.
+constexpr int kLeafChunk = 256;
+
+struct Box12 {
+    int b[6];    // exported AABB (voxels): lo xyz, hi xyz
+    int r[6];    // render box (half-voxel units): lo xyz, hi xyz
+};
+
+__device__ inline void box12_empty(Box12 &x)
+{
+    for (int q = 0; q < 3; ++q) {
+        x.b[q] = x.r[q] = 0x7fffffff;
+        x.b[3 + q] = x.r[3 + q] = -1;
+    }
+}
+
+__device__ inline void box12_leaf(const RebuildArgs &a, int n, int j, Box12 &x)
+{
+    const int u = (n - 1) + j;
+    int l2[3], h2[3];
+    const uint4 w = a.lb_leafbox[j];
+    unpack_box_u(w.x, w.y, w.z, l2, h2);
+    for (int q = 0; q < 3; ++q) {
+        x.b[q] = min(x.b[q], a.lb_lo[3 * u + q]);
+        x.b[3 + q] = max(x.b[3 + q], a.lb_hi[3 * u + q]);
+        x.r[q] = min(x.r[q], l2[q]);
+        x.r[3 + q] = max(x.r[3 + q], h2[q]);
+    }
+}
+
+__device__ inline void box12_wave(Box12 &x)
+{
+    for (int o = 32; o >= 1; o >>= 1)
+        for (int q = 0; q < 3; ++q) {
+            x.b[q] = min(x.b[q], __shfl_xor(x.b[q], o, 64));
+            x.b[3 + q] = max(x.b[3 + q], __shfl_xor(x.b[3 + q], o, 64));
+            x.r[q] = min(x.r[q], __shfl_xor(x.r[q], o, 64));
+            x.r[3 + q] = max(x.r[3 + q], __shfl_xor(x.r[3 + q], o, 64));
+        }
+}
+
+// union of the leaves of each chunk of kLeafChunk sorted keys (one wave each)
+__global__ __launch_bounds__(256) void k_lbvh_chunks(RebuildArgs a)
+{
+    const int n = (int)a.hdr->n;
+    const int lane = threadIdx.x & 63;
+    const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c * kLeafChunk >= n) return;
+    Box12 x;
+    box12_empty(x);
+    const int j1 = (int)min((int64_t)n, (c + 1) * kLeafChunk);
+    for (int j = (int)(c * kLeafChunk) + lane; j < j1; j += 64) box12_leaf(a, n, j, x);
+    box12_wave(x);
+    if (lane < 12) a.lb_chunk[12 * c + lane] = lane < 6 ? x.b[lane] : x.r[lane - 6];
+}
+
 __global__ __launch_bounds__(256) void k_lbvh_boxes(RebuildArgs a)
 {
     const int n = (int)a.hdr->n;
@@ -608,34 +677,27 @@ __global__ __launch_bounds__(256) void k_lbvh_boxes(RebuildArgs a)
     int box[2][6], rbox[2][6];
     for (int side = 0; side < 2; ++side) {
         const int j0 = side == 0 ? rg.x : g + 1, j1 = side == 0 ? g : rg.y;
-        // b: the union of the bricks (exported AABB, voxels); r: the union of
-        // the leaves' render boxes (half-voxel units)
-        int b[6] = {0x7fffffff, 0x7fffffff, 0x7fffffff, -1, -1, -1};
-        int r6[6] = {0x7fffffff, 0x7fffffff, 0x7fffffff, -1, -1, -1};
-        for (int j = j0 + lane; j <= j1; j += 64) {
-            const int u = (n - 1) + j;
-            for (int q = 0; q < 3; ++q) {
-                b[q] = min(b[q], a.lb_lo[3 * u + q]);
-                b[3 + q] = max(b[3 + q], a.lb_hi[3 * u + q]);
-            }
-            int l2[3], h2[3];
-            const uint4 w = a.lb_leafbox[j];
-            unpack_box_u(w.x, w.y, w.z, l2, h2);
-            for (int q = 0; q < 3; ++q) {
-                r6[q] = min(r6[q], l2[q]);
-                r6[3 + q] = max(r6[3 + q], h2[q]);
-            }
+        Box12 x;
+        box12_empty(x);
+        if (j1 - j0 + 1 <= 4 * kLeafChunk) {
+            for (int j = j0 + lane; j <= j1; j += 64) box12_leaf(a, n, j, x);
+        } else {
+            // leaves up to the first chunk boundary, whole chunks, leaves after the last
+            const int c0 = (j0 + kLeafChunk - 1) / kLeafChunk, c1 = (j1 + 1) / kLeafChunk;
+            for (int j = j0 + lane; j < c0 * kLeafChunk; j += 64) box12_leaf(a, n, j, x);
+            for (int c = c0 + lane; c < c1; c += 64)
+                for (int q = 0; q < 3; ++q) {
+                    x.b[q] = min(x.b[q], a.lb_chunk[12 * c + q]);
+                    x.b[3 + q] = max(x.b[3 + q], a.lb_chunk[12 * c + 3 + q]);
+                    x.r[q] = min(x.r[q], a.lb_chunk[12 * c + 6 + q]);
+                    x.r[3 + q] = max(x.r[3 + q], a.lb_chunk[12 * c + 9 + q]);
+                }
+            for (int j = c1 * kLeafChunk + lane; j <= j1; j += 64) box12_leaf(a, n, j, x);
         }
-        for (int o = 32; o >= 1; o >>= 1)
-            for (int q = 0; q < 3; ++q) {
-                b[q] = min(b[q], __shfl_xor(b[q], o, 64));
-                b[3 + q] = max(b[3 + q], __shfl_xor(b[3 + q], o, 64));
-                r6[q] = min(r6[q], __shfl_xor(r6[q], o, 64));
-                r6[3 + q] = max(r6[3 + q], __shfl_xor(r6[3 + q], o, 64));
-            }
+        box12_wave(x);
         for (int q = 0; q < 6; ++q) {
-            box[side][q] = b[q];
-            rbox[side][q] = r6[q];
+            box[side][q] = x.b[q];
+            rbox[side][q] = x.r[q];
         }
     }
     if (lane == 0) {
@@ -744,7 +806,7 @@ hipError_t launch_sort(const RebuildArgs &a, hipStream_t s)
         uint32_t *dst = ((passes - 1 - p) % 2 == 0) ? a.skeys : a.tmpkeys;
         hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)a.nsortblk), dim3(256), 0, s, src, a.hdr, 8 * p,
                            a.hist, a.nsortblk);
-        hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, a.hist, 256 * a.nsortblk);
+        hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, a.hist, a.hdr, a.nsortblk);
         hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)a.nsortblk), dim3(256), 0, s, src, dst, a.hdr,
                            8 * p, a.hist, a.nsortblk);
         src = dst;
@@ -756,6 +818,8 @@ hipError_t launch_lbvh(const RebuildArgs &a, hipStream_t s)
 {
     const unsigned blocks = (unsigned)((a.nb + 255) / 256);
     hipLaunchKernelGGL(k_karras, dim3(blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_lbvh_chunks, dim3((unsigned)((a.nb + 4 * kLeafChunk - 1) / (4 * kLeafChunk))), dim3(256), 0,
+                       s, a);
     hipLaunchKernelGGL(k_lbvh_boxes, dim3((unsigned)((a.nb + 3) / 4)), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_lbvh_height, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
