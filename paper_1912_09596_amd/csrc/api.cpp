@@ -688,12 +688,12 @@ esk_status esk_render_batch(esk_ctx *const *ctxs, int n, int accel, const esk_ca
         const int64_t nbytes = swz_bytes(r.vol.nq, elem_size(r.vol.dtype));
         narrow = narrow && nbytes < (int64_t)0xffffffffLL;
         tfl = tfl && r.N <= 1024;
-        tx = std::max(tx, (r.W + 15) / 16);
-        ty = std::max(ty, (r.H + 15) / 16);
+        tx = std::max(tx, (r.W + render_tile_for(accel) - 1) / render_tile_for(accel));
+        ty = std::max(ty, (r.H + render_tile_for(accel) - 1) / render_tile_for(accel));
     }
     for (int i = 0; i < n; ++i) {
         const RenderArgs &r = c0->staging[i];
-        lds = std::max(lds, (tfl ? (size_t)r.N * 16 : 0) + (size_t)r.stack_cap * 256 * sizeof(int));
+        lds = std::max(lds, (tfl ? (size_t)r.N * 16 : 0) + (size_t)r.stack_cap * render_threads_for(accel) * sizeof(int));
     }
     e = hipSetDevice(c0->device);
     if (e == hipSuccess)

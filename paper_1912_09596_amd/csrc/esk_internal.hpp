@@ -161,6 +161,18 @@ struct RenderArgs {
     int stack_cap;
 };
 
+// Render workgroups cover tile^2 pixels, one wave per 8x8 pixels: one wave
+// for the marches without a tree (fine-grained scheduling balances their
+// uneven per-tile work), 2x2 waves for the tree traversals (measured).
+__host__ __device__ constexpr int render_tile_for(int accel)
+{
+    return (accel == ESK_ACCEL_NONE || accel == ESK_ACCEL_GRID) ? 8 : 16;
+}
+__host__ __device__ constexpr int render_threads_for(int accel)
+{
+    return (render_tile_for(accel) / 8) * (render_tile_for(accel) / 8) * 64;
+}
+
 hipError_t launch_render(int accel, const RenderArgs &r, hipStream_t s);
 // n requests of one accel and volume dtype; d_args: n RenderArgs in device memory
 hipError_t launch_render_batch(int accel, int dtype, const RenderArgs *d_args, int n, int tiles_x, int tiles_y,

@@ -440,7 +440,7 @@ __device__ inline void unpack_box(uint32_t w0, uint32_t w1, uint32_t w2, int lo[
 // k-d): near child first by the sign of the direction along the node's
 // split axis, far child on an LDS stack (lane-interleaved), leaves marched
 // in the order they are reached.  Popped leaves fetch their packed box.
-template <typename T, typename IDX, bool HYB>
+template <typename T, typename IDX, bool HYB, int NT>
 __device__ inline void traverse(const Ray &r, float dt, const RNode *__restrict__ nodes,
                                 const uint4 *__restrict__ leafbox, const GridRef &gr, uint32_t root, int lo[3], int hi[3],
                                 int *stk, int cap, const T *__restrict__ vol, const Vol &v, const Shade &s,
@@ -468,7 +468,7 @@ __device__ inline void traverse(const Ray &r, float dt, const RNode *__restrict_
             const uint32_t nr = flip ? c1 : c0, fr = flip ? c0 : c1;
             if (hn) {
                 if (hf && sp < cap) {
-                    stk[sp * 256 + threadIdx.x] = (int)fr;
+                    stk[sp * NT + threadIdx.x] = (int)fr;
                     ++sp;
                 }
                 cur = nr;
@@ -489,7 +489,7 @@ __device__ inline void traverse(const Ray &r, float dt, const RNode *__restrict_
         }
         if (sp == 0) break;
         --sp;
-        cur = (uint32_t)stk[sp * 256 + threadIdx.x];
+        cur = (uint32_t)stk[sp * NT + threadIdx.x];
         if (cur & kLeaf) {
             const uint4 b = leafbox[cur & kIndexMask];
             unpack_box(b.x, b.y, b.z, lo, hi);
@@ -497,23 +497,25 @@ __device__ inline void traverse(const Ray &r, float dt, const RNode *__restrict_
     }
 }
 
-// One 16x16 pixel tile (tbx, tby) of one request.  TFL: the TF (N <= 1024
+// One kRenderTile^2 pixel tile (tbx, tby) of one request.  TFL: the TF (N <= 1024
 // entries) is staged in LDS; otherwise read from global memory.
 template <int ACCEL, typename T, typename IDX, bool TFL>
 __device__ inline void render_tile(const RenderArgs &ra, int tbx, int tby)
 {
     extern __shared__ float4 lds[];
     constexpr bool tf_lds = TFL;
+    constexpr int kRenderTile = render_tile_for(ACCEL), kRenderThreads = render_threads_for(ACCEL);
     if (tf_lds) {
         const float4 *src = reinterpret_cast<const float4 *>(ra.tf);
-        for (int i = threadIdx.x; i < ra.N; i += 256) lds[i] = src[i];
+        for (int i = threadIdx.x; i < ra.N; i += kRenderThreads) lds[i] = src[i];
         __syncthreads();
     }
     int *stk = reinterpret_cast<int *>(lds + (tf_lds ? ra.N : 0));
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int px = tbx * 16 + (wave & 1) * 8 + (lane & 7);
-    const int py = tby * 16 + (wave >> 1) * 8 + (lane >> 3);
+    constexpr int wx = kRenderTile / 8;   // waves per tile row
+    const int px = tbx * kRenderTile + (wave % wx) * 8 + (lane & 7);
+    const int py = tby * kRenderTile + (wave / wx) * 8 + (lane >> 3);
     if (px >= ra.W || py >= ra.H) return;
 
     const T *__restrict__ vol = static_cast<const T *>(ra.vol.swz);
@@ -569,7 +571,7 @@ __device__ inline void render_tile(const RenderArgs &ra, int tbx, int tby)
                 int lo[3], hi[3];
                 const uint4 b = ra.lb_root[0];
                 unpack_box(b.x, b.y, b.z, lo, hi);
-                traverse<T, IDX, false>(r, dt, ra.lb_rnode, ra.lb_leafbox, grid_ref(ra), N == 1 ? kLeaf : 0u, lo, hi, stk,
+                traverse<T, IDX, false, kRenderThreads>(r, dt, ra.lb_rnode, ra.lb_leafbox, grid_ref(ra), N == 1 ? kLeaf : 0u, lo, hi, stk,
                                  ra.stack_cap, vol, v, s, acc);
             }
         } else if (ACCEL == ESK_ACCEL_KD || ACCEL == ESK_ACCEL_HYBRID) {
@@ -578,7 +580,7 @@ __device__ inline void render_tile(const RenderArgs &ra, int tbx, int tby)
                 int lo[3], hi[3];
                 const uint4 b = ra.kd_box[0];
                 unpack_box(b.x, b.y, b.z, lo, hi);
-                traverse<T, IDX, ACCEL == ESK_ACCEL_HYBRID>(r, dt, ra.kd_rnode, ra.kd_box, grid_ref(ra),
+                traverse<T, IDX, ACCEL == ESK_ACCEL_HYBRID, kRenderThreads>(r, dt, ra.kd_rnode, ra.kd_box, grid_ref(ra),
                                                             M == 1 ? kLeaf : 0u, lo, hi, stk,
                                  ra.stack_cap, vol, v, s, acc);
             }
@@ -590,7 +592,7 @@ __device__ inline void render_tile(const RenderArgs &ra, int tbx, int tby)
 }
 
 template <int ACCEL, typename T, typename IDX, bool TFL>
-__global__ __launch_bounds__(256) void k_render(RenderArgs ra)
+__global__ __launch_bounds__(render_threads_for(ACCEL)) void k_render(RenderArgs ra)
 {
     // plain row-major tiles: the round-robin spread over the XCDs balances
     // the very uneven per-tile work (giving each XCD a band of tiles was
@@ -601,10 +603,11 @@ __global__ __launch_bounds__(256) void k_render(RenderArgs ra)
 // Many requests in one launch: blockIdx.z picks the request, whose tiles
 // cover the front of the (max-sized) grid; the rest of its blocks exit.
 template <int ACCEL, typename T, typename IDX, bool TFL>
-__global__ __launch_bounds__(256) void k_render_batch(const RenderArgs *__restrict__ args)
+__global__ __launch_bounds__(render_threads_for(ACCEL)) void k_render_batch(const RenderArgs *__restrict__ args)
 {
     const RenderArgs ra = args[blockIdx.z];
-    if ((int)blockIdx.x * 16 >= ra.W || (int)blockIdx.y * 16 >= ra.H) return;  // uniform per block
+    if ((int)blockIdx.x * render_tile_for(ACCEL) >= ra.W || (int)blockIdx.y * render_tile_for(ACCEL) >= ra.H)
+        return;  // uniform per block
     render_tile<ACCEL, T, IDX, TFL>(ra, blockIdx.x, blockIdx.y);
 }
 
@@ -616,7 +619,7 @@ hipError_t launch_batch_inst(const RenderArgs *d_args, const dim3 &grid, size_t 
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_render_batch<ACCEL, T, IDX, TFL>), grid, dim3(256), lds, s, d_args);
+    hipLaunchKernelGGL((k_render_batch<ACCEL, T, IDX, TFL>), grid, dim3(render_threads_for(ACCEL)), lds, s, d_args);
     return hipGetLastError();
 }
 
@@ -648,9 +651,10 @@ hipError_t launch_batch_typed(int accel, const RenderArgs *d_args, const dim3 &g
 template <int ACCEL, typename T>
 hipError_t launch_accel(const RenderArgs &r, hipStream_t s)
 {
-    const dim3 grid((r.W + 15) / 16, (r.H + 15) / 16);
+    constexpr int tile = render_tile_for(ACCEL);
+    const dim3 grid((r.W + tile - 1) / tile, (r.H + tile - 1) / tile);
     const size_t lds = (r.N <= 1024 ? (size_t)r.N * sizeof(float4) : 0) +
-                       (size_t)r.stack_cap * 256 * sizeof(int);
+                       (size_t)r.stack_cap * render_threads_for(ACCEL) * sizeof(int);
     const int64_t nbytes = swz_bytes(r.vol.nq, (int)sizeof(T));
     const bool narrow = nbytes < (int64_t)0xffffffffLL;
     const bool tfl = r.N <= 1024;
@@ -666,11 +670,11 @@ hipError_t launch_accel(const RenderArgs &r, hipStream_t s)
         if (e != hipSuccess) return e;
     }
     if (narrow) {
-        if (tfl) hipLaunchKernelGGL((k_render<ACCEL, T, uint32_t, true>), grid, dim3(256), lds, s, r);
-        else hipLaunchKernelGGL((k_render<ACCEL, T, uint32_t, false>), grid, dim3(256), lds, s, r);
+        if (tfl) hipLaunchKernelGGL((k_render<ACCEL, T, uint32_t, true>), grid, dim3(render_threads_for(ACCEL)), lds, s, r);
+        else hipLaunchKernelGGL((k_render<ACCEL, T, uint32_t, false>), grid, dim3(render_threads_for(ACCEL)), lds, s, r);
     } else {
-        if (tfl) hipLaunchKernelGGL((k_render<ACCEL, T, uint64_t, true>), grid, dim3(256), lds, s, r);
-        else hipLaunchKernelGGL((k_render<ACCEL, T, uint64_t, false>), grid, dim3(256), lds, s, r);
+        if (tfl) hipLaunchKernelGGL((k_render<ACCEL, T, uint64_t, true>), grid, dim3(render_threads_for(ACCEL)), lds, s, r);
+        else hipLaunchKernelGGL((k_render<ACCEL, T, uint64_t, false>), grid, dim3(render_threads_for(ACCEL)), lds, s, r);
     }
     return hipGetLastError();
 }
