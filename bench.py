@@ -199,6 +199,48 @@ def batched_vs_plain(esk, torch, count=64, reps=5):
                              "images_identical": bool(same_tuned)}}
 
 
+def graph_replay(esk, torch, count=200):
+    """Launch-bound requests: a 64^3 u8 volume rendered at 256x256 with the
+    LBVH, rebuilt for a new TF before every frame; eager calls against one
+    HIP graph holding the rebuild and the render (replayed with the TF
+    buffer refilled).  Requests per second, both issued back to back."""
+    import synth
+    from paper_1912_09596_amd.graphs import RebuildRenderGraph
+
+    w = synth.c1_workload()
+    vol = torch.from_numpy(w["vol"]).cuda()
+    cam = synth.perspective((64, 64, 64), 256, 256, synth.view_direction(3))
+    tfs = [torch.from_numpy(synth.tf_random(500 + i, 256)).cuda() for i in range(8)]
+    ctx = esk.Context(0)
+    ctx.set_volume(vol, 8, max_tf=256)
+    out = torch.empty((256, 256, 4), dtype=torch.float32, device="cuda")
+
+    def eager(n):
+        for i in range(n):
+            ctx.set_tf(tfs[i % 8], build=("lbvh",))
+            ctx.render(cam, 256, 256, accel="lbvh", out=out)
+        torch.cuda.synchronize()
+
+    g = RebuildRenderGraph(vol, 8, 256, cam, (256, 256), accel="lbvh")
+
+    def graph(n):
+        for i in range(n):
+            g.replay(tfs[i % 8])
+        torch.cuda.synchronize()
+
+    res = {}
+    for name, fn in (("eager", eager), ("graph", graph)):
+        fn(20)
+        t = time.perf_counter()
+        fn(count)
+        res[name + "_requests_per_s"] = round(count / (time.perf_counter() - t), 1)
+    res["speedup"] = round(res["graph_requests_per_s"] / res["eager_requests_per_s"], 3)
+    res["workload"] = "64^3 u8 blobs, 8^3 bricks, LBVH rebuild + 256x256 render per request"
+    g.close()
+    ctx.close()
+    return res
+
+
 def large_volumes(esk, torch, reps=3):
     """1024^3 tubes (~2 % of voxels) stored as f32 and f16, 2048^3 tubes stored
     as u16, 8^3 bricks: set_volume, rebuild per structure and 1080p render
@@ -674,6 +716,8 @@ def main():
         result["batched"] = batched_vs_plain(esk, torch)
         log("serving")
         result["serving"] = serving(esk, torch)
+        log("graph replay")
+        result["graph_replay"] = graph_replay(esk, torch)
     if not args.no_stats:
         log("node/height statistics")
         result["statistics"] = statistics_table(esk, torch, dvol)

@@ -82,3 +82,31 @@ def test_brick_autotuner_choice_renders_the_same_image():
         c.close()
     for im in imgs[1:]:
         assert np.array_equal(im, imgs[0])
+
+
+def test_rebuild_render_graph_replays():
+    """Rebuild + render captured once and replayed with three different TFs:
+    every replay equals the eager rebuild + render of the same TF bit for bit
+    (eager work and synchronisations between the replays)."""
+    torch = _torch()
+    import paper_1912_09596_amd as esk
+    from paper_1912_09596_amd.graphs import RebuildRenderGraph
+    r = make_requests(1, 5)[0]
+    vol = torch.from_numpy(r["vol"]).cuda()
+    print(f"case: graph capture {r['dims']} {r['W']}x{r['H']}", flush=True)
+    for accel in ("lbvh", "grid"):
+        g = RebuildRenderGraph(vol, r["B"], 256, r["cam"], (r["W"], r["H"]), accel=accel)
+        eager = esk.Context(0)
+        eager.set_volume(vol, r["B"], max_tf=256)
+        for seed in (11, 12, 13):
+            tf = torch.from_numpy(synth.tf_random(seed, 256)).cuda()
+            img = g.replay(tf)
+            g.stream.synchronize()
+            got = img.cpu().numpy().copy()
+            eager.set_tf(tf, build=(accel,))
+            want = eager.render(r["cam"], r["W"], r["H"], accel=accel).cpu().numpy()
+            torch.cuda.synchronize()
+            assert np.array_equal(got, want), (accel, seed)
+            assert np.abs(got).max() > 0
+        eager.close()
+        g.close()
