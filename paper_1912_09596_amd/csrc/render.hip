@@ -40,6 +40,10 @@ struct Ray {
     float o[3], d[3];
     float inv[3];   // 1/d (0 where d == 0): conservative tests only
     float t0, tx;
+    // the ray in half-voxel units (o2 = 2 o, inv2 = inv / 2): slab values
+    // against half-unit box bounds equal the voxel-unit ones bit for bit
+    // (scaling by 2 commutes with rounding), without converting each bound
+    float o2[3], inv2[3];
 };
 
 __device__ inline void make_ray(const esk_camera &c, int px, int py, Ray &r)
@@ -64,7 +68,23 @@ __device__ inline void make_ray(const esk_camera &c, int px, int py, Ray &r)
         // d == 0: a huge reciprocal makes the slab unbounded when the origin
         // is inside it and empty when outside, without a branch
         r.inv[a] = r.d[a] != 0.0f ? __builtin_amdgcn_rcpf(r.d[a]) : 1.0e30f;
+        r.o2[a] = r.o[a] * 2.0f;
+        r.inv2[a] = r.inv[a] * 0.5f;
     }
+}
+
+// slab_fast in half-voxel units: bounds lo2/hi2 are box bounds times 2
+__device__ inline void slab_half(const Ray &r, const float lo2[3], const float hi2[3], float &tn, float &tf)
+{
+    float t0 = -3.402823466e+38f, t1 = 3.402823466e+38f;
+    for (int a = 0; a < 3; ++a) {
+        const float ta = (lo2[a] - r.o2[a]) * r.inv2[a];
+        const float tb = (hi2[a] - r.o2[a]) * r.inv2[a];
+        t0 = fmaxf(t0, fminf(ta, tb));
+        t1 = fminf(t1, fmaxf(ta, tb));
+    }
+    tn = t0;
+    tf = t1;
 }
 
 __device__ inline bool slab(const Ray &r, const float lo[3], const float hi[3], float &tn, float &tf)
@@ -273,11 +293,11 @@ __device__ inline bool hit_box(const Ray &r, float dt, const int lo[3], const in
 {
     float l[3], h[3];
     for (int a = 0; a < 3; ++a) {
-        l[a] = (float)lo[a] * 0.5f - kBoxEps;
-        h[a] = (float)hi[a] * 0.5f + kBoxEps;
+        l[a] = (float)lo[a] - 2.0f * kBoxEps;
+        h[a] = (float)hi[a] + 2.0f * kBoxEps;
     }
     float tn, tf;
-    slab_fast(r, l, h, tn, tf);
+    slab_half(r, l, h, tn, tf);
     return tn <= tf + dt && tf >= r.t0 - dt && tn <= r.tx + dt;
 }
 
@@ -384,11 +404,11 @@ __device__ inline void march_leaf(const Ray &r, float dt, const int lo[3], const
     for (int a = 0; a < 3; ++a) {
         bl[a] = (float)lo[a] * 0.5f;   // half-voxel units: exact
         bh[a] = (float)hi[a] * 0.5f;
-        l[a] = bl[a] - kBoxEps;
-        h[a] = bh[a] + kBoxEps;
+        l[a] = (float)lo[a] - 2.0f * kBoxEps;
+        h[a] = (float)hi[a] + 2.0f * kBoxEps;
     }
     float tn, tf;
-    slab_fast(r, l, h, tn, tf);
+    slab_half(r, l, h, tn, tf);
     if (tn > tf + dt) return;
     const float idt = __builtin_amdgcn_rcpf(dt);
     float fa = (tn - r.t0) * idt - 0.5f;
