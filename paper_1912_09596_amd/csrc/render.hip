@@ -460,6 +460,8 @@ __device__ inline void unpack_box(uint32_t w0, uint32_t w1, uint32_t w2, int lo[
 // k-d): near child first by the sign of the direction along the node's
 // split axis, far child on an LDS stack (lane-interleaved), leaves marched
 // in the order they are reached.  Popped leaves fetch their packed box.
+// Each lane descends to its next leaf before any lane marches (lanes that
+// hold a leaf wait), so the leaf marches of a wave run together.
 template <typename T, typename IDX, bool HYB, int NT>
 __device__ inline void traverse(const Ray &r, float dt, const RNode *__restrict__ nodes,
                                 const uint4 *__restrict__ leafbox, const GridRef &gr, uint32_t root, int lo[3], int hi[3],
@@ -470,9 +472,9 @@ __device__ inline void traverse(const Ray &r, float dt, const RNode *__restrict_
     uint32_t cur = root;
     int sp = 0;
     while (true) {
-        if (cur & kLeaf) {
-            march_leaf<T, IDX, HYB>(r, dt, lo, hi, gr, vol, v, s, acc);
-        } else {
+        // descend until this lane holds a leaf (lanes that already hold one
+        // wait here), so that the lanes of a wave march their leaves together
+        while (!(cur & kLeaf)) {
             const uint4 *q = reinterpret_cast<const uint4 *>(&nodes[cur & kIndexMask]);
             const uint4 A = q[0], Q = q[1];
             int l0[3], h0[3], l1[3], h1[3];
@@ -486,28 +488,30 @@ __device__ inline void traverse(const Ray &r, float dt, const RNode *__restrict_
             const bool flip = da < 0.0f;
             const bool hn = flip ? hit1 : hit0, hf = flip ? hit0 : hit1;
             const uint32_t nr = flip ? c1 : c0, fr = flip ? c0 : c1;
-            if (hn) {
-                if (hf && sp < cap) {
+            if (hn || hf) {
+                if (hn && hf && sp < cap) {
                     stk[sp * NT + threadIdx.x] = (int)fr;
                     ++sp;
                 }
-                cur = nr;
+                const bool near = hn;
+                cur = near ? nr : fr;
+                const bool one = near == flip;   // child 1 taken
                 for (int a = 0; a < 3; ++a) {
-                    lo[a] = flip ? l1[a] : l0[a];
-                    hi[a] = flip ? h1[a] : h0[a];
+                    lo[a] = one ? l1[a] : l0[a];
+                    hi[a] = one ? h1[a] : h0[a];
                 }
                 continue;
             }
-            if (hf) {
-                cur = fr;
-                for (int a = 0; a < 3; ++a) {
-                    lo[a] = flip ? l0[a] : l1[a];
-                    hi[a] = flip ? h0[a] : h1[a];
-                }
-                continue;
+            if (sp == 0) return;
+            --sp;
+            cur = (uint32_t)stk[sp * NT + threadIdx.x];
+            if (cur & kLeaf) {
+                const uint4 b = leafbox[cur & kIndexMask];
+                unpack_box(b.x, b.y, b.z, lo, hi);
             }
         }
-        if (sp == 0) break;
+        march_leaf<T, IDX, HYB>(r, dt, lo, hi, gr, vol, v, s, acc);
+        if (sp == 0) return;
         --sp;
         cur = (uint32_t)stk[sp * NT + threadIdx.x];
         if (cur & kLeaf) {
