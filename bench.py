@@ -241,6 +241,53 @@ def graph_replay(esk, torch, count=200):
     return res
 
 
+def small_config(esk, torch, reps=20):
+    """The small configuration (64^3 u8 blobs, 8^3 bricks, 128x128, step 0.5):
+    set_volume, each rebuild from enqueue to completion (wall clock, with the
+    synchronisation), each render (HIP events); next to the latency floor of
+    one tiny kernel launch waited on the same way."""
+    import synth
+    w = synth.c1_workload()
+    vol = torch.from_numpy(w["vol"]).cuda()
+    tf = torch.from_numpy(w["tf"]).cuda()
+    ctx = esk.Context(0)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def wall(fn):
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t) * 1e3)
+        return round(statistics.median(ts), 4)
+
+    res = {"workload": "64^3 u8 blobs (~10% non-zero), 8^3 bricks, ramp TF, 128x128 perspective, step 0.5"}
+    res["set_volume_ms"] = wall(lambda: ctx.set_volume(vol, w["brick"], max_tf=256))
+    res["rebuild_ms"] = {a: wall(lambda a=a: ctx.set_tf(tf, build=(a,), kd=esk.Kd(1, 32, 4)) or ctx.sync())
+                         for a in ACCELS}
+    ctx.set_tf(tf, build=ACCELS, kd=esk.Kd(1, 32, 4))
+    out = torch.empty((w["H"], w["W"], 4), dtype=torch.float32, device="cuda")
+    render = {}
+    for a in ACCELS + ("none",):
+        ts = []
+        for _ in range(reps):
+            e0.record(stream)
+            ctx.render(w["cam"], w["W"], w["H"], accel=a, step=w["dt"], out=out)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        render[a] = round(statistics.median(ts), 4)
+    res["render_ms"] = render
+    res["render_mrays_per_s"] = {a: round(w["W"] * w["H"] / render[a] / 1e3, 1) for a in render}
+    x = torch.zeros(1, device="cuda")
+    res["launch_floor_ms"] = wall(lambda: x.add_(1.0))
+    ctx.close()
+    return res
+
+
 def large_volumes(esk, torch, reps=3):
     """1024^3 tubes (~2 % of voxels) stored as f32 and f16, 2048^3 tubes stored
     as u16, 8^3 bricks: set_volume, rebuild per structure and 1080p render
@@ -669,6 +716,27 @@ def main():
         ctx.render(cams[j], W, H, accel=a, out=outs["lbvh"], counts=cnt)
         tight[a + "_samples"] = int(cnt.sum().item())
 
+    # a plain device copy of the volume's size: the streaming rate this box
+    # reaches, next to which set_volume's rate is read
+    src = dvol.view(-1)
+    dst = torch.empty_like(src)
+    cp = []
+    for _ in range(5):
+        e0.record(stream)
+        dst.copy_(src)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        cp.append(e0.elapsed_time(e1))
+    del dst
+    copy_gbs = 2 * src.numel() * 4 / (statistics.median(cp) * 1e-3) / 1e9
+    # set_volume's algorithmic bytes: the min/max pass reads the volume and
+    # writes two values per brick; the blocked copy reads it and writes the
+    # blocked layout (8^3 blocks, rows of 9 values with the x apron)
+    nvox = DIMS[0] * DIMS[1] * DIMS[2]
+    nq = [(d + 7) // 8 for d in DIMS]
+    sv_bytes = nvox * 4 + 2 * st["n_bricks"] * 4 + nvox * 4 + nq[0] * nq[1] * nq[2] * 64 * 9 * 4
+    sv_gbs = sv_bytes / (statistics.median(sv) * 1e-3) / 1e9
+
     mean_ms = {a: statistics.mean(render_ms[a]) for a in ACCELS}
     dominant = max(ACCELS, key=lambda a: mean_ms[a])
     # algorithmic work: the samples of the non-empty bricks (what the grid
@@ -695,6 +763,8 @@ def main():
                    "image": [W, H], "brick": BRICK, "step_voxels": 0.5, "path": "plain"},
         "phases": {
             "set_volume_ms": round(statistics.median(sv), 4),
+            "set_volume_gb_per_s": {"achieved": round(sv_gbs, 1), "bytes": sv_bytes, "peak": 8000.0,
+                                    "measured_copy": round(copy_gbs, 1)},
             "rebuild": {a: {k: round(v, 4) for k, v in rebuild[a].items()} for a in ACCELS},
             "render_ms": {a: round(statistics.median(render_ms[a]), 4) for a in ACCELS},
             "render_mrays_per_s": {a: round(W * H / statistics.median(render_ms[a]) / 1e3, 1)
@@ -702,6 +772,8 @@ def main():
             "naive_render_ms": round(statistics.median(naive), 4),
             "naive_mrays_per_s": round(W * H / statistics.median(naive) / 1e3, 1),
             "samples_per_frame": samples,
+            "gsamples_per_s": {a: round(samples[a] / (statistics.median(render_ms[a]) * 1e-3) / 1e9, 2)
+                               for a in ACCELS},
             "bricks_nonempty": st["n_nonempty"], "lbvh_nodes": st["lbvh_nodes"],
             "lbvh_height": st["lbvh_height"], "kd_nodes": st["kd_nodes"], "kd_height": st["kd_height"],
             "shallow_kd_and_hybrid": shallow,
@@ -711,6 +783,8 @@ def main():
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP32_TFLOPS, 5), "traffic": measured_traffic(dominant)},
     }
+    log("small configuration (64^3 u8, 128x128)")
+    result["small_config"] = small_config(esk, torch)
     if not args.no_batch:
         log("batched vs plain")
         result["batched"] = batched_vs_plain(esk, torch)

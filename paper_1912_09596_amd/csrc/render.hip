@@ -524,10 +524,9 @@ __device__ inline void traverse(const Ray &r, float dt, const RNode *__restrict_
 // Waves per SIMD the render kernels are compiled for.  The scheduler
 // otherwise trades latency hiding for occupancy: aiming at 5-8 waves it
 // waits on each sample's gathers in turn instead of issuing a whole group
-// before the first wait (measured 20-40 % slower marches).
-#ifndef ESK_RENDER_WAVES
-#define ESK_RENDER_WAVES 3
-#endif
+// before the first wait (measured 20-40 % slower marches).  2 for the
+// full march, 3 for the others (measured best of 2..6).
+constexpr int render_waves_for(int accel) { return accel == ESK_ACCEL_NONE ? 2 : 3; }
 
 // One kRenderTile^2 pixel tile (tbx, tby) of one request.  TFL: the TF (N <= 1024
 // entries) is staged in LDS; otherwise read from global memory.
@@ -624,7 +623,7 @@ __device__ inline void render_tile(const RenderArgs &ra, int tbx, int tby)
 }
 
 template <int ACCEL, typename T, typename IDX, bool TFL>
-__global__ __launch_bounds__(render_threads_for(ACCEL)) __attribute__((amdgpu_waves_per_eu(1, ESK_RENDER_WAVES))) void
+__global__ __launch_bounds__(render_threads_for(ACCEL)) __attribute__((amdgpu_waves_per_eu(1, render_waves_for(ACCEL)))) void
 k_render(RenderArgs ra)
 {
     // plain row-major tiles: the round-robin spread over the XCDs balances
@@ -636,7 +635,7 @@ k_render(RenderArgs ra)
 // Many requests in one launch: blockIdx.z picks the request, whose tiles
 // cover the front of the (max-sized) grid; the rest of its blocks exit.
 template <int ACCEL, typename T, typename IDX, bool TFL>
-__global__ __launch_bounds__(render_threads_for(ACCEL)) __attribute__((amdgpu_waves_per_eu(1, ESK_RENDER_WAVES))) void
+__global__ __launch_bounds__(render_threads_for(ACCEL)) __attribute__((amdgpu_waves_per_eu(1, render_waves_for(ACCEL)))) void
 k_render_batch(const RenderArgs *__restrict__ args)
 {
     const RenderArgs ra = args[blockIdx.z];
