@@ -156,14 +156,15 @@ def test_ragged_volumes(dims, B, dtype, seed):
 
 
 def test_float_value_range_and_opacity_modes():
-    log("case: f32 with value range [-2, 3], dt 0.37 / 1.0, ref 0")
+    log("case: f32 with value range [-2, 3], dt 0.05 / 0.37 / 1.0 / 2.3 / 7.9, ref 0 / 1 / 2")
     dims = (40, 36, 44)
     base = synth.blobs_u8(dims, seed=77, n_blobs=6, cut=30).astype(np.float64)
     vol = (base / 255.0 * 5.0 - 2.0).astype(np.float32)
     tf = synth.tf_random(99, 300)
     esk, ctx, flags, _, _ = run_case(vol, tf, 8, lo=-2.0, hi=3.0, label="range")
     cam = synth.perspective(dims, 64, 48, synth.view_direction(9))
-    for dt, ref in ((0.37, 1.0), (1.0, 0.0), (0.5, 2.0)):
+    # fine and coarse steps (a step longer than a brick skips whole leaves)
+    for dt, ref in ((0.37, 1.0), (1.0, 0.0), (0.5, 2.0), (0.05, 1.0), (2.3, 1.0), (7.9, 0.0)):
         check_images(ctx, vol, tf, cam, 64, 48, flags, 8, lo=-2.0, hi=3.0, dt=dt, ref=ref,
                      label=f"dt={dt} ref={ref}")
 
