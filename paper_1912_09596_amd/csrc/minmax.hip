@@ -248,46 +248,82 @@ hipError_t launch_typed(const VolumeDesc &v, void *minv, void *maxv, hipStream_t
     return hipGetLastError();
 }
 
-// Blocked copy for the renderer: one workgroup per row of 8^3 blocks
-// (fixed qy, qz); threads stream voxel rows of the 8 x 8 slab coalesced and
-// write each voxel to its block.  Padding voxels (past the volume) are zero
-// and never sampled (the sampler clamps indices to the volume).
-// The blocked copy, one workgroup per run of up to 8 blocks along x of one
-// (block row, block slab): the 64 voxel rows of the run (plus the apron
-// voxel) are read with coalesced loads into LDS, then the blocks are written
-// out as one contiguous stretch, so every cache line of the copy is written
-// whole.
+// The blocked copy for the renderer, one workgroup per run of up to 8 blocks
+// along x of one (block row, block slab): the 64 voxel rows of the run (plus
+// the apron voxel) are staged in LDS, then the blocks are written out as one
+// contiguous stretch with 16-byte stores, so every cache line of the copy is
+// written whole.  VEC: rows are read with 16-byte loads (nx a multiple of
+// the 16-byte element count and a 16-byte aligned volume), else one element
+// per load.  Padding voxels (past the volume) are zero and never sampled
+// (the sampler clamps indices to the volume).
 constexpr int kSwzRun = 8;
 
-template <typename T>
+template <typename T, bool VEC>
 __global__ __launch_bounds__(256) void k_swizzle(const T *__restrict__ vol, int nx, int ny, int nz, int nqx,
                                                  int nqy, T *__restrict__ swz)
 {
     constexpr int ROW = swz_row((int)sizeof(T));
-    constexpr int W = kSwzRun * 8 + 1;   // staged voxels per row
-    __shared__ T tile[64 * W];
+    constexpr int V = 16 / (int)sizeof(T);                       // elements per 16-byte access
+    constexpr int W = (kSwzRun * 8 + 1 + V - 1) / V * V;         // staged row: 64 voxels, apron, padding
+    __shared__ __align__(16) T tile[64 * W];
     const int qx0 = blockIdx.x * kSwzRun, qy = blockIdx.y, qz = blockIdx.z;
     const int nblk = min(kSwzRun, nqx - qx0);
-    for (int i = threadIdx.x; i < 64 * W; i += 256) {
-        const int r = i / W, xi = i - r * W;
-        const int x = qx0 * 8 + xi, y = qy * 8 + (r & 7), z = qz * 8 + (r >> 3);
-        tile[i] = (x < nx && y < ny && z < nz) ? vol[((size_t)z * ny + y) * (size_t)nx + x] : (T)0;
+    const int x0 = qx0 * 8;
+    if (VEC) {
+        constexpr int CH = kSwzRun * 8 / V;   // 16-byte chunks per row
+        for (int i = threadIdx.x; i < 64 * CH; i += 256) {
+            const int r = i / CH, c = i - r * CH;
+            const int x = x0 + c * V, y = qy * 8 + (r & 7), z = qz * 8 + (r >> 3);
+            uint4 w = make_uint4(0u, 0u, 0u, 0u);
+            if (x < nx && y < ny && z < nz)
+                w = *reinterpret_cast<const uint4 *>(vol + ((size_t)z * ny + y) * (size_t)nx + x);
+            *reinterpret_cast<uint4 *>(&tile[r * W + c * V]) = w;
+        }
+        if (threadIdx.x < 64) {
+            const int r = threadIdx.x;
+            const int x = x0 + kSwzRun * 8, y = qy * 8 + (r & 7), z = qz * 8 + (r >> 3);
+            tile[r * W + kSwzRun * 8] = (x < nx && y < ny && z < nz) ? vol[((size_t)z * ny + y) * (size_t)nx + x] : (T)0;
+        }
+    } else {
+        for (int i = threadIdx.x; i < 64 * (kSwzRun * 8 + 1); i += 256) {
+            const int r = i / (kSwzRun * 8 + 1), xi = i - r * (kSwzRun * 8 + 1);
+            const int x = x0 + xi, y = qy * 8 + (r & 7), z = qz * 8 + (r >> 3);
+            tile[r * W + xi] = (x < nx && y < ny && z < nz) ? vol[((size_t)z * ny + y) * (size_t)nx + x] : (T)0;
+        }
     }
     __syncthreads();
+    // the run's blocks are contiguous; 64 * ROW elements per block is a
+    // multiple of V for every element type, so the stretch splits into
+    // whole 16-byte stores
     T *out = swz + (((size_t)qz * nqy + qy) * nqx + qx0) * (64 * ROW);
-    for (int i = threadIdx.x; i < nblk * 64 * ROW; i += 256) {
-        const int b = i / (64 * ROW), rem = i - b * (64 * ROW);
-        const int r = rem / ROW, xi = rem - r * ROW;
-        out[i] = tile[r * W + b * 8 + xi];
+    const int total = nblk * 64 * ROW;
+    for (int i = threadIdx.x * V; i < total; i += 256 * V) {
+        T v[V];
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            const int j = i + e;
+            const int b = j / (64 * ROW), rem = j - b * (64 * ROW);
+            const int r = rem / ROW, xi = rem - r * ROW;
+            v[e] = tile[r * W + b * 8 + xi];
+        }
+        uint4 w;
+        __builtin_memcpy(&w, v, 16);
+        *reinterpret_cast<uint4 *>(out + i) = w;
     }
 }
 
 template <typename T>
 hipError_t launch_swz_typed(const VolumeDesc &v, void *swz, hipStream_t s)
 {
+    static_assert((64 * swz_row((int)sizeof(T))) % (16 / (int)sizeof(T)) == 0, "blocks split into 16-byte stores");
     const dim3 grid((unsigned)((v.nq[0] + kSwzRun - 1) / kSwzRun), (unsigned)v.nq[1], (unsigned)v.nq[2]);
-    hipLaunchKernelGGL((k_swizzle<T>), grid, dim3(256), 0, s, static_cast<const T *>(v.vox), v.nx, v.ny, v.nz,
-                       v.nq[0], v.nq[1], static_cast<T *>(swz));
+    const bool vec = (v.nx % (16 / (int)sizeof(T)) == 0) && ((reinterpret_cast<uintptr_t>(v.vox) & 15) == 0);
+    if (vec)
+        hipLaunchKernelGGL((k_swizzle<T, true>), grid, dim3(256), 0, s, static_cast<const T *>(v.vox), v.nx, v.ny,
+                           v.nz, v.nq[0], v.nq[1], static_cast<T *>(swz));
+    else
+        hipLaunchKernelGGL((k_swizzle<T, false>), grid, dim3(256), 0, s, static_cast<const T *>(v.vox), v.nx, v.ny,
+                           v.nz, v.nq[0], v.nq[1], static_cast<T *>(swz));
     return hipGetLastError();
 }
 
