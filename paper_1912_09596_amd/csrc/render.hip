@@ -394,13 +394,13 @@ __device__ inline void march_grid(const Ray &r, float dt, int k, int k_end, cons
     }
 }
 
-// samples of the lattice that fall in the leaf box [lo/2, hi/2); HYB: only
-// those in non-empty bricks, found with the macrocell grid (hybrid grid)
-template <typename T, typename IDX, bool HYB>
-__device__ inline void march_leaf(const Ray &r, float dt, const int lo[3], const int hi[3], const GridRef &gr,
-                                  const T *__restrict__ vol, const Vol &v, const Shade &s, Accum &acc)
+// The sample range [ka, kb) that may fall in the leaf box [lo/2, hi/2)
+// (conservative: membership is decided per sample against bl/bh, the box in
+// voxels); an empty range where the ray misses the box.
+__device__ inline void leaf_range(const Ray &r, float dt, const int lo[3], const int hi[3], int &ka, int &kb,
+                                  float bl[3], float bh[3])
 {
-    float l[3], h[3], bl[3], bh[3];
+    float l[3], h[3];
     for (int a = 0; a < 3; ++a) {
         bl[a] = (float)lo[a] * 0.5f;   // half-voxel units: exact
         bh[a] = (float)hi[a] * 0.5f;
@@ -409,41 +409,27 @@ __device__ inline void march_leaf(const Ray &r, float dt, const int lo[3], const
     }
     float tn, tf;
     slab_half(r, l, h, tn, tf);
+    ka = kb = 0;
     if (tn > tf + dt) return;
     const float idt = __builtin_amdgcn_rcpf(dt);
     float fa = (tn - r.t0) * idt - 0.5f;
     float fb = (tf - r.t0) * idt - 0.5f;
     fa = fminf(fmaxf(fa, -4.0f), 1.0e9f);
     fb = fminf(fmaxf(fb, -4.0f), 1.0e9f);
-    const int ka = max(0, (int)floorf(fa) - 1);
-    const int kb = (int)floorf(fb) + 2;
-    if constexpr (HYB) {
-        march_grid<T, IDX>(r, dt, ka, kb, bl, bh, gr, vol, v, s, acc);
-        return;
-    }
-    for (int k = ka; k < kb; k += kGroup) {
-        // a group of consecutive samples: every gather is issued before the
-        // first value is composited (the clamped addresses are valid for
-        // any point), then the group is composited in k order
-        Corners g[kGroup];
-        bool ok[kGroup];
-        bool more = true;
-#pragma unroll
-        for (int j = 0; j < kGroup; ++j) {
-            const float t = lattice_t(r, dt, k + j);
-            float p[3];
-            point_at(r, t, p);
-            const bool live = t < r.tx;
-            ok[j] = (k + j < kb) & live & (p[0] >= bl[0]) & (p[0] < bh[0]) & (p[1] >= bl[1]) &
-                    (p[1] < bh[1]) & (p[2] >= bl[2]) & (p[2] < bh[2]);
-            gather<T, IDX>(vol, v, p, g[j]);
-            more = live;
-        }
-        group_fence();
-#pragma unroll
-        for (int j = 0; j < kGroup; ++j) composite(s, lerp3(g[j]), ok[j], acc);
-        if (!more) break;
-    }
+    ka = max(0, (int)floorf(fa) - 1);
+    kb = (int)floorf(fb) + 2;
+}
+
+// samples of the lattice that fall in the leaf box [lo/2, hi/2), found with
+// the macrocell grid (hybrid grid): only those in non-empty bricks
+template <typename T, typename IDX>
+__device__ inline void march_leaf_grid(const Ray &r, float dt, const int lo[3], const int hi[3], const GridRef &gr,
+                                       const T *__restrict__ vol, const Vol &v, const Shade &s, Accum &acc)
+{
+    int ka, kb;
+    float bl[3], bh[3];
+    leaf_range(r, dt, lo, hi, ka, kb, bl, bh);
+    if (ka < kb) march_grid<T, IDX>(r, dt, ka, kb, bl, bh, gr, vol, v, s, acc);
 }
 
 __device__ inline void unpack_box(uint32_t w0, uint32_t w1, uint32_t w2, int lo[3], int hi[3])
@@ -456,12 +442,76 @@ __device__ inline void unpack_box(uint32_t w0, uint32_t w1, uint32_t w2, int lo[
     hi[2] = (int)(w2 >> 16);
 }
 
+// Where a lane stands in its ordered traversal: cur is still to be visited
+// while `have` holds; sp entries wait on the lane's LDS stack.
+struct Trav {
+    uint32_t cur;
+    bool have;
+    int sp;
+};
+
 // Ordered traversal of a binary hierarchy stored as RNode records (LBVH or
 // k-d): near child first by the sign of the direction along the node's
-// split axis, far child on an LDS stack (lane-interleaved), leaves marched
-// in the order they are reached.  Popped leaves fetch their packed box.
-// Each lane descends to its next leaf before any lane marches (lanes that
-// hold a leaf wait), so the leaf marches of a wave run together.
+// split axis, far child on an LDS stack (lane-interleaved).  Descends to the
+// lane's next leaf (lo/hi: its box; popped leaves fetch their packed box);
+// false once the hierarchy is exhausted.
+template <int NT>
+__device__ inline bool next_leaf(const Ray &r, float dt, const RNode *__restrict__ nodes,
+                                 const uint4 *__restrict__ leafbox, int *stk, int cap, Trav &tr, int lo[3],
+                                 int hi[3])
+{
+    while (true) {
+        if (!tr.have) {
+            if (tr.sp == 0) return false;
+            --tr.sp;
+            tr.cur = (uint32_t)stk[tr.sp * NT + threadIdx.x];
+            if (tr.cur & kLeaf) {
+                const uint4 b = leafbox[tr.cur & kIndexMask];
+                unpack_box(b.x, b.y, b.z, lo, hi);
+            }
+            tr.have = true;
+        }
+        if (tr.cur & kLeaf) {
+            tr.have = false;
+            return true;
+        }
+        const uint4 *q = reinterpret_cast<const uint4 *>(&nodes[tr.cur & kIndexMask]);
+        const uint4 A = q[0], Q = q[1];
+        int l0[3], h0[3], l1[3], h1[3];
+        unpack_box(A.x, A.y, A.z, l0, h0);
+        unpack_box(A.w, Q.x, Q.y, l1, h1);
+        const uint32_t c0 = Q.z & (kLeaf | kIndexMask), c1 = Q.w;
+        const int axis = (int)((Q.z >> 29) & 3u);
+        const bool hit0 = hit_box(r, dt, l0, h0), hit1 = hit_box(r, dt, l1, h1);
+        // select, not index: a dynamic index would move the ray to scratch
+        const float da = axis == 0 ? r.d[0] : (axis == 1 ? r.d[1] : r.d[2]);
+        const bool flip = da < 0.0f;
+        const bool hn = flip ? hit1 : hit0, hf = flip ? hit0 : hit1;
+        const uint32_t nr = flip ? c1 : c0, fr = flip ? c0 : c1;
+        if (hn || hf) {
+            if (hn && hf && tr.sp < cap) {
+                stk[tr.sp * NT + threadIdx.x] = (int)fr;
+                ++tr.sp;
+            }
+            tr.cur = hn ? nr : fr;
+            const bool one = hn == flip;   // child 1 taken
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = one ? l1[a] : l0[a];
+                hi[a] = one ? h1[a] : h0[a];
+            }
+        } else {
+            tr.have = false;
+        }
+    }
+}
+
+// The tree renders: each round every lane descends to its next two leaves
+// (lanes that hold them wait, so the wave's descents run together), then
+// marches their samples as one sequence in groups -- leaf one's range, then
+// leaf two's, in ray order -- so a round costs the wave its longest pair of
+// leaves rather than its longest leaf twice (measured: three or four leaves
+// per round gain nothing more).  HYB: each leaf is marched with the
+// macrocell grid inside it (hybrid grid).
 template <typename T, typename IDX, bool HYB, int NT>
 __device__ inline void traverse(const Ray &r, float dt, const RNode *__restrict__ nodes,
                                 const uint4 *__restrict__ leafbox, const GridRef &gr, uint32_t root, int lo[3], int hi[3],
@@ -469,55 +519,48 @@ __device__ inline void traverse(const Ray &r, float dt, const RNode *__restrict_
                                 Accum &acc)
 {
     if (!hit_box(r, dt, lo, hi)) return;
-    uint32_t cur = root;
-    int sp = 0;
+    Trav tr{root, true, 0};
     while (true) {
-        // descend until this lane holds a leaf (lanes that already hold one
-        // wait here), so that the lanes of a wave march their leaves together
-        while (!(cur & kLeaf)) {
-            const uint4 *q = reinterpret_cast<const uint4 *>(&nodes[cur & kIndexMask]);
-            const uint4 A = q[0], Q = q[1];
-            int l0[3], h0[3], l1[3], h1[3];
-            unpack_box(A.x, A.y, A.z, l0, h0);
-            unpack_box(A.w, Q.x, Q.y, l1, h1);
-            const uint32_t c0 = Q.z & (kLeaf | kIndexMask), c1 = Q.w;
-            const int axis = (int)((Q.z >> 29) & 3u);
-            const bool hit0 = hit_box(r, dt, l0, h0), hit1 = hit_box(r, dt, l1, h1);
-            // select, not index: a dynamic index would move the ray to scratch
-            const float da = axis == 0 ? r.d[0] : (axis == 1 ? r.d[1] : r.d[2]);
-            const bool flip = da < 0.0f;
-            const bool hn = flip ? hit1 : hit0, hf = flip ? hit0 : hit1;
-            const uint32_t nr = flip ? c1 : c0, fr = flip ? c0 : c1;
-            if (hn || hf) {
-                if (hn && hf && sp < cap) {
-                    stk[sp * NT + threadIdx.x] = (int)fr;
-                    ++sp;
+        if (!next_leaf<NT>(r, dt, nodes, leafbox, stk, cap, tr, lo, hi)) return;
+        int lo2[3], hi2[3];
+        const bool two = next_leaf<NT>(r, dt, nodes, leafbox, stk, cap, tr, lo2, hi2);
+        if constexpr (HYB) {
+            march_leaf_grid<T, IDX>(r, dt, lo, hi, gr, vol, v, s, acc);
+            if (two) march_leaf_grid<T, IDX>(r, dt, lo2, hi2, gr, vol, v, s, acc);
+        } else {
+            int ka1, kb1, ka2 = 0, kb2 = 0;
+            float bl1[3], bh1[3], bl2[3] = {0.0f, 0.0f, 0.0f}, bh2[3] = {0.0f, 0.0f, 0.0f};
+            leaf_range(r, dt, lo, hi, ka1, kb1, bl1, bh1);
+            if (two) leaf_range(r, dt, lo2, hi2, ka2, kb2, bl2, bh2);
+            const int n1 = max(0, kb1 - ka1), n = n1 + max(0, kb2 - ka2);
+            for (int i = 0; i < n; i += kGroup) {
+                // a group of the sequence: the points first, then every
+                // gather (the clamped addresses are valid for any point),
+                // then the group is composited in order
+                Corners g[kGroup];
+                bool ok[kGroup];
+                float p[kGroup][3];
+#pragma unroll
+                for (int j = 0; j < kGroup; ++j) {
+                    const int idx = i + j;
+                    const bool first = idx < n1;
+                    const int k = first ? ka1 + idx : ka2 + (idx - n1);
+                    const float t = lattice_t(r, dt, k);
+                    point_at(r, t, p[j]);
+                    bool in = (idx < n) & (t < r.tx);
+                    for (int a = 0; a < 3; ++a)
+                        in = in & (p[j][a] >= (first ? bl1[a] : bl2[a])) & (p[j][a] < (first ? bh1[a] : bh2[a]));
+                    ok[j] = in;
                 }
-                const bool near = hn;
-                cur = near ? nr : fr;
-                const bool one = near == flip;   // child 1 taken
-                for (int a = 0; a < 3; ++a) {
-                    lo[a] = one ? l1[a] : l0[a];
-                    hi[a] = one ? h1[a] : h0[a];
-                }
-                continue;
-            }
-            if (sp == 0) return;
-            --sp;
-            cur = (uint32_t)stk[sp * NT + threadIdx.x];
-            if (cur & kLeaf) {
-                const uint4 b = leafbox[cur & kIndexMask];
-                unpack_box(b.x, b.y, b.z, lo, hi);
+                group_fence();
+#pragma unroll
+                for (int j = 0; j < kGroup; ++j) gather<T, IDX>(vol, v, p[j], g[j]);
+                group_fence();
+#pragma unroll
+                for (int j = 0; j < kGroup; ++j) composite(s, lerp3(g[j]), ok[j], acc);
             }
         }
-        march_leaf<T, IDX, HYB>(r, dt, lo, hi, gr, vol, v, s, acc);
-        if (sp == 0) return;
-        --sp;
-        cur = (uint32_t)stk[sp * NT + threadIdx.x];
-        if (cur & kLeaf) {
-            const uint4 b = leafbox[cur & kIndexMask];
-            unpack_box(b.x, b.y, b.z, lo, hi);
-        }
+        if (!two) return;
     }
 }
 
