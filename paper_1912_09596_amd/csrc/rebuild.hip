@@ -390,6 +390,70 @@ __global__ __launch_bounds__(256) void k_compact(RebuildArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// a4-a6 in Morton order: bricks lie on a grid, so enumerating the Morton
+// codes of the brick grid in ascending order and keeping those of non-empty
+// bricks yields the sorted keys directly -- the same array the radix sort
+// produces (keys are unique), without sorting.  Used while the code domain
+// 2^key_bits is at most 4x the brick count (near-cubic brick grids); one
+// block per 1024 codes: count, scan of the block counts, scatter.
+// ---------------------------------------------------------------------------
+constexpr int kMortonBlock = 1024;
+
+__device__ inline bool morton_flag(const RebuildArgs &a, uint32_t m)
+{
+    const uint32_t bx = compact3(m >> 2), by = compact3(m >> 1), bz = compact3(m);
+    if (bx >= (uint32_t)a.vol.nb[0] || by >= (uint32_t)a.vol.nb[1] || bz >= (uint32_t)a.vol.nb[2]) return false;
+    return a.flags[bx + (int64_t)a.vol.nb[0] * (by + (int64_t)a.vol.nb[1] * bz)] != 0;
+}
+
+__global__ __launch_bounds__(256) void k_morton_count(RebuildArgs a, uint32_t *cnt, int64_t codes)
+{
+    __shared__ uint32_t wcount[4];
+    const int64_t base = (int64_t)blockIdx.x * kMortonBlock;
+    uint32_t c = 0;
+    for (int j = 0; j < 4; ++j) {
+        const int64_t m = base + 256 * j + threadIdx.x;
+        const bool f = m < codes && morton_flag(a, (uint32_t)m);
+        c += (uint32_t)__popcll(__ballot(f));
+    }
+    if ((threadIdx.x & 63) == 0) wcount[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) cnt[blockIdx.x] = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+}
+
+// cnt: exclusive block offsets (k_scan_blocks)
+__global__ __launch_bounds__(256) void k_morton_scatter(RebuildArgs a, const uint32_t *cnt, int64_t codes)
+{
+    __shared__ uint32_t woff[16];
+    const int64_t base = (int64_t)blockIdx.x * kMortonBlock;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    bool f[4];
+    uint64_t mk[4];
+    for (int j = 0; j < 4; ++j) {
+        const int64_t m = base + 256 * j + threadIdx.x;
+        f[j] = m < codes && morton_flag(a, (uint32_t)m);
+        mk[j] = __ballot(f[j]);
+        if (lane == 0) woff[4 * j + wave] = (uint32_t)__popcll(mk[j]);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // codes ascend with j, then wave, then lane
+        uint32_t run = cnt[blockIdx.x];
+        for (int q = 0; q < 16; ++q) {
+            const uint32_t t = woff[q];
+            woff[q] = run;
+            run += t;
+        }
+    }
+    __syncthreads();
+    for (int j = 0; j < 4; ++j)
+        if (f[j]) {
+            const uint32_t pos = woff[4 * j + wave] + (uint32_t)__popcll(mk[j] & lanemask_lt());
+            a.skeys[pos] = (uint32_t)(base + 256 * j + threadIdx.x);
+        }
+}
+
+// ---------------------------------------------------------------------------
 // a6: LSD radix sort of the Morton keys (ids are recovered from keys)
 // ---------------------------------------------------------------------------
 
@@ -791,6 +855,17 @@ hipError_t launch_classify_compact(const RebuildArgs &a, hipStream_t s)
 
 hipError_t launch_sort(const RebuildArgs &a, hipStream_t s)
 {
+    const int64_t codes = (int64_t)1 << a.key_bits;
+    if (codes <= 4 * a.nb) {
+        // sorted keys by enumeration; the block counts go to `hist` (the
+        // sort's histogram, unused on this path: ceil(nb/4096)*256 entries
+        // >= codes/1024 blocks)
+        const unsigned blocks = (unsigned)((codes + kMortonBlock - 1) / kMortonBlock);
+        hipLaunchKernelGGL(k_morton_count, dim3(blocks), dim3(256), 0, s, a, a.hist, codes);
+        hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, a.hist, (int64_t)blocks, a.hdr);
+        hipLaunchKernelGGL(k_morton_scatter, dim3(blocks), dim3(256), 0, s, a, a.hist, codes);
+        return hipGetLastError();
+    }
     if (a.nb <= kSortSingleMax) {
         const size_t lds = sizeof(uint32_t) * (kSortSingleMax + kSortSingleMax / 32);
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sort_single),
