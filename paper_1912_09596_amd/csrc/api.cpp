@@ -398,6 +398,7 @@ static RebuildArgs rebuild_args(esk_ctx *c)
     a.vhi = c->vhi;
     a.N = c->N;
     a.tf = at<float>(c, L.tf);
+    a.tf_src = nullptr;
     a.tfP = at<int32_t>(c, L.tfP);
     a.minv = c->ws + L.minv;
     a.maxv = c->ws + L.maxv;
@@ -492,9 +493,9 @@ esk_status esk_set_transfer_function(esk_ctx *c, const float *d_rgba, int n_entr
     c->kd_on_device = false;
     c->N = n_entries;
     const Layout &L = c->L;
-    e = hipMemcpyAsync(c->ws + L.tf, d_rgba, (size_t)n_entries * 16, hipMemcpyDeviceToDevice, c->stream);
-    if (e != hipSuccess) return hip_check(c, e, "TF copy");
+    // k_classify copies the TF into the workspace for the renderer
     RebuildArgs a = rebuild_args(c);
+    a.tf_src = d_rgba;
     if (build_mask & ESK_CLASSIFY_VOXEL) {
         a.vote = 1;
         e = launch_vote(a, c->stream);

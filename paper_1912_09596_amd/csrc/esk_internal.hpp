@@ -89,7 +89,8 @@ struct RebuildArgs {
     VolumeDesc vol;
     float vlo, vhi;
     int N;                 // TF entries
-    const float *tf;       // workspace copy
+    float *tf;             // workspace copy (written by k_classify, read by the renderer)
+    const float *tf_src;   // the caller's TF (read by the vote and k_classify)
     int32_t *tfP;
     const void *minv, *maxv;
     uint8_t *flags;

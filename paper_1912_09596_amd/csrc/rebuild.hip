@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void k_vote(RebuildArgs a)
 {
     __shared__ float alpha[kMaxTF];
     const int N = a.N;
-    for (int i = threadIdx.x; i < N; i += 256) alpha[i] = a.tf[4 * i + 3];
+    for (int i = threadIdx.x; i < N; i += 256) alpha[i] = a.tf_src[4 * i + 3];
     __syncthreads();
     const int B = a.vol.B, sh = a.vol.log2B;
     const int nx = a.vol.nx, ny = a.vol.ny, nz = a.vol.nz;
@@ -286,17 +286,21 @@ __global__ __launch_bounds__(256) void k_classify(RebuildArgs a)
         const int per = (N + 255) / 256;
         const int i0 = threadIdx.x * per;
         uint32_t c = 0;
-        for (int i = i0; i < min(N, i0 + per); ++i) c += a.tf[4 * i + 3] > 0.0f ? 1u : 0u;
+        for (int i = i0; i < min(N, i0 + per); ++i) c += a.tf_src[4 * i + 3] > 0.0f ? 1u : 0u;
         uint32_t tot;
         uint32_t run = block_exclusive_scan<256>(c, scratch, &tot);
         for (int i = i0; i < min(N, i0 + per); ++i) {
             P[i] = (int32_t)run;
-            run += a.tf[4 * i + 3] > 0.0f ? 1u : 0u;
+            run += a.tf_src[4 * i + 3] > 0.0f ? 1u : 0u;
         }
         if (threadIdx.x == 0) P[N] = (int32_t)tot;
         __syncthreads();
-        if (blockIdx.x == 0)
+        if (blockIdx.x == 0) {
             for (int i = threadIdx.x; i <= N; i += 256) a.tfP[i] = P[i];
+            // the renderer's copy of the TF (both 16-byte aligned)
+            for (int i = threadIdx.x; i < N; i += 256)
+                reinterpret_cast<float4 *>(a.tf)[i] = reinterpret_cast<const float4 *>(a.tf_src)[i];
+        }
     }
     const int64_t base = (int64_t)blockIdx.x * kClassifyBlock;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -606,72 +610,11 @@ __device__ inline int delta(const uint32_t *k, int n, int i, int j)
 // gets its children (Karras 2012: direction, range by doubling + binary
 // search, split by binary search) and registers itself as their parent.
 // Node numbering: internal i -> i, leaf j -> (n-1)+j.
-__global__ __launch_bounds__(256) void k_karras(RebuildArgs a)
-{
-    const int n = (int)a.hdr->n;
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t *k = a.skeys;
-    {
-        const uint32_t key = k[i];
-        const uint32_t bx = compact3(key >> 2), by = compact3(key >> 1), bz = compact3(key);
-        a.sids[i] = bx + (uint32_t)a.vol.nb[0] * (by + (uint32_t)a.vol.nb[1] * bz);
-        const int node = (n - 1) + i;
-        const int b[3] = {(int)bx, (int)by, (int)bz};
-        const int nn[3] = {a.vol.nx, a.vol.ny, a.vol.nz};
-        int lo2[3], hi2[3];
-        for (int q = 0; q < 3; ++q) {
-            a.lb_lo[3 * node + q] = a.vol.B * b[q];
-            a.lb_hi[3 * node + q] = min(a.vol.B * b[q] + a.vol.B, nn[q]);
-            lo2[q] = 2 * a.lb_lo[3 * node + q];
-            hi2[q] = 2 * a.lb_hi[3 * node + q];
-        }
-        // the leaf's render box: its brick, or the brick's voxel-tight box
-        uint4 box;
-        if (a.tight) {
-            box = a.tbox[a.sids[i]];
-        } else {
-            uint32_t w[3];
-            pack_box(lo2, hi2, w);
-            box = make_uint4(w[0], w[1], w[2], 0u);
-        }
-        a.lb_leafbox[i] = box;
-        if (n == 1) a.lb_root[0] = box;
-    }
-    if (i >= n - 1) return;
-    const int d = (delta(k, n, i, i + 1) - delta(k, n, i, i - 1)) > 0 ? 1 : -1;
-    const int dmin = delta(k, n, i, i - d);
-    int lmax = 2;
-    while (delta(k, n, i, i + lmax * d) > dmin) lmax <<= 1;
-    int l = 0;
-    for (int t = lmax >> 1; t >= 1; t >>= 1)
-        if (delta(k, n, i, i + (l + t) * d) > dmin) l += t;
-    const int j = i + l * d;
-    const int dnode = delta(k, n, i, j);
-    int s = 0;
-    for (int div = 2;; div <<= 1) {
-        const int t = (l + div - 1) / div;
-        if (delta(k, n, i, i + (s + t) * d) > dnode) s += t;
-        if (t == 1) break;
-    }
-    const int g = i + s * d + min(d, 0);
-    const int lo = min(i, j), hi = max(i, j);
-    const uint32_t left = (lo == g) ? (kLeaf | (uint32_t)g) : (uint32_t)g;
-    const uint32_t right = (hi == g + 1) ? (kLeaf | (uint32_t)(g + 1)) : (uint32_t)(g + 1);
-    a.lb_left[i] = left;
-    a.lb_right[i] = right;
-    const int hb = 31 - dnode;  // highest differing bit of the range
-    a.lb_axis[i] = 2 - hb % 3;
-    a.lb_parent[(left & kLeaf) ? (n - 1) + g : g] = (uint32_t)i;
-    a.lb_parent[(right & kLeaf) ? (n - 1) + g + 1 : g + 1] = (uint32_t)i;
-    a.lb_range[i] = make_int2(lo, hi);
-}
-
 // a8: AABBs.  Every internal node covers a contiguous range of sorted keys,
 // so its children's boxes are unions over two leaf ranges: one wave per
 // internal node reduces both ranges (no cross-node dependency, no atomics),
 // writes the node's own box (the union) and its traversal record.  Ranges
-// longer than a few chunks read the per-chunk unions of k_lbvh_chunks for
+// longer than a few chunks read the per-chunk unions (written by k_karras) for
 // their whole chunks, so the few nodes near the root do not each stream
 // every leaf.
 constexpr int kLeafChunk = 256;
@@ -714,19 +657,97 @@ __device__ inline void box12_wave(Box12 &x)
         }
 }
 
-// union of the leaves of each chunk of kLeafChunk sorted keys (one wave each)
-__global__ __launch_bounds__(256) void k_lbvh_chunks(RebuildArgs a)
+// Karras nodes and leaf boxes.  A block's 256 leaves are one chunk of
+// kLeafChunk sorted keys: the block also writes the chunk's union boxes
+// (read by k_lbvh_boxes for long ranges).
+static_assert(kLeafChunk == 256, "one k_karras block per leaf chunk");
+__global__ __launch_bounds__(256) void k_karras(RebuildArgs a)
 {
+    __shared__ int red[4][12];
     const int n = (int)a.hdr->n;
-    const int lane = threadIdx.x & 63;
-    const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (c * kLeafChunk >= n) return;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if ((int64_t)blockIdx.x * kLeafChunk >= n) return;   // uniform per block
+    const uint32_t *k = a.skeys;
     Box12 x;
     box12_empty(x);
-    const int j1 = (int)min((int64_t)n, (c + 1) * kLeafChunk);
-    for (int j = (int)(c * kLeafChunk) + lane; j < j1; j += 64) box12_leaf(a, n, j, x);
+    if (i < n) {
+        const uint32_t key = k[i];
+        const uint32_t bx = compact3(key >> 2), by = compact3(key >> 1), bz = compact3(key);
+        a.sids[i] = bx + (uint32_t)a.vol.nb[0] * (by + (uint32_t)a.vol.nb[1] * bz);
+        const int node = (n - 1) + i;
+        const int b[3] = {(int)bx, (int)by, (int)bz};
+        const int nn[3] = {a.vol.nx, a.vol.ny, a.vol.nz};
+        int lo2[3], hi2[3];
+        for (int q = 0; q < 3; ++q) {
+            a.lb_lo[3 * node + q] = a.vol.B * b[q];
+            a.lb_hi[3 * node + q] = min(a.vol.B * b[q] + a.vol.B, nn[q]);
+            lo2[q] = 2 * a.lb_lo[3 * node + q];
+            hi2[q] = 2 * a.lb_hi[3 * node + q];
+        }
+        // the leaf's render box: its brick, or the brick's voxel-tight box
+        uint4 box;
+        if (a.tight) {
+            box = a.tbox[a.sids[i]];
+        } else {
+            uint32_t w[3];
+            pack_box(lo2, hi2, w);
+            box = make_uint4(w[0], w[1], w[2], 0u);
+        }
+        a.lb_leafbox[i] = box;
+        if (n == 1) a.lb_root[0] = box;
+        int l2[3], h2[3];
+        unpack_box_u(box.x, box.y, box.z, l2, h2);
+        for (int q = 0; q < 3; ++q) {
+            x.b[q] = a.lb_lo[3 * node + q];
+            x.b[3 + q] = a.lb_hi[3 * node + q];
+            x.r[q] = l2[q];
+            x.r[3 + q] = h2[q];
+        }
+    }
+    // the chunk's union: waves, then the block
     box12_wave(x);
-    if (lane < 12) a.lb_chunk[12 * c + lane] = lane < 6 ? x.b[lane] : x.r[lane - 6];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int val = 0;   // lane q < 12 holds face q (selects: no dynamic register index)
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        val = lane == q ? x.b[q] : val;
+        val = lane == 6 + q ? x.r[q] : val;
+    }
+    if (lane < 12) red[wave][lane] = val;
+    __syncthreads();
+    if (threadIdx.x < 12) {
+        const int q = threadIdx.x, qq = q % 6;
+        int v = red[0][q];
+        for (int w = 1; w < 4; ++w) v = qq < 3 ? min(v, red[w][q]) : max(v, red[w][q]);
+        a.lb_chunk[12 * (int64_t)blockIdx.x + q] = v;
+    }
+    if (i >= n - 1) return;
+    const int d = (delta(k, n, i, i + 1) - delta(k, n, i, i - 1)) > 0 ? 1 : -1;
+    const int dmin = delta(k, n, i, i - d);
+    int lmax = 2;
+    while (delta(k, n, i, i + lmax * d) > dmin) lmax <<= 1;
+    int l = 0;
+    for (int t = lmax >> 1; t >= 1; t >>= 1)
+        if (delta(k, n, i, i + (l + t) * d) > dmin) l += t;
+    const int j = i + l * d;
+    const int dnode = delta(k, n, i, j);
+    int s = 0;
+    for (int div = 2;; div <<= 1) {
+        const int t = (l + div - 1) / div;
+        if (delta(k, n, i, i + (s + t) * d) > dnode) s += t;
+        if (t == 1) break;
+    }
+    const int g = i + s * d + min(d, 0);
+    const int lo = min(i, j), hi = max(i, j);
+    const uint32_t left = (lo == g) ? (kLeaf | (uint32_t)g) : (uint32_t)g;
+    const uint32_t right = (hi == g + 1) ? (kLeaf | (uint32_t)(g + 1)) : (uint32_t)(g + 1);
+    a.lb_left[i] = left;
+    a.lb_right[i] = right;
+    const int hb = 31 - dnode;  // highest differing bit of the range
+    a.lb_axis[i] = 2 - hb % 3;
+    a.lb_parent[(left & kLeaf) ? (n - 1) + g : g] = (uint32_t)i;
+    a.lb_parent[(right & kLeaf) ? (n - 1) + g + 1 : g + 1] = (uint32_t)i;
+    a.lb_range[i] = make_int2(lo, hi);
 }
 
 __global__ __launch_bounds__(256) void k_lbvh_boxes(RebuildArgs a)
@@ -893,8 +914,6 @@ hipError_t launch_lbvh(const RebuildArgs &a, hipStream_t s)
 {
     const unsigned blocks = (unsigned)((a.nb + 255) / 256);
     hipLaunchKernelGGL(k_karras, dim3(blocks), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_lbvh_chunks, dim3((unsigned)((a.nb + 4 * kLeafChunk - 1) / (4 * kLeafChunk))), dim3(256), 0,
-                       s, a);
     hipLaunchKernelGGL(k_lbvh_boxes, dim3((unsigned)((a.nb + 3) / 4)), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_lbvh_height, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
