@@ -15,9 +15,9 @@
  *    voxels [B*b, min(B*b+B, n)) on each axis; its linear id is
  *    bx + nbx*(by + nby*bz) with nbx = ceil(nx/B) (likewise y, z).  At most 1024 bricks per
  *    axis (10 bits per axis of the 30-bit Morton code, Sec. 3.1), at most
- *    2^28 bricks in all, and 64*R*ceil(nx/8)*ceil(ny/8) < 2^32 (R = 9 for
- *    f32, else 8: the element stride of an 8-voxel z-slab of the renderer's
- *    blocked copy); beyond these limits calls return ESK_ELIMIT.
+ *    2^28 bricks in all, and at most 32767 voxels per axis (the renderer's
+ *    boxes are uint16 in half-voxel units); beyond these limits calls return
+ *    ESK_ELIMIT.
  *  - Transfer functions are N x RGBA float32, N in [2, 4096]; entry i sits at
  *    the normalised value i/(N-1).  Normalised value s(v): v/255 (u8),
  *    v/65535 (u16), clamp((v-lo)/(hi-lo), 0, 1) (f16, f32).

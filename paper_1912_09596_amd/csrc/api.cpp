@@ -179,11 +179,6 @@ esk_status check_shape(esk_ctx *c, int nx, int ny, int nz, int dtype, int brick,
         return fail(c, ESK_ELIMIT, "more than %d bricks on an axis (%d %d %d)", kMaxBricksPerAxis, nbx, nby, nbz);
     if ((int64_t)nbx * nby * nbz > kMaxBricks)
         return fail(c, ESK_ELIMIT, "more than %lld bricks", (long long)kMaxBricks);
-    // the renderer addresses a z-slab of 8^3 blocks with 32-bit element strides
-    const int64_t slab = (int64_t)64 * swz_row(elem_size(dtype)) * ((nx + kSwzEdge - 1) / kSwzEdge) *
-                         ((ny + kSwzEdge - 1) / kSwzEdge);
-    if (slab > (int64_t)0xffffffffLL)
-        return fail(c, ESK_ELIMIT, "an 8-voxel z-slab of %d x %d voxels exceeds 2^32 elements", nx, ny);
     return ESK_OK;
 }
 

@@ -62,17 +62,20 @@ Layout make_layout(int nx, int ny, int nz, int brick, int elem_bytes, int max_tf
 int elem_size(int dtype);
 
 // ---- launchers (each enqueues on `s`; returns hipSuccess or the launch error)
-// The renderer samples a copy of the volume stored in 8^3-voxel blocks
-// (one block contiguous: 64 rows of 8 voxels, x fastest, then y, then z;
-// blocks x-fastest), made at esk_set_volume: the 2x2x2 footprints of the 64
-// rays of a wave then fall into a few blocks instead of dozens of voxel rows.
-// FP32 rows hold a ninth element, the first voxel of the next block along x,
-// so both x neighbours of a sample come from one 8-byte load.
-constexpr int kSwzEdge = 8;
-__host__ __device__ constexpr int swz_row(int elem_bytes) { return elem_bytes == 4 ? 9 : 8; }
+// The renderer samples a copy of the volume stored in 8^3-voxel blocks, made
+// at esk_set_volume: the 2x2x2 footprints of the 64 rays of a wave then fall
+// into a few blocks instead of dozens of voxel rows.  A stored block holds
+// the 9^3 voxels from its corner (its own 8^3 and the first voxel of the next
+// block along each axis, edge voxels repeated past the volume), x fastest,
+// then y, then z, padded to 736 elements (a multiple of 16 bytes for every
+// element type); blocks x-fastest.  All 8 neighbours of a sample then lie in
+// one stored block at fixed offsets.
+constexpr int kSwzEdge = 8;     // voxels per block edge
+constexpr int kSwzSpan = 9;     // stored voxels per block edge
+constexpr int kSwzBlock = 736;  // stored elements per block (9^3 = 729, padded)
 inline int64_t swz_bytes(const int nq[3], int elem_bytes)
 {
-    return (int64_t)nq[0] * nq[1] * nq[2] * 64 * swz_row(elem_bytes) * elem_bytes;
+    return (int64_t)nq[0] * nq[1] * nq[2] * kSwzBlock * elem_bytes;
 }
 
 struct VolumeDesc {

@@ -249,65 +249,76 @@ hipError_t launch_typed(const VolumeDesc &v, void *minv, void *maxv, hipStream_t
 }
 
 // The blocked copy for the renderer, one workgroup per run of blocks along x
-// of one (block row, block slab): the 64 voxel rows of the run (plus
-// the apron voxel) are staged in LDS, then the blocks are written out as one
-// contiguous stretch with 16-byte stores, so every cache line of the copy is
-// written whole.  VEC: rows are read with 16-byte loads (nx a multiple of
-// the 16-byte element count and a 16-byte aligned volume), else one element
-// per load.  Padding voxels (past the volume) are zero and never sampled
-// (the sampler clamps indices to the volume).
-// blocks per run: every staged voxel row is 512 bytes long (measured against
-// 128-, 256-byte rows: 5-20 % faster, the most for 2-byte types at 2048^3)
-template <typename T> constexpr int swz_run() { return 512 / (8 * (int)sizeof(T)); }
+// of one (block row, block slab): the 81 voxel rows the run's stored blocks
+// draw on (9 in y by 9 in z, edge rows repeated past the volume) are staged
+// in LDS, then the run's blocks are written out as one contiguous stretch of
+// 16-byte stores, so every cache line of the copy is written whole.  VEC:
+// rows are read with 16-byte loads (nx a multiple of the 16-byte element
+// count and a 16-byte aligned volume), else one element per load.
+// Runs are 256 bytes of voxel row (measured against 128- and 512-byte runs:
+// the 81 staged rows of a 512-byte run hold 43 KB of LDS and 3 workgroups
+// per CU; 7-30 % slower).
+template <typename T> constexpr int swz_run() { return 256 / (8 * (int)sizeof(T)); }
 
 template <typename T, bool VEC>
 __global__ __launch_bounds__(256) void k_swizzle(const T *__restrict__ vol, int nx, int ny, int nz, int nqx,
                                                  int nqy, T *__restrict__ swz)
 {
     constexpr int kSwzRun = swz_run<T>();
-    constexpr int ROW = swz_row((int)sizeof(T));
     constexpr int V = 16 / (int)sizeof(T);                       // elements per 16-byte access
-    constexpr int W = (kSwzRun * 8 + 1 + V - 1) / V * V;         // staged row: run voxels, apron, padding
-    __shared__ __align__(16) T tile[64 * W];
+    constexpr int X = kSwzRun * kSwzEdge + 1;                    // voxels of a staged row
+    constexpr int W = (X + V - 1) / V * V;                       // staged row with padding
+    constexpr int ROWS = kSwzSpan * kSwzSpan;
+    __shared__ __align__(16) T tile[ROWS * W];
     const int qx0 = blockIdx.x * kSwzRun, qy = blockIdx.y, qz = blockIdx.z;
     const int nblk = min(kSwzRun, nqx - qx0);
-    const int x0 = qx0 * 8;
+    const int x0 = qx0 * kSwzEdge;
+    // staged row r: voxel row y = min(8 qy + r % 9, ny - 1), z = min(8 qz + r / 9, nz - 1)
+    auto row_ptr = [&](int r) {
+        const int y = min(qy * kSwzEdge + r % kSwzSpan, ny - 1), z = min(qz * kSwzEdge + r / kSwzSpan, nz - 1);
+        return vol + ((size_t)z * ny + y) * (size_t)nx;
+    };
     if (VEC) {
-        constexpr int CH = kSwzRun * 8 / V;   // 16-byte chunks per row
-        for (int i = threadIdx.x; i < 64 * CH; i += 256) {
+        constexpr int CH = kSwzRun * kSwzEdge / V;   // 16-byte chunks per row
+        for (int i = threadIdx.x; i < ROWS * CH; i += 256) {
             const int r = i / CH, c = i - r * CH;
-            const int x = x0 + c * V, y = qy * 8 + (r & 7), z = qz * 8 + (r >> 3);
-            uint4 w = make_uint4(0u, 0u, 0u, 0u);
-            if (x < nx && y < ny && z < nz)
-                w = *reinterpret_cast<const uint4 *>(vol + ((size_t)z * ny + y) * (size_t)nx + x);
-            *reinterpret_cast<uint4 *>(&tile[r * W + c * V]) = w;
+            const int x = x0 + c * V;
+            const T *row = row_ptr(r);
+            if (x < nx) {
+                *reinterpret_cast<uint4 *>(&tile[r * W + c * V]) = *reinterpret_cast<const uint4 *>(row + x);
+            } else {
+                const T e = row[nx - 1];   // past the volume: the edge voxel
+                for (int k = 0; k < V; ++k) tile[r * W + c * V + k] = e;
+            }
         }
-        if (threadIdx.x < 64) {
+        if (threadIdx.x < ROWS) {
             const int r = threadIdx.x;
-            const int x = x0 + kSwzRun * 8, y = qy * 8 + (r & 7), z = qz * 8 + (r >> 3);
-            tile[r * W + kSwzRun * 8] = (x < nx && y < ny && z < nz) ? vol[((size_t)z * ny + y) * (size_t)nx + x] : (T)0;
+            tile[r * W + X - 1] = row_ptr(r)[min(x0 + X - 1, nx - 1)];
         }
     } else {
-        for (int i = threadIdx.x; i < 64 * (kSwzRun * 8 + 1); i += 256) {
-            const int r = i / (kSwzRun * 8 + 1), xi = i - r * (kSwzRun * 8 + 1);
-            const int x = x0 + xi, y = qy * 8 + (r & 7), z = qz * 8 + (r >> 3);
-            tile[r * W + xi] = (x < nx && y < ny && z < nz) ? vol[((size_t)z * ny + y) * (size_t)nx + x] : (T)0;
+        for (int i = threadIdx.x; i < ROWS * X; i += 256) {
+            const int r = i / X, c = i - r * X;
+            tile[r * W + c] = row_ptr(r)[min(x0 + c, nx - 1)];
         }
     }
     __syncthreads();
-    // the run's blocks are contiguous; 64 * ROW elements per block is a
-    // multiple of V for every element type, so the stretch splits into
-    // whole 16-byte stores
-    T *out = swz + (((size_t)qz * nqy + qy) * nqx + qx0) * (64 * ROW);
-    const int total = nblk * 64 * ROW;
+    // the run's blocks are contiguous and kSwzBlock is a multiple of V, so the
+    // stretch splits into whole 16-byte stores
+    T *out = swz + (((size_t)qz * nqy + qy) * nqx + qx0) * kSwzBlock;
+    const int total = nblk * kSwzBlock;
     for (int i = threadIdx.x * V; i < total; i += 256 * V) {
+        // position of the chunk's first element, then stepped element by
+        // element (x, then the 9x9 rows; past the 729th: padding)
+        const int b = i / kSwzBlock, rem = i - b * kSwzBlock;
+        int row = rem / kSwzSpan, lx = rem - row * kSwzSpan;   // row = lz * 9 + ly
+        const int col0 = b * kSwzEdge;
         T v[V];
 #pragma unroll
         for (int e = 0; e < V; ++e) {
-            const int j = i + e;
-            const int b = j / (64 * ROW), rem = j - b * (64 * ROW);
-            const int r = rem / ROW, xi = rem - r * ROW;
-            v[e] = tile[r * W + b * 8 + xi];
+            v[e] = row < kSwzSpan * kSwzSpan ? tile[row * W + col0 + lx] : (T)0;
+            const bool wrap = lx == kSwzSpan - 1;
+            lx = wrap ? 0 : lx + 1;
+            row = wrap ? row + 1 : row;
         }
         uint4 w;
         __builtin_memcpy(&w, v, 16);
@@ -318,7 +329,7 @@ __global__ __launch_bounds__(256) void k_swizzle(const T *__restrict__ vol, int 
 template <typename T>
 hipError_t launch_swz_typed(const VolumeDesc &v, void *swz, hipStream_t s)
 {
-    static_assert((64 * swz_row((int)sizeof(T))) % (16 / (int)sizeof(T)) == 0, "blocks split into 16-byte stores");
+    static_assert(kSwzBlock % (16 / (int)sizeof(T)) == 0, "blocks split into 16-byte stores");
     constexpr int kSwzRun = swz_run<T>();
     const dim3 grid((unsigned)((v.nq[0] + kSwzRun - 1) / kSwzRun), (unsigned)v.nq[1], (unsigned)v.nq[2]);
     const bool vec = (v.nx % (16 / (int)sizeof(T)) == 0) && ((reinterpret_cast<uintptr_t>(v.vox) & 15) == 0);

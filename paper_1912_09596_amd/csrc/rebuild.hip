@@ -239,18 +239,18 @@ template <typename T> hipError_t launch_tight_typed(const RebuildArgs &a, hipStr
 // are folded into a value stored only if impossible, so the loads stay.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_warm(RebuildArgs a, int row_bytes, uint32_t *sink, int never)
+__global__ __launch_bounds__(256) void k_warm(RebuildArgs a, int block_bytes, uint32_t *sink, int never)
 {
     const int n = (int)a.hdr->n;
     const int B = a.vol.B;
     const uint32_t nbx = (uint32_t)a.vol.nb[0], nby = (uint32_t)a.vol.nb[1];
     const int nq0 = a.vol.nq[0], nq1 = a.vol.nq[1], nq2 = a.vol.nq[2];
-    const int blk16 = 64 * row_bytes / 16;   // 16-byte words per block
+    const int blk16 = block_bytes / 16;   // 16-byte words per stored block
     const uint4 *swz = static_cast<const uint4 *>(a.vol.swz);
     // only when the blocks fit the last-level cache (256 MB; budget 192 MB):
     // beyond that the warm-up would evict its own lines before the render
     const int64_t per_brick = B >= 8 ? (int64_t)(B >> 3) * (B >> 3) * (B >> 3) : 1;
-    if ((int64_t)n * per_brick * 64 * row_bytes > ((int64_t)192 << 20)) return;
+    if ((int64_t)n * per_brick * block_bytes > ((int64_t)192 << 20)) return;
     uint32_t acc = 0;
     for (int i = blockIdx.x; i < n; i += gridDim.x) {
         const uint32_t id = a.ids[i];
@@ -859,9 +859,8 @@ hipError_t launch_tight(const RebuildArgs &a, hipStream_t s)
 
 hipError_t launch_warm(const RebuildArgs &a, int elem_bytes, hipStream_t s)
 {
-    const int row_bytes = swz_row(elem_bytes) * elem_bytes;
-    hipLaunchKernelGGL(k_warm, dim3((unsigned)std::min<int64_t>(a.nb, 2048)), dim3(256), 0, s, a, row_bytes,
-                       a.blkcnt, -1);
+    hipLaunchKernelGGL(k_warm, dim3((unsigned)std::min<int64_t>(a.nb, 2048)), dim3(256), 0, s, a,
+                       kSwzBlock * elem_bytes, a.blkcnt, -1);
     return hipGetLastError();
 }
 

@@ -145,14 +145,16 @@ struct Accum {
 struct Vol {
     int n[3];
     float fn[3];
-    uint32_t sy;       // elements between block rows of the blocked copy (a slab is nq1 rows)
-    uint32_t nq1;      // blocks along y
+    float fm[3];       // n - 1: the largest continuous voxel index
+    uint32_t nq0, nq1; // blocks along x and y
 };
 
 // cell-centred trilinear interpolation (clamp to edge) from the blocked copy:
-// with R elements per block row (R = 8, or 9 for FP32 rows carrying the next
-// block's first voxel), element (x, y, z) sits at
-// ((z>>3)*nq1 + (y>>3))*sy + (x>>3)*64R + ((z&7)*8 + (y&7))*R + (x&7), sy = 64R*nq0.
+// voxel (x, y, z) of stored block ((z>>3)*nq1 + (y>>3))*nq0 + (x>>3) sits at
+// ((z&7)*9 + (y&7))*9 + (x&7), and its +1 neighbours at +1, +9, +81.  The
+// continuous index u = p - 1/2 is clamped to [0, n-1] per axis: there the
+// weight of the far neighbour is 0, so the result equals clamping both
+// neighbour indices to the volume, and any point gives valid addresses.
 // Split in two so a group of samples can issue all its gathers before the
 // first interpolation: gather() loads the 8 corners and the weights, lerp3()
 // combines them.
@@ -164,63 +166,49 @@ struct Corners {
 template <typename T, typename IDX>
 __device__ inline void gather(const T *__restrict__ vol, const Vol &v, const float p[3], Corners &g)
 {
-    constexpr int R = swz_row((int)sizeof(T));
-    const float ux = p[0] - 0.5f, uy = p[1] - 0.5f, uz = p[2] - 0.5f;
+    const float ux = fminf(fmaxf(p[0] - 0.5f, 0.0f), v.fm[0]);
+    const float uy = fminf(fmaxf(p[1] - 0.5f, 0.0f), v.fm[1]);
+    const float uz = fminf(fmaxf(p[2] - 0.5f, 0.0f), v.fm[2]);
     const float fx = floorf(ux), fy = floorf(uy), fz = floorf(uz);
     g.w[0] = ux - fx;
     g.w[1] = uy - fy;
     g.w[2] = uz - fz;
-    const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
-    const int x0 = min(max(ix, 0), v.n[0] - 1), x1 = min(max(ix + 1, 0), v.n[0] - 1);
-    const int y0 = min(max(iy, 0), v.n[1] - 1), y1 = min(max(iy + 1, 0), v.n[1] - 1);
-    const int z0 = min(max(iz, 0), v.n[2] - 1), z1 = min(max(iz + 1, 0), v.n[2] - 1);
-    // IDX = uint32_t: the copy is < 4 GiB, so byte offsets are 32-bit and every
-    // load is a scalar base plus one 32-bit vector offset
-    constexpr IDX E = (IDX)sizeof(T);
-    // block strides: (y>>3)*sy and (z>>3)*sz = ((z>>3)*nq1)*sy.  With 32-bit
-    // offsets every factor is below 2^24 (sy = 64R*nq0 with nq0 <= 4096,
-    // z>>3 and nq1 <= 4096), so the full-rate 24-bit multiply is exact in
-    // the low 32 bits; 64-bit offsets multiply in 64 bits
-    // (the masks only state known ranges: block indices and nq1 are below
-    // 4096 -- at most 32768 voxels per axis -- and sy <= 576 * 4096 < 2^22)
-    const uint32_t sy = v.sy & 0x3fffffu, nq1 = v.nq1 & 0xfffu;
-    auto mul = [&](uint32_t a, uint32_t b) -> IDX {
-        if constexpr (sizeof(IDX) == 4) return (IDX)__umul24(a, b);
-        else return (IDX)a * (IDX)b;
-    };
-    auto q = [](int c) { return (uint32_t)(c >> 3) & 0xfffu; };
-    auto ox = [&](int x) { return ((IDX)__umul24(q(x), 64 * R) + (IDX)(x & 7)) * E; };
-    auto oy = [&](int y) { return (mul(q(y), sy) + (IDX)(y & 7) * R) * E; };
-    auto oz = [&](int z) { return (mul(__umul24(q(z), nq1), sy) + (IDX)(z & 7) * (8 * R)) * E; };
-    const IDX r00 = oz(z0) + oy(y0), r10 = oz(z0) + oy(y1);
-    const IDX r01 = oz(z1) + oy(y0), r11 = oz(z1) + oy(y1);
-    const char *__restrict__ base = reinterpret_cast<const char *>(vol);
-    if constexpr (R == 9) {
-        // x0 and x0 + 1 are adjacent in every row: one 8-byte (dword-aligned)
-        // load per row; a clamped x1 (== x0) takes the first value twice
-        const IDX bx = ox(x0);
-        const bool same = x1 == x0;
-        auto ld2 = [&](IDX off, float &a, float &b) {
+    const uint32_t ix = (uint32_t)(int)fx, iy = (uint32_t)(int)fy, iz = (uint32_t)(int)fz;
+    // indices are below 32768, block counts below 4096 (the masks state it),
+    // so the 24-bit multiplies are exact; IDX = uint32_t: the copy is
+    // < 4 GiB, so byte offsets are 32-bit and every load is a scalar base
+    // plus one 32-bit vector offset
+    constexpr uint32_t E = (uint32_t)sizeof(T);
+    const uint32_t row = __umul24((iz >> 3) & 0xfffu, v.nq1 & 0xfffu) + ((iy >> 3) & 0xfffu);
+    const uint32_t local = __umul24(__umul24(iz & 7u, 9u) + (iy & 7u), 9u) + (ix & 7u);
+    IDX off;
+    if constexpr (sizeof(IDX) == 4)
+        off = __umul24(__umul24(row, v.nq0 & 0xfffu) + ((ix >> 3) & 0xfffu), (uint32_t)kSwzBlock * E) + local * E;
+    else
+        off = ((IDX)row * v.nq0 + ((ix >> 3) & 0xfffu)) * ((IDX)kSwzBlock * E) + (IDX)(local * E);
+    const char *__restrict__ base = reinterpret_cast<const char *>(vol) + off;
+    if constexpr (sizeof(T) == 4) {
+        // x and x + 1 are adjacent: one 8-byte (dword-aligned) load per row
+        auto ld2 = [&](uint32_t o, float &a, float &b) {
             float q[2];
-            __builtin_memcpy(q, base + off, 8);
+            __builtin_memcpy(q, base + o, 8);
             a = q[0];
-            b = same ? q[0] : q[1];
+            b = q[1];
         };
-        ld2(r00 + bx, g.c[0], g.c[1]);
-        ld2(r10 + bx, g.c[2], g.c[3]);
-        ld2(r01 + bx, g.c[4], g.c[5]);
-        ld2(r11 + bx, g.c[6], g.c[7]);
+        ld2(0, g.c[0], g.c[1]);
+        ld2(9 * E, g.c[2], g.c[3]);
+        ld2(81 * E, g.c[4], g.c[5]);
+        ld2(90 * E, g.c[6], g.c[7]);
     } else {
-        const IDX bx0 = ox(x0), bx1 = ox(x1);
-        auto ld = [&](IDX off) { return (float)*reinterpret_cast<const T *>(base + off); };
-        g.c[0] = ld(r00 + bx0);
-        g.c[1] = ld(r00 + bx1);
-        g.c[2] = ld(r10 + bx0);
-        g.c[3] = ld(r10 + bx1);
-        g.c[4] = ld(r01 + bx0);
-        g.c[5] = ld(r01 + bx1);
-        g.c[6] = ld(r11 + bx0);
-        g.c[7] = ld(r11 + bx1);
+        auto ld = [&](uint32_t o) { return (float)*reinterpret_cast<const T *>(base + o); };
+        g.c[0] = ld(0);
+        g.c[1] = ld(E);
+        g.c[2] = ld(9 * E);
+        g.c[3] = ld(10 * E);
+        g.c[4] = ld(81 * E);
+        g.c[5] = ld(82 * E);
+        g.c[6] = ld(90 * E);
+        g.c[7] = ld(91 * E);
     }
 }
 
@@ -595,9 +583,11 @@ __device__ inline void render_tile(const RenderArgs &ra, int tbx, int tby)
     const T *__restrict__ vol = static_cast<const T *>(ra.vol.swz);
     Vol v;
     v.n[0] = ra.vol.nx; v.n[1] = ra.vol.ny; v.n[2] = ra.vol.nz;
-    for (int a = 0; a < 3; ++a) v.fn[a] = (float)v.n[a];
-    constexpr uint32_t R = (uint32_t)swz_row((int)sizeof(T));
-    v.sy = 64u * R * (uint32_t)ra.vol.nq[0];
+    for (int a = 0; a < 3; ++a) {
+        v.fn[a] = (float)v.n[a];
+        v.fm[a] = (float)(v.n[a] - 1);
+    }
+    v.nq0 = (uint32_t)ra.vol.nq[0];
     v.nq1 = (uint32_t)ra.vol.nq[1];
     Shade s;
     s.tf = tf_lds ? lds : reinterpret_cast<const float4 *>(ra.tf);

@@ -47,9 +47,9 @@ def test_workspace_bytes_and_limits():
     # render boxes are uint16 in half-voxel units: at most 32767 voxels per axis
     assert L.esk_workspace_bytes(32767, 8, 8, esk.U8, 32, 256, ctypes.byref(out)) == esk.OK
     assert L.esk_workspace_bytes(32768, 8, 8, esk.U8, 32, 256, ctypes.byref(out)) == esk.ELIMIT
-    # the renderer's blocked copy needs 64*R*ceil(nx/8)*ceil(ny/8) < 2^32 (R = 9 for f32, else 8)
+    # the renderer's blocked copy is addressed with 64-bit offsets beyond 4 GiB: no slab limit
     assert L.esk_workspace_bytes(22528, 22528, 32, esk.U8, 32, 256, ctypes.byref(out)) == esk.OK
-    assert L.esk_workspace_bytes(22528, 22528, 32, esk.F32, 32, 256, ctypes.byref(out)) == esk.ELIMIT
+    assert L.esk_workspace_bytes(22528, 22528, 32, esk.F32, 32, 256, ctypes.byref(out)) == esk.OK
 
 
 class _VCtx:
