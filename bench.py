@@ -731,10 +731,10 @@ def main():
     copy_gbs = 2 * src.numel() * 4 / (statistics.median(cp) * 1e-3) / 1e9
     # set_volume's algorithmic bytes: the min/max pass reads the volume and
     # writes two values per brick; the blocked copy reads it and writes the
-    # blocked layout (8^3 blocks, rows of 9 values with the x apron)
+    # blocked layout (per 8^3 block its 9^3 voxels, padded to 736 values)
     nvox = DIMS[0] * DIMS[1] * DIMS[2]
     nq = [(d + 7) // 8 for d in DIMS]
-    sv_bytes = nvox * 4 + 2 * st["n_bricks"] * 4 + nvox * 4 + nq[0] * nq[1] * nq[2] * 64 * 9 * 4
+    sv_bytes = nvox * 4 + 2 * st["n_bricks"] * 4 + nvox * 4 + nq[0] * nq[1] * nq[2] * 736 * 4
     sv_gbs = sv_bytes / (statistics.median(sv) * 1e-3) / 1e9
 
     mean_ms = {a: statistics.mean(render_ms[a]) for a in ACCELS}
