@@ -48,6 +48,7 @@ Layout make_layout(int nx, int ny, int nz, int brick, int elem_bytes, int max_tf
     const size_t n4 = (size_t)nb * 4;
     L.header = take(sizeof(DevHeader));
     L.swz = take((size_t)swz_bytes(nq, elem_bytes));
+    L.blksum = take((size_t)nq[0] * nq[1] * nq[2] * 16 * sizeof(float));
     L.minv = take((size_t)nb * elem_bytes);
     L.maxv = take((size_t)nb * elem_bytes);
     L.tf = take((size_t)max_tf * 16);
@@ -368,8 +369,18 @@ esk_status esk_set_volume(esk_ctx *c, const void *d_vox, int dtype, int nx, int 
     c->vol.nq[0] = (nx + kSwzEdge - 1) / kSwzEdge;
     c->vol.nq[1] = (ny + kSwzEdge - 1) / kSwzEdge;
     c->vol.nq[2] = (nz + kSwzEdge - 1) / kSwzEdge;
-    if (e == hipSuccess) e = launch_minmax(c->vol, c->ws + L.minv, c->ws + L.maxv, c->stream);
-    if (e == hipSuccess) e = launch_swizzle(c->vol, c->ws + L.swz, c->stream);
+    if (brick >= kSwzEdge && elem_size(dtype) == 4) {
+        // one pass over the volume: the blocked copy also summarises each
+        // stored block, and the bricks' min/max are combined from those
+        // (FP32 only: for 1- and 2-byte voxels the summaries cost more than
+        // the separate min/max pass, measured)
+        float *blksum = at<float>(c, L.blksum);
+        if (e == hipSuccess) e = launch_swizzle(c->vol, c->ws + L.swz, blksum, c->stream);
+        if (e == hipSuccess) e = launch_minmax_from_blocks(c->vol, blksum, c->ws + L.minv, c->ws + L.maxv, c->stream);
+    } else {
+        if (e == hipSuccess) e = launch_minmax(c->vol, c->ws + L.minv, c->ws + L.maxv, c->stream);
+        if (e == hipSuccess) e = launch_swizzle(c->vol, c->ws + L.swz, nullptr, c->stream);
+    }
     if (e != hipSuccess) return hip_check(c, e, "set_volume launch");
     c->has_volume = true;
     return ESK_OK;

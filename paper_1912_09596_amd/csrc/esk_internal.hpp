@@ -49,7 +49,7 @@ struct Layout {
     int64_t nb;            // bricks
     int64_t nblk;          // classification blocks
     int64_t nsortblk;      // multi-block sort blocks
-    size_t header, swz, minv, maxv, tf, tfP, flags, grid, blkcnt;
+    size_t header, swz, blksum, minv, maxv, tf, tfP, flags, grid, blkcnt;
     size_t ids, keys, skeys, tmpkeys, sids, hist;
     size_t tbox;           // voxel-tight box per brick (half-voxel units, packed)
     size_t lb_left, lb_right, lb_axis, lb_parent, lb_lo, lb_hi, lb_range, lb_rnode, lb_leafbox, lb_root, lb_chunk;
@@ -86,7 +86,11 @@ struct VolumeDesc {
 };
 
 hipError_t launch_minmax(const VolumeDesc &v, void *minv, void *maxv, hipStream_t s);
-hipError_t launch_swizzle(const VolumeDesc &v, void *swz, hipStream_t s);
+// blksum: null, or 16 floats per stored block receiving its min/max summaries
+// (for launch_minmax_from_blocks; bricks of 8 voxels or more)
+hipError_t launch_swizzle(const VolumeDesc &v, void *swz, float *blksum, hipStream_t s);
+hipError_t launch_minmax_from_blocks(const VolumeDesc &v, const float *blksum, void *minv, void *maxv,
+                                     hipStream_t s);
 
 struct RebuildArgs {
     VolumeDesc vol;

@@ -260,9 +260,16 @@ hipError_t launch_typed(const VolumeDesc &v, void *minv, void *maxv, hipStream_t
 // per CU; 7-30 % slower).
 template <typename T> constexpr int swz_run() { return 256 / (8 * (int)sizeof(T)); }
 
-template <typename T, bool VEC>
+// Min/max summaries of a stored block (its 9^3 voxels, index l in 0..8 per
+// axis), 8 minima then 8 maxima, summary m restricted to the layer l = 7 of
+// every axis in m (bit 0: x, bit 1: y, bit 2: z).  The apron range of brick b
+// along an axis, [bB - 1, bB + B] clamped to the volume, is exactly the full
+// extent of the stored blocks bB/8 .. (b+1)B/8 - 1 plus the layer 7 of block
+// bB/8 - 1 (B >= 8), so a brick's min/max combines these summaries (and the
+// edge voxels repeated past the volume change neither).
+template <typename T, bool VEC, bool SUM>
 __global__ __launch_bounds__(256) void k_swizzle(const T *__restrict__ vol, int nx, int ny, int nz, int nqx,
-                                                 int nqy, T *__restrict__ swz)
+                                                 int nqy, T *__restrict__ swz, float *__restrict__ blksum)
 {
     constexpr int kSwzRun = swz_run<T>();
     constexpr int V = 16 / (int)sizeof(T);                       // elements per 16-byte access
@@ -302,6 +309,65 @@ __global__ __launch_bounds__(256) void k_swizzle(const T *__restrict__ vol, int 
         }
     }
     __syncthreads();
+    if constexpr (SUM) {
+        // each (block, row (lz, ly)): minimum/maximum over lx and the voxel
+        // at lx = 7; then per block the summaries over all 81 rows, the 9
+        // rows with ly = 7 or lz = 7, and the row with both
+        constexpr int R81 = kSwzSpan * kSwzSpan;
+        __shared__ float rmin[kSwzRun * R81], rmax[kSwzRun * R81], r7[kSwzRun * R81];
+        for (int pr = threadIdx.x; pr < nblk * R81; pr += 256) {
+            const int bb = pr / R81, r = pr - bb * R81;
+            const T *row = &tile[r * W + bb * kSwzEdge];
+            float rn = (float)row[0], rx = rn;
+#pragma unroll
+            for (int lx = 1; lx < kSwzSpan; ++lx) {
+                const float q = (float)row[lx];
+                rn = fminf(rn, q);
+                rx = fmaxf(rx, q);
+            }
+            rmin[pr] = rn;
+            rmax[pr] = rx;
+            r7[pr] = (float)row[7];
+        }
+        __syncthreads();
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        for (int b = wave; b < nblk; b += 4) {
+            const int o = b * R81;
+            // all rows: lanes take rows lane and lane + 64
+            float a0 = rmin[o + lane], a1 = rmax[o + lane], a2 = r7[o + lane], a3 = a2;
+            if (lane + 64 < R81) {
+                a0 = fminf(a0, rmin[o + lane + 64]);
+                a1 = fmaxf(a1, rmax[o + lane + 64]);
+                a2 = fminf(a2, r7[o + lane + 64]);
+                a3 = fmaxf(a3, r7[o + lane + 64]);
+            }
+            for (int d = 32; d >= 1; d >>= 1) {
+                a0 = fminf(a0, __shfl_xor(a0, d, 64));
+                a1 = fmaxf(a1, __shfl_xor(a1, d, 64));
+                a2 = fminf(a2, __shfl_xor(a2, d, 64));
+                a3 = fmaxf(a3, __shfl_xor(a3, d, 64));
+            }
+            // lanes 0..15 produce value i of the 16 (minima 0..7, maxima 8..15)
+            const int m = lane & 7;
+            const bool isMax = lane >= 8;
+            float val;
+            if (m == 0) val = isMax ? a1 : a0;
+            else if (m == 1) val = isMax ? a3 : a2;
+            else {
+                // layers: m = 2, 3 (ly = 7) and 4, 5 (lz = 7) over 9 rows; 6, 7 one row
+                const bool x7 = (m & 1) != 0;
+                const float *src = x7 ? r7 : (isMax ? rmax : rmin);
+                val = isMax ? -__builtin_inff() : __builtin_inff();
+                const int cnt = m >= 6 ? 1 : kSwzSpan;
+                for (int k = 0; k < cnt; ++k) {
+                    const int r = m >= 6 ? 7 * kSwzSpan + 7 : (m < 4 ? k * kSwzSpan + 7 : 7 * kSwzSpan + k);
+                    const float q = src[o + r];
+                    val = isMax ? fmaxf(val, q) : fminf(val, q);
+                }
+            }
+            if (lane < 16) blksum[((((size_t)qz * nqy + qy) * nqx + qx0 + b) << 4) + lane] = val;
+        }
+    }
     // the run's blocks are contiguous and kSwzBlock is a multiple of V, so the
     // stretch splits into whole 16-byte stores
     T *out = swz + (((size_t)qz * nqy + qy) * nqx + qx0) * kSwzBlock;
@@ -327,30 +393,96 @@ __global__ __launch_bounds__(256) void k_swizzle(const T *__restrict__ vol, int 
 }
 
 template <typename T>
-hipError_t launch_swz_typed(const VolumeDesc &v, void *swz, hipStream_t s)
+hipError_t launch_swz_typed(const VolumeDesc &v, void *swz, float *blksum, hipStream_t s)
 {
     static_assert(kSwzBlock % (16 / (int)sizeof(T)) == 0, "blocks split into 16-byte stores");
     constexpr int kSwzRun = swz_run<T>();
     const dim3 grid((unsigned)((v.nq[0] + kSwzRun - 1) / kSwzRun), (unsigned)v.nq[1], (unsigned)v.nq[2]);
     const bool vec = (v.nx % (16 / (int)sizeof(T)) == 0) && ((reinterpret_cast<uintptr_t>(v.vox) & 15) == 0);
-    if (vec)
-        hipLaunchKernelGGL((k_swizzle<T, true>), grid, dim3(256), 0, s, static_cast<const T *>(v.vox), v.nx, v.ny,
-                           v.nz, v.nq[0], v.nq[1], static_cast<T *>(swz));
+    const T *vox = static_cast<const T *>(v.vox);
+    T *out = static_cast<T *>(swz);
+    if (vec && blksum)
+        hipLaunchKernelGGL((k_swizzle<T, true, true>), grid, dim3(256), 0, s, vox, v.nx, v.ny, v.nz, v.nq[0], v.nq[1],
+                           out, blksum);
+    else if (vec)
+        hipLaunchKernelGGL((k_swizzle<T, true, false>), grid, dim3(256), 0, s, vox, v.nx, v.ny, v.nz, v.nq[0],
+                           v.nq[1], out, blksum);
+    else if (blksum)
+        hipLaunchKernelGGL((k_swizzle<T, false, true>), grid, dim3(256), 0, s, vox, v.nx, v.ny, v.nz, v.nq[0],
+                           v.nq[1], out, blksum);
     else
-        hipLaunchKernelGGL((k_swizzle<T, false>), grid, dim3(256), 0, s, static_cast<const T *>(v.vox), v.nx, v.ny,
-                           v.nz, v.nq[0], v.nq[1], static_cast<T *>(swz));
+        hipLaunchKernelGGL((k_swizzle<T, false, false>), grid, dim3(256), 0, s, vox, v.nx, v.ny, v.nz, v.nq[0],
+                           v.nq[1], out, blksum);
+    return hipGetLastError();
+}
+
+// Brick min/max from the stored blocks' summaries (one thread per brick;
+// B >= 8): every combination of "layer 7 of the block below" and "the core
+// blocks" per axis (the lower layer only where the brick is not first).
+template <typename T>
+__global__ __launch_bounds__(256) void k_minmax_blocks(const float *__restrict__ blksum, int B, int nbx, int nby,
+                                                       int nbz, int nq0, int nq1, int nq2, T *__restrict__ outmin,
+                                                       T *__restrict__ outmax)
+{
+    const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (id >= (int64_t)nbx * nby * nbz) return;
+    const int b[3] = {(int)(id % nbx), (int)((id / nbx) % nby), (int)(id / ((int64_t)nbx * nby))};
+    const int nq[3] = {nq0, nq1, nq2};
+    const int per = B / kSwzEdge;
+    int c0[3], c1[3];
+    for (int a = 0; a < 3; ++a) {
+        c0[a] = b[a] * per;
+        c1[a] = min(c0[a] + per, nq[a]);
+    }
+    float mn = __builtin_inff(), mx = -__builtin_inff();
+    for (int m = 0; m < 8; ++m) {
+        if (((m & 1) && b[0] == 0) || ((m & 2) && b[1] == 0) || ((m & 4) && b[2] == 0)) continue;
+        const int x0 = (m & 1) ? c0[0] - 1 : c0[0], x1 = (m & 1) ? c0[0] : c1[0];
+        const int y0 = (m & 2) ? c0[1] - 1 : c0[1], y1 = (m & 2) ? c0[1] : c1[1];
+        const int z0 = (m & 4) ? c0[2] - 1 : c0[2], z1 = (m & 4) ? c0[2] : c1[2];
+        for (int qz = z0; qz < z1; ++qz)
+            for (int qy = y0; qy < y1; ++qy)
+                for (int qx = x0; qx < x1; ++qx) {
+                    const float *sm = blksum + ((((size_t)qz * nq1 + qy) * nq0 + qx) << 4);
+                    mn = fminf(mn, sm[m]);
+                    mx = fmaxf(mx, sm[8 + m]);
+                }
+    }
+    outmin[id] = from_float<T>(mn);
+    outmax[id] = from_float<T>(mx);
+}
+
+template <typename T>
+hipError_t launch_mmb_typed(const VolumeDesc &v, const float *blksum, void *minv, void *maxv, hipStream_t s)
+{
+    const int64_t nb = (int64_t)v.nb[0] * v.nb[1] * v.nb[2];
+    hipLaunchKernelGGL((k_minmax_blocks<T>), dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, blksum, v.B,
+                       v.nb[0], v.nb[1], v.nb[2], v.nq[0], v.nq[1], v.nq[2], static_cast<T *>(minv),
+                       static_cast<T *>(maxv));
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_swizzle(const VolumeDesc &v, void *swz, hipStream_t s)
+hipError_t launch_swizzle(const VolumeDesc &v, void *swz, float *blksum, hipStream_t s)
 {
     switch (v.dtype) {
-    case ESK_U8: return launch_swz_typed<uint8_t>(v, swz, s);
-    case ESK_U16: return launch_swz_typed<uint16_t>(v, swz, s);
-    case ESK_F16: return launch_swz_typed<_Float16>(v, swz, s);
-    case ESK_F32: return launch_swz_typed<float>(v, swz, s);
+    case ESK_U8: return launch_swz_typed<uint8_t>(v, swz, blksum, s);
+    case ESK_U16: return launch_swz_typed<uint16_t>(v, swz, blksum, s);
+    case ESK_F16: return launch_swz_typed<_Float16>(v, swz, blksum, s);
+    case ESK_F32: return launch_swz_typed<float>(v, swz, blksum, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_minmax_from_blocks(const VolumeDesc &v, const float *blksum, void *minv, void *maxv, hipStream_t s)
+{
+    if (v.B < kSwzEdge) return hipErrorInvalidValue;
+    switch (v.dtype) {
+    case ESK_U8: return launch_mmb_typed<uint8_t>(v, blksum, minv, maxv, s);
+    case ESK_U16: return launch_mmb_typed<uint16_t>(v, blksum, minv, maxv, s);
+    case ESK_F16: return launch_mmb_typed<_Float16>(v, blksum, minv, maxv, s);
+    case ESK_F32: return launch_mmb_typed<float>(v, blksum, minv, maxv, s);
     }
     return hipErrorInvalidValue;
 }
