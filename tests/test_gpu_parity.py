@@ -135,6 +135,10 @@ def test_c1_workload_full_parity():
     ((61, 40, 47), 8, np.float16, 2),
     ((70, 23, 38), 4, np.uint16, 3),
     ((100, 90, 70), 32, np.uint8, 4),
+    # FP32 bricks of 8 and 32 voxels: min/max combined from the blocked
+    # copy's per-block summaries (1 and 4 stored blocks per brick axis)
+    ((29, 37, 23), 8, np.float32, 5),
+    ((70, 41, 99), 32, np.float32, 6),
 ])
 def test_ragged_volumes(dims, B, dtype, seed):
     log(f"case: ragged {dims} B={B} {np.dtype(dtype).name} seed={seed}")
