@@ -729,12 +729,13 @@ def main():
         cp.append(e0.elapsed_time(e1))
     del dst
     copy_gbs = 2 * src.numel() * 4 / (statistics.median(cp) * 1e-3) / 1e9
-    # set_volume's algorithmic bytes: the min/max pass reads the volume and
-    # writes two values per brick; the blocked copy reads it and writes the
-    # blocked layout (per 8^3 block its 9^3 voxels, padded to 736 values)
+    # set_volume's algorithmic bytes (FP32, bricks of 16): the blocked copy
+    # reads the volume once and writes the blocked layout (per 8^3 block its
+    # 9^3 voxels, padded to 736 values) and 16 min/max summaries per block;
+    # the bricks' min/max are combined from those and written
     nvox = DIMS[0] * DIMS[1] * DIMS[2]
-    nq = [(d + 7) // 8 for d in DIMS]
-    sv_bytes = nvox * 4 + 2 * st["n_bricks"] * 4 + nvox * 4 + nq[0] * nq[1] * nq[2] * 736 * 4
+    nblocks = ((DIMS[0] + 7) // 8) * ((DIMS[1] + 7) // 8) * ((DIMS[2] + 7) // 8)
+    sv_bytes = nvox * 4 + nblocks * 736 * 4 + nblocks * 64 + 2 * st["n_bricks"] * 4
     sv_gbs = sv_bytes / (statistics.median(sv) * 1e-3) / 1e9
 
     mean_ms = {a: statistics.mean(render_ms[a]) for a in ACCELS}
