@@ -48,7 +48,8 @@ Layout make_layout(int nx, int ny, int nz, int brick, int elem_bytes, int max_tf
     const size_t n4 = (size_t)nb * 4;
     L.header = take(sizeof(DevHeader));
     L.swz = take((size_t)swz_bytes(nq, elem_bytes));
-    L.blksum = take((size_t)nq[0] * nq[1] * nq[2] * 16 * sizeof(float));
+    // min/max summaries per stored block: FP32 volumes with bricks of 8 or more
+    L.blksum = take(elem_bytes == 4 && brick >= kSwzEdge ? (size_t)nq[0] * nq[1] * nq[2] * 16 * sizeof(float) : 0);
     L.minv = take((size_t)nb * elem_bytes);
     L.maxv = take((size_t)nb * elem_bytes);
     L.tf = take((size_t)max_tf * 16);
