@@ -318,7 +318,6 @@ esk_status esk_workspace_bytes(int nx, int ny, int nz, int dtype, int brick, int
     if (!out) return ESK_EINVAL;
     esk_status s = check_shape(nullptr, nx, ny, nz, dtype, brick, max_tf_entries);
     if (s != ESK_OK) return s;
-    const int nbx = (nx + brick - 1) / brick, nby = (ny + brick - 1) / brick, nbz = (nz + brick - 1) / brick;
     *out = make_layout(nx, ny, nz, brick, elem_size(dtype), max_tf_entries).total;
     return ESK_OK;
 }
