@@ -83,6 +83,7 @@ Layout make_layout(int nx, int ny, int nz, int brick, int elem_bytes, int max_tf
     L.kd_first = take(2 * n4);
     L.kd_split = take(2 * n4);
     L.kd_clo = take(2 * n4 * 12);
+    L.kd_plist = take(2 * n4);
     L.kd_rnode = take(2 * (size_t)nb * sizeof(RNode));
     L.kd_box = take(2 * (size_t)nb * 16);
     L.total = off;
@@ -457,6 +458,7 @@ static KdArgs kd_args(esk_ctx *c, const esk_kd_params *p)
     k.first = at<int32_t>(c, L.kd_first);
     k.split = at<int32_t>(c, L.kd_split);
     k.clo = at<int32_t>(c, L.kd_clo);
+    k.plist = at<int32_t>(c, L.kd_plist);
     k.rnode = at<RNode>(c, L.kd_rnode);
     k.box = at<uint4>(c, L.kd_box);
     k.hdr = at<DevHeader>(c, L.header);

@@ -53,7 +53,7 @@ struct Layout {
     size_t ids, keys, skeys, tmpkeys, sids, hist;
     size_t tbox;           // voxel-tight box per brick (half-voxel units, packed)
     size_t lb_left, lb_right, lb_axis, lb_parent, lb_lo, lb_hi, lb_range, lb_rnode, lb_leafbox, lb_root, lb_chunk;
-    size_t kd_S, kd_lo, kd_hi, kd_axis, kd_plane, kd_first, kd_split, kd_clo, kd_rnode, kd_box;
+    size_t kd_S, kd_lo, kd_hi, kd_axis, kd_plane, kd_first, kd_split, kd_clo, kd_plist, kd_rnode, kd_box;
     size_t total;
 };
 
@@ -132,6 +132,7 @@ struct KdArgs {
     const uint8_t *flags;
     int32_t *S;
     int32_t *lo, *hi, *axis, *plane, *first, *split, *clo;  // clo: [node][side][6 faces]
+    int32_t *plist;        // the splitting nodes of the last level, in order (parents of the next level)
     RNode *rnode;
     uint4 *box;
     DevHeader *hdr;

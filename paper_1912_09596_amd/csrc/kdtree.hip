@@ -161,13 +161,30 @@ constexpr int kMaxCand = 45;   // 3 axes x (16 bins - 1)
 // face) binary search runs on its own lane; lane 0 writes axis, plane, split
 // flag and the two children's tight boxes.  tb: this wave's scratch.
 template <typename SP>
-__device__ void eval_node(const KdArgs &k, SP S, int64_t node, int64_t vroot, int16_t (*tb)[2][6])
+__device__ void eval_node(const KdArgs &k, SP S, int64_t node, int64_t begin, int64_t vroot, int16_t (*tb)[2][6])
 {
     const int lane = threadIdx.x & 63;
     int lo[3], hi[3];
-    for (int q = 0; q < 3; ++q) {
-        lo[q] = k.lo[3 * node + q];
-        hi[q] = k.hi[3 * node + q];
+    if (node == 0) {
+        for (int q = 0; q < 3; ++q) {
+            lo[q] = k.lo[q];
+            hi[q] = k.hi[q];
+        }
+    } else {
+        // child `side` of the (r/2)-th splitting node of the level above: its
+        // box from the parent's child boxes, recorded for later readers
+        const int64_t r = node - begin;
+        const int64_t p = k.plist[r >> 1];
+        const int32_t *cb = &k.clo[12 * p + 6 * (r & 1)];
+        for (int q = 0; q < 3; ++q) {
+            lo[q] = cb[q];
+            hi[q] = cb[3 + q];
+        }
+        if (lane == 0)
+            for (int q = 0; q < 3; ++q) {
+                k.lo[3 * node + q] = lo[q];
+                k.hi[3 * node + q] = hi[q];
+            }
     }
     const int64_t V = box_volume(k, lo, hi);
     const bool allowed = k.halting == 0 ? (10 * V > vroot) : (V > 512);
@@ -331,7 +348,7 @@ __global__ __launch_bounds__(256) void k_kd_level(KdArgs k)
     const int64_t vroot = root_volume(k);
     for (int64_t node = (int64_t)begin + (int64_t)blockIdx.x * 4 + wave; node < end;
          node += (int64_t)gridDim.x * 4) {
-        eval_node(k, (const int32_t *)k.S, node, vroot, tb[wave]);
+        eval_node(k, (const int32_t *)k.S, node, (int64_t)begin, vroot, tb[wave]);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -355,17 +372,12 @@ __global__ __launch_bounds__(256) void k_kd_level(KdArgs k)
     uint32_t run = block_exclusive_scan<256>(c, scratch, &total);
     const bool fits = (int64_t)end + 2 * (int64_t)total <= k.cap;
     if (fits) {
+        // children are numbered in parent order; each child reads its box
+        // from the parent's record when its own level is evaluated
         for (int64_t i = i0; i < i1; ++i) {
             if (!__hip_atomic_load(&k.split[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) continue;
-            const int64_t child = (int64_t)end + 2 * (int64_t)run;
-            k.first[i] = (int32_t)child;
-            for (int s2 = 0; s2 < 2; ++s2)
-                for (int q = 0; q < 3; ++q) {
-                    k.lo[3 * (child + s2) + q] = __hip_atomic_load(&k.clo[12 * i + 6 * s2 + q], __ATOMIC_RELAXED,
-                                                                   __HIP_MEMORY_SCOPE_AGENT);
-                    k.hi[3 * (child + s2) + q] = __hip_atomic_load(&k.clo[12 * i + 6 * s2 + 3 + q],
-                                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
+            k.first[i] = (int32_t)((int64_t)end + 2 * (int64_t)run);
+            k.plist[run] = (int32_t)i;
             ++run;
         }
     }
