@@ -416,47 +416,58 @@ hipError_t launch_swz_typed(const VolumeDesc &v, void *swz, float *blksum, hipSt
     return hipGetLastError();
 }
 
-// Brick min/max from the stored blocks' summaries (one thread per brick;
-// B >= 8): every combination of "layer 7 of the block below" and "the core
-// blocks" per axis (the lower layer only where the brick is not first).
+// Brick min/max from the stored blocks' summaries (B >= 8): every
+// combination of "layer 7 of the block below" and "the core blocks" per axis
+// (the lower layer only where the brick is not first); eight lanes per brick,
+// one combination each, then a reduction over the eight.
 template <typename T>
 __global__ __launch_bounds__(256) void k_minmax_blocks(const float *__restrict__ blksum, int B, int nbx, int nby,
                                                        int nbz, int nq0, int nq1, int nq2, T *__restrict__ outmin,
                                                        T *__restrict__ outmax)
 {
-    const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (id >= (int64_t)nbx * nby * nbz) return;
-    const int b[3] = {(int)(id % nbx), (int)((id / nbx) % nby), (int)(id / ((int64_t)nbx * nby))};
-    const int nq[3] = {nq0, nq1, nq2};
-    const int per = B / kSwzEdge;
-    int c0[3], c1[3];
-    for (int a = 0; a < 3; ++a) {
-        c0[a] = b[a] * per;
-        c1[a] = min(c0[a] + per, nq[a]);
-    }
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t id = t >> 3;
+    const int m = (int)(t & 7);
+    const bool live = id < (int64_t)nbx * nby * nbz;
     float mn = __builtin_inff(), mx = -__builtin_inff();
-    for (int m = 0; m < 8; ++m) {
-        if (((m & 1) && b[0] == 0) || ((m & 2) && b[1] == 0) || ((m & 4) && b[2] == 0)) continue;
-        const int x0 = (m & 1) ? c0[0] - 1 : c0[0], x1 = (m & 1) ? c0[0] : c1[0];
-        const int y0 = (m & 2) ? c0[1] - 1 : c0[1], y1 = (m & 2) ? c0[1] : c1[1];
-        const int z0 = (m & 4) ? c0[2] - 1 : c0[2], z1 = (m & 4) ? c0[2] : c1[2];
-        for (int qz = z0; qz < z1; ++qz)
-            for (int qy = y0; qy < y1; ++qy)
-                for (int qx = x0; qx < x1; ++qx) {
-                    const float *sm = blksum + ((((size_t)qz * nq1 + qy) * nq0 + qx) << 4);
-                    mn = fminf(mn, sm[m]);
-                    mx = fmaxf(mx, sm[8 + m]);
-                }
+    if (live) {
+        const int b[3] = {(int)(id % nbx), (int)((id / nbx) % nby), (int)(id / ((int64_t)nbx * nby))};
+        const int nq[3] = {nq0, nq1, nq2};
+        const int per = B / kSwzEdge;
+        int c0[3], c1[3];
+        for (int a = 0; a < 3; ++a) {
+            c0[a] = b[a] * per;
+            c1[a] = min(c0[a] + per, nq[a]);
+        }
+        if (!(((m & 1) && b[0] == 0) || ((m & 2) && b[1] == 0) || ((m & 4) && b[2] == 0))) {
+            const int x0 = (m & 1) ? c0[0] - 1 : c0[0], x1 = (m & 1) ? c0[0] : c1[0];
+            const int y0 = (m & 2) ? c0[1] - 1 : c0[1], y1 = (m & 2) ? c0[1] : c1[1];
+            const int z0 = (m & 4) ? c0[2] - 1 : c0[2], z1 = (m & 4) ? c0[2] : c1[2];
+            for (int qz = z0; qz < z1; ++qz)
+                for (int qy = y0; qy < y1; ++qy)
+                    for (int qx = x0; qx < x1; ++qx) {
+                        const float *sm = blksum + ((((size_t)qz * nq1 + qy) * nq0 + qx) << 4);
+                        mn = fminf(mn, sm[m]);
+                        mx = fmaxf(mx, sm[8 + m]);
+                    }
+        }
     }
-    outmin[id] = from_float<T>(mn);
-    outmax[id] = from_float<T>(mx);
+    // the brick's eight lanes are consecutive and aligned within the wave
+    for (int o = 4; o >= 1; o >>= 1) {
+        mn = fminf(mn, __shfl_xor(mn, o, 64));
+        mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    }
+    if (live && m == 0) {
+        outmin[id] = from_float<T>(mn);
+        outmax[id] = from_float<T>(mx);
+    }
 }
 
 template <typename T>
 hipError_t launch_mmb_typed(const VolumeDesc &v, const float *blksum, void *minv, void *maxv, hipStream_t s)
 {
     const int64_t nb = (int64_t)v.nb[0] * v.nb[1] * v.nb[2];
-    hipLaunchKernelGGL((k_minmax_blocks<T>), dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, blksum, v.B,
+    hipLaunchKernelGGL((k_minmax_blocks<T>), dim3((unsigned)((8 * nb + 255) / 256)), dim3(256), 0, s, blksum, v.B,
                        v.nb[0], v.nb[1], v.nb[2], v.nq[0], v.nq[1], v.nq[2], static_cast<T *>(minv),
                        static_cast<T *>(maxv));
     return hipGetLastError();
