@@ -404,8 +404,14 @@ __device__ inline void leaf_range(const Ray &r, float dt, const int lo[3], const
     float fb = (tf - r.t0) * idt - 0.5f;
     fa = fminf(fmaxf(fa, -4.0f), 1.0e9f);
     fb = fminf(fmaxf(fb, -4.0f), 1.0e9f);
-    ka = max(0, (int)floorf(fa) - 1);
-    kb = (int)floorf(fb) + 2;
+    // Along the ray the box slack kBoxEps is at least 1/32 voxel, and the
+    // FP32 error of tn, tf (and of fa, fb, in voxels) stays below t * 2^-21:
+    // under 1/32 voxel while t < 65536, for any dt.  Rays that end before
+    // t = 16384 therefore take [floor(fa), floor(fb) + 1) as is; farther
+    // ones widen it by a sample on each side.
+    const int m = r.tx < 16384.0f ? 0 : 1;
+    ka = max(0, (int)floorf(fa) - m);
+    kb = (int)floorf(fb) + 1 + m;
 }
 
 // samples of the lattice that fall in the leaf box [lo/2, hi/2), found with
