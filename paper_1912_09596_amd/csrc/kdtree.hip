@@ -365,21 +365,50 @@ __global__ __launch_bounds__(256) void k_kd_level(KdArgs k)
     const int64_t per = (width + 255) / 256;
     const int64_t i0 = begin + threadIdx.x * per;
     const int64_t i1 = min((int64_t)end, i0 + per);
+    // plain loads: the fence above (acquire, agent scope) follows the other
+    // blocks' release through the ticket, so their flags are visible; eight
+    // at a time so the loads overlap instead of waiting one by one
+    constexpr int U = 8;
     uint32_t c = 0;
-    for (int64_t i = i0; i < i1; ++i)
-        c += (uint32_t)__hip_atomic_load(&k.split[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    {
+        int64_t i = i0;
+        for (; i + U <= i1; i += U) {
+            int32_t f[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) f[u] = k.split[i + u];
+#pragma unroll
+            for (int u = 0; u < U; ++u) c += f[u] != 0 ? 1u : 0u;
+        }
+        for (; i < i1; ++i) c += k.split[i] != 0 ? 1u : 0u;
+    }
     uint32_t total;
     uint32_t run = block_exclusive_scan<256>(c, scratch, &total);
     const bool fits = (int64_t)end + 2 * (int64_t)total <= k.cap;
     if (fits) {
         // children are numbered in parent order; each child reads its box
         // from the parent's record when its own level is evaluated
-        for (int64_t i = i0; i < i1; ++i) {
-            if (!__hip_atomic_load(&k.split[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) continue;
-            k.first[i] = (int32_t)((int64_t)end + 2 * (int64_t)run);
-            k.plist[run] = (int32_t)i;
-            ++run;
+        const int32_t *__restrict__ sp = k.split;
+        int32_t *__restrict__ fp = k.first;
+        int32_t *__restrict__ pl = k.plist;
+        int64_t i = i0;
+        for (; i + U <= i1; i += U) {
+            int32_t f[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) f[u] = sp[i + u];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (f[u]) {
+                    fp[i + u] = (int32_t)((int64_t)end + 2 * (int64_t)run);
+                    pl[run] = (int32_t)(i + u);
+                    ++run;
+                }
         }
+        for (; i < i1; ++i)
+            if (sp[i]) {
+                fp[i] = (int32_t)((int64_t)end + 2 * (int64_t)run);
+                pl[run] = (int32_t)i;
+                ++run;
+            }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
