@@ -159,6 +159,19 @@ def test_ragged_volumes(dims, B, dtype, seed):
         check_images(ctx, vol, tf, cam, W, H, flags, B, label=f"{dims} ortho={ortho}")
 
 
+def test_far_cameras():
+    # rays ending beyond t = 16384 take leaf sample ranges widened by a
+    # sample on each side (FP32 error of the slab values grows with t)
+    w = synth.c1_workload()
+    log("case: C1 seen from ~22000 voxels (perspective and orthographic)")
+    esk, ctx, flags, _, _ = run_case(w["vol"], w["tf"], w["brick"], label="far")
+    cam = synth.perspective((64, 64, 64), 64, 48, synth.view_direction(7), fovy_deg=0.25, dist=200.0)
+    assert float(np.linalg.norm(cam["eye"] - 32.0)) > 16384 + 200
+    check_images(ctx, w["vol"], w["tf"], cam, 64, 48, flags, w["brick"], label="far perspective")
+    cam = synth.orthographic((64, 64, 64), 64, 48, synth.view_direction(8), dist=200.0)
+    check_images(ctx, w["vol"], w["tf"], cam, 64, 48, flags, w["brick"], label="far ortho")
+
+
 def test_float_value_range_and_opacity_modes():
     log("case: f32 with value range [-2, 3], dt 0.05 / 0.37 / 1.0 / 2.3 / 7.9, ref 0 / 1 / 2")
     dims = (40, 36, 44)
