@@ -186,11 +186,13 @@ esk_status esk_set_volume(esk_ctx *ctx, const void *d_vox, int dtype, int nx, in
 
 /* Sets the TF and rebuilds (Sec. 3.1, 3.2.2): TF prefix count -> brick
  * classification (or the per-voxel vote with ESK_CLASSIFY_VOXEL) -> grid
- * bitmask -> compaction -> Morton codes -> radix sort -> Karras hierarchy ->
+ * bitmask -> compaction -> Morton codes in sorted order (by enumerating the
+ * brick grid's codes, or a radix sort for lopsided grids) -> Karras hierarchy ->
  * AABB refit (if ESK_ACCEL_LBVH in build_mask), and the 3-D occupancy prefix
  * count -> level-synchronous binned k-d build (if ESK_ACCEL_KD).  The grid
- * is always built.  d_rgba: N x RGBA float32 on the device, copied into the
- * workspace (the caller may reuse it once the stream reaches this point).
+ * is always built.  d_rgba: N x RGBA float32 on the device (16-byte
+ * aligned), read by the enqueued work and copied into the workspace (the
+ * caller may reuse it once the stream reaches this point).
  * kd may be NULL when ESK_ACCEL_KD is not requested.  Asynchronous: the k-d
  * build runs on an internal stream of the context and is checked for
  * completion (one synchronisation) when the tree is first used. */
