@@ -550,12 +550,6 @@ esk_status esk_set_transfer_function(esk_ctx *c, const float *d_rgba, int n_entr
         c->kd_on_device = true;
         c->kd_joined = false;
     }
-#ifndef ESK_NO_WARM
-    // stream the non-empty bricks' blocks of the renderer's copy into the
-    // last-level cache ahead of the first render
-    e = launch_warm(a, elem_size(c->vol.dtype), c->stream);
-    if (e != hipSuccess) return hip_check(c, e, "warm-up launch");
-#endif
     // classification always writes the grid bitmask
     c->built = (build_mask & (ESK_ACCEL_LBVH | ESK_ACCEL_KD)) | ESK_ACCEL_GRID;
     c->has_tf = true;

@@ -122,7 +122,6 @@ struct RebuildArgs {
 
 hipError_t launch_vote(const RebuildArgs &a, hipStream_t s);
 hipError_t launch_tight(const RebuildArgs &a, hipStream_t s);
-hipError_t launch_warm(const RebuildArgs &a, int elem_bytes, hipStream_t s);
 hipError_t launch_classify_compact(const RebuildArgs &a, hipStream_t s);
 hipError_t launch_sort(const RebuildArgs &a, hipStream_t s);
 hipError_t launch_lbvh(const RebuildArgs &a, hipStream_t s);

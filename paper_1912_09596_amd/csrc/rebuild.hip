@@ -230,51 +230,6 @@ template <typename T> hipError_t launch_tight_typed(const RebuildArgs &a, hipStr
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// Cache warm-up of the blocked copy: after a rebuild, the 8^3 blocks of the
-// non-empty bricks (what the renderer will gather from) are read once with
-// wide streaming loads, so the device's last-level cache holds them before
-// the first render instead of the render missing on them one gather at a
-// time.  One workgroup per non-empty brick (grid-stride); the loaded words
-// are folded into a value stored only if impossible, so the loads stay.
-// ---------------------------------------------------------------------------
-
-__global__ __launch_bounds__(256) void k_warm(RebuildArgs a, int block_bytes, uint32_t *sink, int never)
-{
-    const int n = (int)a.hdr->n;
-    const int B = a.vol.B;
-    const uint32_t nbx = (uint32_t)a.vol.nb[0], nby = (uint32_t)a.vol.nb[1];
-    const int nq0 = a.vol.nq[0], nq1 = a.vol.nq[1], nq2 = a.vol.nq[2];
-    const int blk16 = block_bytes / 16;   // 16-byte words per stored block
-    const uint4 *swz = static_cast<const uint4 *>(a.vol.swz);
-    // only when the blocks fit the last-level cache (256 MB; budget 192 MB):
-    // beyond that the warm-up would evict its own lines before the render
-    const int64_t per_brick = B >= 8 ? (int64_t)(B >> 3) * (B >> 3) * (B >> 3) : 1;
-    if ((int64_t)n * per_brick * block_bytes > ((int64_t)192 << 20)) return;
-    uint32_t acc = 0;
-    for (int i = blockIdx.x; i < n; i += gridDim.x) {
-        const uint32_t id = a.ids[i];
-        const int bc[3] = {(int)(id % nbx), (int)((id / nbx) % nby), (int)(id / (nbx * nby))};
-        int q0[3], qn[3];
-        for (int q = 0; q < 3; ++q) {
-            q0[q] = (bc[q] * B) >> 3;
-            qn[q] = max(1, B >> 3);
-        }
-        qn[0] = min(qn[0], nq0 - q0[0]);
-        qn[1] = min(qn[1], nq1 - q0[1]);
-        qn[2] = min(qn[2], nq2 - q0[2]);
-        const int words = qn[0] * qn[1] * qn[2] * blk16;
-        for (int w = threadIdx.x; w < words; w += 256) {
-            const int b = w / blk16, o = w - b * blk16;
-            const int qx = q0[0] + b % qn[0], qy = q0[1] + (b / qn[0]) % qn[1], qz = q0[2] + b / (qn[0] * qn[1]);
-            const uint4 v = swz[(((size_t)qz * nq1 + qy) * nq0 + qx) * blk16 + o];
-            acc ^= v.x ^ v.y ^ v.z ^ v.w;
-        }
-    }
-    // never taken (the host passes never = -1), but not provably so
-    if (acc == 0x9e3779b9u && (int)threadIdx.x == never) *sink = acc;
-}
-
 __global__ __launch_bounds__(256) void k_classify(RebuildArgs a)
 {
     __shared__ int32_t P[kMaxTF + 1];
@@ -855,13 +810,6 @@ hipError_t launch_tight(const RebuildArgs &a, hipStream_t s)
     case ESK_F32: return launch_tight_typed<float>(a, s);
     }
     return hipErrorInvalidValue;
-}
-
-hipError_t launch_warm(const RebuildArgs &a, int elem_bytes, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_warm, dim3((unsigned)std::min<int64_t>(a.nb, 2048)), dim3(256), 0, s, a,
-                       kSwzBlock * elem_bytes, a.blkcnt, -1);
-    return hipGetLastError();
 }
 
 hipError_t launch_classify_compact(const RebuildArgs &a, hipStream_t s)
