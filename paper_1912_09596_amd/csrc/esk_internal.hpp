@@ -122,7 +122,12 @@ struct RebuildArgs {
 
 hipError_t launch_vote(const RebuildArgs &a, hipStream_t s);
 hipError_t launch_tight(const RebuildArgs &a, hipStream_t s);
-hipError_t launch_classify_compact(const RebuildArgs &a, hipStream_t s);
+// classification, grid bitmask and block counts (hdr->n)
+hipError_t launch_classify(const RebuildArgs &a, hipStream_t s);
+// ids of the non-empty bricks in ascending id, with their Morton keys (after launch_classify)
+hipError_t launch_compact(const RebuildArgs &a, hipStream_t s);
+// the sorted keys come from enumerating the brick grid's Morton codes (no sort, no compaction input)
+bool sort_by_enumeration(const RebuildArgs &a);
 hipError_t launch_sort(const RebuildArgs &a, hipStream_t s);
 hipError_t launch_lbvh(const RebuildArgs &a, hipStream_t s);
 

@@ -812,19 +812,29 @@ hipError_t launch_tight(const RebuildArgs &a, hipStream_t s)
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_classify_compact(const RebuildArgs &a, hipStream_t s)
+hipError_t launch_classify(const RebuildArgs &a, hipStream_t s)
 {
     const unsigned blocks = (unsigned)a.nblk;
     hipLaunchKernelGGL(k_classify, dim3(blocks), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, a.blkcnt, a.nblk, a.hdr);
-    hipLaunchKernelGGL(k_compact, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
+}
+
+hipError_t launch_compact(const RebuildArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)a.nblk), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+bool sort_by_enumeration(const RebuildArgs &a)
+{
+    return ((int64_t)1 << a.key_bits) <= 4 * a.nb;
 }
 
 hipError_t launch_sort(const RebuildArgs &a, hipStream_t s)
 {
     const int64_t codes = (int64_t)1 << a.key_bits;
-    if (codes <= 4 * a.nb) {
+    if (sort_by_enumeration(a)) {
         // sorted keys by enumeration; the block counts go to `hist` (the
         // sort's histogram, unused on this path: ceil(nb/4096)*256 entries
         // >= codes/1024 blocks)
