@@ -420,3 +420,47 @@ def test_voxel_tight_boxes(dims, B, dtype, seed):
         for accel in ("grid", "lbvh", "kd", "hybrid"):
             assert np.array_equal(imgs[accel], imgs["none"]), (kd, accel)
         log(f"  kd={kd}: samples full {int(ref.shape[0])}x, brick {int(c_brick.sum())}, tight {int(c_tight.sum())}")
+
+
+def test_compaction_on_export():
+    """The brick ids and their Morton keys are compacted in the rebuild only
+    where a later step reads them (voxel-tight boxes, the radix sort), else
+    when exported: every export must show the current classification, after
+    rebuilds that compacted and rebuilds that did not, across TFs and
+    volumes, and in either export order."""
+    esk, ctx = make_ctx()
+    torch = _torch()
+    steps = [
+        # (dims, B, build, tight, tf seed, export keys first)
+        ((64, 64, 64), 8, ("grid",), False, 1, True),      # no compaction in the rebuild
+        ((64, 64, 64), 8, ("grid",), False, 2, False),     # new TF: the old ids must not show
+        ((64, 64, 64), 8, ("lbvh",), False, 3, True),      # sorted keys by enumeration
+        ((64, 64, 64), 8, ("grid",), True, 4, False),      # compacted for the tight boxes
+        ((64, 64, 64), 8, ("kd",), False, 5, True),
+        ((200, 24, 24), 8, ("lbvh",), False, 6, False),    # 25x3x3 bricks: radix sort
+        ((200, 24, 24), 8, ("grid",), False, 7, True),
+    ]
+    last = None
+    for dims, B, build, tight, seed, keys_first in steps:
+        log(f"case: compaction on export {dims} B={B} {build} tight={tight} tf={seed}")
+        vol = synth.blobs_u8(dims, seed=sum(dims), n_blobs=5, cut=40)
+        tf = synth.tf_random(seed + 60, 256)
+        if (dims, B) != last:
+            ctx.set_volume(to_dev(vol), B, max_tf=256)
+            last = (dims, B)
+        ctx.set_tf(to_dev(tf), build=build, kd=esk.Kd(1, 0, 4), tight=tight)
+        torch.cuda.synchronize()
+        mn, mx = oracle.brick_minmax(vol, B)
+        flags = oracle.classify(mn, mx, vol.dtype, tf)
+        ids = oracle.compact(flags)
+        nb = oracle.brick_grid(dims, B)
+        keys = oracle.morton_keys(ids, nb[0], nb[1])
+        order = ("keys", "ids") if keys_first else ("ids", "keys")
+        got = {k: ctx.export(k) for k in order}
+        assert np.array_equal(ctx.export("flags"), flags)
+        assert np.array_equal(got["ids"], ids), (dims, build, seed)
+        assert np.array_equal(got["keys"], keys), (dims, build, seed)
+        if "lbvh" in build:
+            sk, si = oracle.sort_pairs(keys, ids)
+            assert np.array_equal(ctx.export("sorted_keys"), sk)
+            assert np.array_equal(ctx.export("sorted_ids"), si)
