@@ -236,7 +236,10 @@ esk_status esk_get_stats(esk_ctx *ctx, esk_stats *out);
 
 /* Synchronises and copies one array of the current state into `host`
  * (capacity cap bytes); *used receives the byte count (also when cap is too
- * small, which returns ESK_ENOSPC). */
+ * small, which returns ESK_ENOSPC).  ESK_X_IDS and ESK_X_KEYS: where the
+ * last rebuild did not need them (no voxel-tight boxes, sorted keys by
+ * enumeration) the export first enqueues the compaction (Sec. 3.1) of the
+ * current flags on the context's stream. */
 esk_status esk_export(esk_ctx *ctx, int what, void *host, size_t cap, size_t *used);
 
 const char *esk_strerror(esk_status s);

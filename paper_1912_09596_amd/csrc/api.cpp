@@ -129,7 +129,7 @@ struct esk_ctx {
     hipEvent_t ev_fork = nullptr, ev_kd = nullptr;
     DevHeader *pinned_kd = nullptr;   // header snapshot taken at the end of the k-d build
     bool kd_joined = true;            // main stream already ordered after the last k-d build
-    bool compacted = false;           // ids/keys of the current classification written
+    bool rebuild_compacts = false;    // the last rebuild (and any replay of it) writes ids/keys
 };
 
 namespace {
@@ -514,9 +514,10 @@ esk_status esk_set_transfer_function(esk_ctx *c, const float *d_rgba, int n_entr
     if (e != hipSuccess) return hip_check(c, e, "classify launch");
     c->tight = (build_mask & ESK_TIGHT_BOXES) != 0;
     // the compacted ids/keys feed the tight boxes and the radix sort only;
-    // otherwise they are made when exported
-    c->compacted = c->tight || ((build_mask & ESK_ACCEL_LBVH) && !sort_by_enumeration(a));
-    if (c->compacted) {
+    // otherwise every export of them makes them from the current flags (a
+    // replayed capture of this rebuild classifies again without the host)
+    c->rebuild_compacts = c->tight || ((build_mask & ESK_ACCEL_LBVH) && !sort_by_enumeration(a));
+    if (c->rebuild_compacts) {
         e = launch_compact(a, c->stream);
         if (e != hipSuccess) return hip_check(c, e, "compaction launch");
     }
@@ -774,11 +775,10 @@ esk_status esk_export(esk_ctx *c, int what, void *host, size_t cap, size_t *used
     const bool need_tf = what != ESK_X_MINMAX;
     if (need_tf && !c->has_tf) return fail(c, ESK_ESTATE, "no transfer function set");
     const bool lbvh = c->built & ESK_ACCEL_LBVH;
-    if ((what == ESK_X_IDS || what == ESK_X_KEYS) && !c->compacted) {
+    if ((what == ESK_X_IDS || what == ESK_X_KEYS) && !c->rebuild_compacts) {
         e = launch_compact(rebuild_args(c), c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) return hip_check(c, e, "compaction for export");
-        c->compacted = true;
     }
     switch (what) {
     case ESK_X_MINMAX: {

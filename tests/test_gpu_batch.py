@@ -87,7 +87,10 @@ def test_brick_autotuner_choice_renders_the_same_image():
 def test_rebuild_render_graph_replays():
     """Rebuild + render captured once and replayed with three different TFs:
     every replay equals the eager rebuild + render of the same TF bit for bit
-    (eager work and synchronisations between the replays)."""
+    (eager work and synchronisations between the replays), and the flags,
+    brick ids and Morton keys exported after each replay are the oracle's
+    for that TF (the ids and keys are made at export when the captured
+    rebuild does not make them)."""
     torch = _torch()
     import paper_1912_09596_amd as esk
     from paper_1912_09596_amd.graphs import RebuildRenderGraph
@@ -108,5 +111,12 @@ def test_rebuild_render_graph_replays():
             torch.cuda.synchronize()
             assert np.array_equal(got, want), (accel, seed)
             assert np.abs(got).max() > 0
+            mn, mx = oracle.brick_minmax(r["vol"], r["B"])
+            flags = oracle.classify(mn, mx, r["vol"].dtype, synth.tf_random(seed, 256))
+            ids = oracle.compact(flags)
+            nb = oracle.brick_grid(r["dims"], r["B"])
+            assert np.array_equal(g.ctx.export("flags"), flags), (accel, seed)
+            assert np.array_equal(g.ctx.export("ids"), ids), (accel, seed)
+            assert np.array_equal(g.ctx.export("keys"), oracle.morton_keys(ids, nb[0], nb[1])), (accel, seed)
         eager.close()
         g.close()
