@@ -20,7 +20,9 @@
  *    ESK_ELIMIT.
  *  - Transfer functions are N x RGBA float32, N in [2, 4096]; entry i sits at
  *    the normalised value i/(N-1).  Normalised value s(v): v/255 (u8),
- *    v/65535 (u16), clamp((v-lo)/(hi-lo), 0, 1) (f16, f32).
+ *    v/65535 (u16), clamp((v-lo)/(hi-lo), 0, 1) (f16, f32).  Every step
+ *    reads an entry's opacity clamped to [0, 1], with NaN read as 0, so an
+ *    entry is visible iff its alpha > 0; colour is used as given.
  *  - Images are H x W x RGBA float32, row 0 at the top, premultiplied colour.
  *  - Device pointers are HIP device addresses on the context's device.  All
  *    device memory is owned by the caller; the library borrows it and never

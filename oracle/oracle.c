@@ -100,6 +100,19 @@ int orc_brick_minmax(const void *vol, int dtype, int nx, int ny, int nz, int B,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Opacity of TF entry i as every step below reads it: the paper leaves the  */
+/* TF's value range unstated; an opacity is a fraction, so values above 1    */
+/* count as 1 and negative or NaN values as 0 (fully transparent).  Colour   */
+/* is used as given.                                                          */
+/* ------------------------------------------------------------------------ */
+static float tf_alpha(const float *tf, int i)
+{
+    float a = tf[4 * i + 3];
+    if (!(a > 0.0f)) return 0.0f; /* also NaN */
+    return a > 1.0f ? 1.0f : a;
+}
+
+/* ------------------------------------------------------------------------ */
 /* a2: prefix count of visible transfer-function entries,                    */
 /* P[0] = 0, P[i+1] = P[i] + (alpha_i > 0).  (The range-query table the      */
 /* commented-out note under the statistics table prices at 1024 entries.)    */
@@ -108,7 +121,7 @@ int orc_tf_prefix(const float *tf, int N, int32_t *P)
 {
     if (!tf || N < 2) return -1;
     P[0] = 0;
-    for (int i = 0; i < N; ++i) P[i + 1] = P[i] + (tf[4 * i + 3] > 0.0f ? 1 : 0);
+    for (int i = 0; i < N; ++i) P[i + 1] = P[i] + (tf_alpha(tf, i) > 0.0f ? 1 : 0);
     return 0;
 }
 
@@ -194,7 +207,7 @@ int64_t orc_vote(const void *vol, int dtype, int nx, int ny, int nz, int B, floa
                 int i0 = (int)t;
                 if (i0 > N - 2) i0 = N - 2;
                 const float f = t - (float)i0;
-                const float a0 = tf[4 * i0 + 3], a1 = tf[4 * (i0 + 1) + 3];
+                const float a0 = tf_alpha(tf, i0), a1 = tf_alpha(tf, i0 + 1);
                 if (fmaf(f, a1 - a0, a0) > 0.0f) flags[b] = 1;
             }
     int64_t count = 0;
@@ -712,7 +725,8 @@ static int64_t march_pixel(const render_ctx *r, const orc_camera *cam, int px, i
         double f = x - (double)i0;
         double c[4];
         for (int ch = 0; ch < 4; ++ch) {
-            double a0 = r->tf[4 * i0 + ch], a1 = r->tf[4 * (i0 + 1) + ch];
+            double a0 = ch == 3 ? tf_alpha(r->tf, i0) : r->tf[4 * i0 + ch];
+            double a1 = ch == 3 ? tf_alpha(r->tf, i0 + 1) : r->tf[4 * (i0 + 1) + ch];
             c[ch] = a0 + f * (a1 - a0);
         }
         double alpha = r->ref > 0.0f ? 1.0 - pow(1.0 - c[3], expo) : c[3];
@@ -779,7 +793,8 @@ int orc_sample(const void *vol, int dtype, int nx, int ny, int nz, float vlo, fl
         if (i0 > N - 2) i0 = N - 2;
         double f = x - (double)i0;
         for (int ch = 0; ch < 4; ++ch) {
-            double a0 = tf[4 * i0 + ch], a1 = tf[4 * (i0 + 1) + ch];
+            double a0 = ch == 3 ? tf_alpha(tf, i0) : tf[4 * i0 + ch];
+            double a1 = ch == 3 ? tf_alpha(tf, i0 + 1) : tf[4 * (i0 + 1) + ch];
             rgba[4 * i + ch] = a0 + f * (a1 - a0);
         }
     }

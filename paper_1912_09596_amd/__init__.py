@@ -121,6 +121,23 @@ def _dtype_code(t) -> int:
     return codes[t.dtype]
 
 
+def _require(t, name, device, dtype=None, shape=None):
+    """Raises unless tensor t has the dtype and shape the kernels read, is
+    contiguous, and lives on HIP device `device` (checked before any call
+    into the library: a wrong buffer would be read or written out of bounds)."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.device.type != "cuda" or t.device.index != device:
+        raise ValueError(f"{name} must be on cuda:{device}, got {t.device}")
+
+
 def workspace_bytes(dims_xyz, dtype_code: int, brick: int, max_tf: int = 4096) -> int:
     out = ctypes.c_size_t()
     st = lib().esk_workspace_bytes(int(dims_xyz[0]), int(dims_xyz[1]), int(dims_xyz[2]),
@@ -180,16 +197,19 @@ class Context:
     def set_volume(self, vol, brick: int, value_range=(0.0, 1.0), max_tf: int = 1024, workspace=None):
         """vol: contiguous [nz, ny, nx] device tensor (u8/u16/f16/f32)."""
         import torch
-        if not vol.is_contiguous() or vol.dim() != 3:
-            raise ValueError("volume must be a contiguous 3-D tensor [nz, ny, nx]")
-        nz, ny, nx = vol.shape
+        if not isinstance(vol, torch.Tensor) or vol.dim() != 3:
+            raise ValueError("volume must be a 3-D tensor [nz, ny, nx]")
         code = _dtype_code(vol)
+        _require(vol, "volume", self.device)
+        nz, ny, nx = vol.shape
         need = workspace_bytes((nx, ny, nz), code, brick, max_tf)
         if workspace is None:
             workspace = torch.empty(need, dtype=torch.uint8, device=vol.device)
+        _require(workspace, "workspace", self.device)
         self._check(self._lib.esk_set_volume(self._ctx, ctypes.c_void_p(vol.data_ptr()), code, nx, ny, nz,
                                              float(value_range[0]), float(value_range[1]), brick, max_tf,
-                                             ctypes.c_void_p(workspace.data_ptr()), workspace.numel()))
+                                             ctypes.c_void_p(workspace.data_ptr()),
+                                             workspace.numel() * workspace.element_size()))
         self._keep = {"vol": vol, "ws": workspace}
         self.dims = (nx, ny, nz)
         self.brick = brick
@@ -202,8 +222,10 @@ class Context:
         structures.  classify: "minmax" (conservative brick value ranges) or
         "voxel" (the per-voxel vote).  tight: march LBVH and k-d leaves inside
         voxel-tight boxes."""
-        if tf.dtype.is_floating_point is False or tf.dim() != 2 or tf.shape[1] != 4:
+        import torch
+        if not isinstance(tf, torch.Tensor) or tf.dim() != 2 or tf.shape[1] != 4:
             raise ValueError("TF must be an [N, 4] float32 tensor")
+        _require(tf, "TF", self.device, torch.float32)
         if classify not in ("minmax", "voxel"):
             raise ValueError("classify must be 'minmax' or 'voxel'")
         mask = (CLASSIFY_VOXEL if classify == "voxel" else 0) | (TIGHT_BOXES if tight else 0)
@@ -227,6 +249,9 @@ class Context:
         import torch
         if out is None:
             out = torch.empty((H, W, 4), dtype=torch.float32, device=self._keep["vol"].device)
+        _require(out, "out", self.device, torch.float32, (H, W, 4))
+        if counts is not None:
+            _require(counts, "counts", self.device, torch.int32, (H, W))
         c = camera_struct(cam)
         self._check(self._lib.esk_render(self._ctx, ACCEL[accel] if isinstance(accel, str) else int(accel),
                                          ctypes.byref(c), W, H, float(step), float(ref),
@@ -283,6 +308,11 @@ def render_batch(contexts, cams, sizes, accel="lbvh", step=0.5, ref=1.0, outs=No
         args_buffer = torch.empty(need.value, dtype=torch.uint8, device=dev)
     if outs is None:
         outs = [torch.empty((h, w, 4), dtype=torch.float32, device=dev) for (w, h) in sizes]
+    if not (len(cams) == n and len(sizes) == n and len(outs) == n):
+        raise ValueError("contexts, cams, sizes and outs must have one entry per request")
+    for c, o, (w, h) in zip(contexts, outs, sizes):
+        _require(o, "out", c.device, torch.float32, (h, w, 4))
+    _require(args_buffer, "args_buffer", contexts[0].device, torch.uint8)
     ctx_arr = (ctypes.c_void_p * n)(*[c._ctx.value for c in contexts])
     cam_arr = (Camera * n)(*[camera_struct(c) for c in cams])
     w_arr = (ctypes.c_int * n)(*[int(w) for (w, h) in sizes])

@@ -91,12 +91,17 @@ __global__ __launch_bounds__(256) void k_fill_u8(uint8_t *p, int64_t n)
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0;
 }
 
+// Opacity of a TF entry as every kernel reads it: clamped to [0, 1], NaN as
+// 0 (an opacity is a fraction; the caller's TF is not trusted to be one).
+// Visibility (alpha > 0) is unchanged by the clamp.
+__device__ inline float clean_alpha(float a) { return a > 0.0f ? fminf(a, 1.0f) : 0.0f; }
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_vote(RebuildArgs a)
 {
     __shared__ float alpha[kMaxTF];
     const int N = a.N;
-    for (int i = threadIdx.x; i < N; i += 256) alpha[i] = a.tf_src[4 * i + 3];
+    for (int i = threadIdx.x; i < N; i += 256) alpha[i] = clean_alpha(a.tf_src[4 * i + 3]);
     __syncthreads();
     const int B = a.vol.B, sh = a.vol.log2B;
     const int nx = a.vol.nx, ny = a.vol.ny, nz = a.vol.nz;
@@ -252,9 +257,12 @@ __global__ __launch_bounds__(256) void k_classify(RebuildArgs a)
         __syncthreads();
         if (blockIdx.x == 0) {
             for (int i = threadIdx.x; i <= N; i += 256) a.tfP[i] = P[i];
-            // the renderer's copy of the TF (both 16-byte aligned)
-            for (int i = threadIdx.x; i < N; i += 256)
-                reinterpret_cast<float4 *>(a.tf)[i] = reinterpret_cast<const float4 *>(a.tf_src)[i];
+            // the renderer's copy of the TF (both 16-byte aligned), opacity clamped
+            for (int i = threadIdx.x; i < N; i += 256) {
+                float4 e = reinterpret_cast<const float4 *>(a.tf_src)[i];
+                e.w = clean_alpha(e.w);
+                reinterpret_cast<float4 *>(a.tf)[i] = e;
+            }
         }
     }
     const int64_t base = (int64_t)blockIdx.x * kClassifyBlock;

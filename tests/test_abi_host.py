@@ -136,3 +136,43 @@ def test_status_strings_and_null_handles():
     assert L.esk_destroy(None) == esk.EINVAL
     assert L.esk_sync(None) == esk.EINVAL
     assert L.esk_create(-2, None, ctypes.byref(ctypes.c_void_p())) == esk.EINVAL
+
+
+def test_binding_rejects_bad_tensors():
+    """The binding checks every tensor it hands to the library (dtype, shape,
+    contiguity, device) before the call: a half-precision TF, a strided
+    buffer, an undersized or host-resident image would otherwise reach the
+    kernels as a wrong or wild pointer."""
+    torch = pytest.importorskip("torch")
+    ctx = esk.Context(-1)
+    tf32 = torch.zeros((256, 4), dtype=torch.float32)
+    with pytest.raises(TypeError):
+        ctx.set_tf(tf32.half())                                   # 8 bytes per entry, not 16
+    with pytest.raises(TypeError):
+        ctx.set_tf(tf32.double())
+    with pytest.raises(ValueError):
+        ctx.set_tf(torch.zeros((4, 256), dtype=torch.float32).t())  # [256, 4] but strided
+    with pytest.raises(ValueError):
+        ctx.set_tf(torch.zeros((256, 3), dtype=torch.float32))
+    with pytest.raises(ValueError):
+        ctx.set_tf(tf32)                                          # host memory
+    vol = torch.zeros((8, 8, 8), dtype=torch.uint8)
+    with pytest.raises(ValueError):
+        ctx.set_volume(vol, 8)                                    # host memory
+    with pytest.raises(ValueError):
+        ctx.set_volume(torch.zeros((8, 8, 16), dtype=torch.uint8)[:, :, ::2], 8)
+    with pytest.raises(TypeError):
+        ctx.set_volume(torch.zeros((8, 8, 8), dtype=torch.int32), 8)
+    cam = dict(ortho=0, eye=[0, 0, -10], dir00=[0, 0, 1], du=[0.01, 0, 0], dv=[0, -0.01, 0])
+    with pytest.raises(ValueError):
+        ctx.render(cam, 16, 8, out=torch.zeros((8, 16, 4), dtype=torch.float32))      # host memory
+    with pytest.raises(ValueError):
+        ctx.render(cam, 16, 8, out=torch.zeros((8, 15, 4), dtype=torch.float32))      # too small
+    with pytest.raises(TypeError):
+        ctx.render(cam, 16, 8, out=torch.zeros((8, 16, 4), dtype=torch.float16))
+    # the counts check (int32 [H, W]) is the same helper
+    with pytest.raises(TypeError):
+        esk._require(torch.zeros((8, 16), dtype=torch.int64), "counts", 0, torch.int32, (8, 16))
+    with pytest.raises(ValueError):
+        esk._require(torch.zeros((8, 17), dtype=torch.int32), "counts", 0, torch.int32, (8, 16))
+    ctx.close()

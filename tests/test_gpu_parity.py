@@ -15,7 +15,13 @@ import synth
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-3
-KD_VARIANTS = [(0, 0), (1, 0), (1, 32), (1, 128)]
+# (halting, max leaf size, bins): the paper's 4 bins for every halting
+# rule, and the other bin counts the ABI accepts
+KD_VARIANTS = [(0, 0, 4), (1, 0, 4), (1, 32, 4), (1, 128, 4), (1, 0, 2), (0, 0, 3), (1, 32, 8), (1, 0, 16)]
+
+
+def kd_bins(kd):
+    return kd[2] if len(kd) > 2 else 4
 
 
 def _torch():
@@ -72,7 +78,7 @@ def check_hierarchies(ctx, vol, tf, B, lo=0.0, hi=1.0, kd=(1, 0), label=""):
     assert st["n_nonempty"] == ids.size, label
     assert st["lbvh_height"] == t["height"], label
     assert st["lbvh_nodes"] == (2 * ids.size - 1 if ids.size else 0)
-    k = oracle.kd(flags, B, dims, kd[0], kd[1])
+    k = oracle.kd(flags, B, dims, kd[0], kd[1], kd_bins(kd))
     for name in ("lo", "hi", "axis", "plane"):
         assert np.array_equal(ctx.export("kd_" + name), k[name]), (label, name)
     assert np.array_equal(ctx.export("kd_first"), k["first_child"]), label
@@ -86,7 +92,7 @@ def run_case(vol, tf, B, lo=0.0, hi=1.0, kd=(1, 0), label=""):
     dv = to_dev(vol)
     dtf = to_dev(tf)
     ctx.set_volume(dv, B, (lo, hi), max_tf=max(256, tf.shape[0]))
-    ctx.set_tf(dtf, build=("grid", "lbvh", "kd"), kd=esk.Kd(kd[0], kd[1], 4))
+    ctx.set_tf(dtf, build=("grid", "lbvh", "kd"), kd=esk.Kd(kd[0], kd[1], kd_bins(kd)))
     torch.cuda.synchronize()
     flags = check_hierarchies(ctx, vol, tf, B, lo, hi, kd, label)
     return esk, ctx, flags, dv, dtf
@@ -216,6 +222,27 @@ def test_degenerate_occupancies():
         only[200:, :] = [1.0, 0.5, 0.25, 0.9]
         esk, ctx, flags, _, _ = run_case(v, only, 32, label=f"spots {spots}")
         check_images(ctx, v, only, cam, 48, 40, flags, 32, label=f"spots {spots}")
+
+
+def test_tf_alpha_out_of_range():
+    """Opacities outside [0, 1] and NaN are read clamped (NaN as 0) by every
+    step: hierarchies exact, images within tolerance of the oracle's and
+    every skipping mode equal to the full march."""
+    dims = (41, 37, 30)
+    vol = synth.blobs_u8(dims, seed=12, n_blobs=6, cut=40)
+    tf = synth.tf_random(21, 256)
+    a = tf[:, 3].copy()
+    a[40:60] = -0.3
+    a[90:95] = np.nan
+    a[150:170] = 1.8
+    a[200:203] = np.inf
+    tf[:, 3] = a
+    log("case: TF alpha with negative, NaN, > 1 and inf entries")
+    esk, ctx, flags, _, _ = run_case(vol, tf, 8, label="alpha clamp")
+    assert 0 < flags.mean() < 1
+    cam = synth.perspective(dims, 56, 48, synth.view_direction(13))
+    imgs = check_images(ctx, vol, tf, cam, 56, 48, flags, 8, label="alpha clamp")
+    assert np.isfinite(imgs["none"]).all()
 
 
 def test_menger_sponge_kd_root_only():

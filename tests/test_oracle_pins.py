@@ -93,6 +93,28 @@ def test_tf_prefix_ramp_closed_form():
         assert P[i] == max(0, i - 77)
 
 
+def test_tf_alpha_read_clamped():
+    # an opacity outside [0, 1] is read clamped, NaN as 0: the prefix count
+    # sees NaN and -0.5 as invisible and 1.7 as visible
+    tf = np.zeros((5, 4), np.float32)
+    tf[:, 3] = [np.nan, -0.5, 1.7, 0.0, 0.3]
+    assert list(oracle.tf_prefix(tf)) == [0, 0, 0, 1, 1, 2]
+    # constant volume, every entry with alpha 1.7: the first sample is opaque
+    # (1 - (1 - 1)^(dt/ref) = 1), so every hit pixel is exactly (rgb, 1)
+    nx, ny, nz = 8, 6, 10
+    vol = np.full((nz, ny, nx), 90, np.uint8)
+    cam = _axis_camera(nx, ny)
+    tf = np.zeros((256, 4), np.float32)
+    tf[:] = [0.25, 0.5, 0.75, 1.7]
+    img = oracle.render(vol, tf, cam, nx, ny, dt=0.5, ref=1.0)
+    assert np.all(img == np.array([0.25, 0.5, 0.75, 1.0]))
+    # negative or NaN opacity everywhere: nothing is visible
+    for bad in (-0.5, np.nan):
+        tf[:, 3] = bad
+        assert np.all(oracle.render(vol, tf, cam, nx, ny) == 0.0)
+        assert np.all(oracle.sample(vol, tf, [[2.5, 2.5, 2.5]])[:, 3] == 0.0)
+
+
 def test_classify_tf_extremes():
     vol = synth.blobs_u8((40, 24, 33), seed=4)
     mn, mx = oracle.brick_minmax(vol, 8)
@@ -330,17 +352,71 @@ def test_render_tight_boxes_equal_full_march(seed):
     assert np.all(c2 <= c1) and np.all(c1 <= c0) and c2.sum() < c1.sum()
 
 
+@pytest.mark.parametrize("entry,flagged", [(2, 0), (3, 1), (4, 1), (6, 1), (7, 0)])
+def test_classify_u16_index_window_exact(entry, flagged):
+    # u16, N = 256: x(v) = v * 255 / 65535 = v / 257, so the constant value
+    # 1028 sits exactly on entry 4 and the window is [4 - 1, 4 + 2] = [3, 6].
+    # (A single-precision 1028 * (1/65535) * 255 rounds to 3.9999998, which
+    # would shift the window to [2, 5].)
+    vol = np.full((12, 12, 12), 1028, np.uint16)
+    mn, mx = oracle.brick_minmax(vol, 8)
+    tf = np.zeros((256, 4), np.float32)
+    tf[entry, 3] = 0.5
+    assert np.all(oracle.classify(mn, mx, vol.dtype, tf) == flagged)
+
+
+@pytest.mark.parametrize("N,entry,flagged", [(256, 114, 0), (256, 115, 1), (256, 118, 1), (256, 119, 0),
+                                             (1000, 455, 0), (1000, 456, 1), (1000, 459, 1), (1000, 460, 0)])
+def test_classify_u16_index_window_fraction(N, entry, flagged):
+    # u16 value 30000: x = 30000 * 255 / 65535 = 116.73 (window [115, 118]);
+    # with N = 1000, x = 30000 * 999 / 65535 = 457.31 (window [456, 459])
+    vol = np.full((10, 9, 11), 30000, np.uint16)
+    mn, mx = oracle.brick_minmax(vol, 8)
+    tf = np.zeros((N, 4), np.float32)
+    tf[entry, 3] = 0.25
+    assert np.all(oracle.classify(mn, mx, vol.dtype, tf) == flagged)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float16])
+@pytest.mark.parametrize("value,visible", [
+    (0.5, {126: 1, 129: 1, 125: 0, 130: 0}),     # s = (0.5 + 2) / 5 = 0.5, x = 127.5: window [126, 129]
+    (3.7, {254: 1, 255: 1, 253: 0}),             # above hi: s = 1, x = 255: window [254, 255]
+    (-2.5, {0: 1, 2: 1, 3: 0}),                  # below lo: s = 0, x = 0: window [0, 2]
+    (-1.0, {50: 1, 53: 1, 49: 0, 54: 0}),        # s = 0.2, x = 51 (0.2f * 255 rounds to 51): window [50, 53]
+])
+def test_classify_float_value_range(dtype, value, visible):
+    # f16/f32 volumes are normalised by s = clamp((v - lo) / (hi - lo), 0, 1)
+    # with the value range [lo, hi] = [-2, 3]: dividing by hi instead of
+    # hi - lo, or adding lo, moves every window above
+    vol = np.full((9, 10, 11), value, dtype)
+    mn, mx = oracle.brick_minmax(vol, 8)
+    for entry, flagged in visible.items():
+        tf = np.zeros((256, 4), np.float32)
+        tf[entry, 3] = 0.5
+        got = oracle.classify(mn, mx, vol.dtype, tf, -2.0, 3.0)
+        assert np.all(got == flagged), (value, entry)
+
+
 @pytest.mark.parametrize("seed", [0, 1, 2])
-@pytest.mark.parametrize("dtype", [np.uint8, np.float32, np.float16])
-def test_classify_conservative_dense_sampling(seed, dtype):
+@pytest.mark.parametrize("dtype,vrange", [(np.uint8, None), (np.uint16, None), (np.float32, (0.0, 1.0)),
+                                          (np.float16, (0.0, 1.0)), (np.float32, (-2.0, 3.0)),
+                                          (np.float16, (-2.0, 3.0))])
+def test_classify_conservative_dense_sampling(seed, dtype, vrange):
     # every sample point owned by an unflagged brick must have alpha exactly 0
     dims = (35, 27, 30)
     B = 8
     base = synth.blobs_u8(dims, seed=10 + seed, cut=40)
+    lo, hi = vrange if vrange else (0.0, 1.0)
     if dtype == np.uint8:
-        vol, lo, hi = base, 0.0, 1.0
+        vol = base
+    elif dtype == np.uint16:
+        # spread over the whole u16 range, with values between the multiples of 257
+        vol = (base.astype(np.uint32) * 257 + (base.astype(np.uint32) * 97) % 257).clip(0, 65535).astype(np.uint16)
+    elif lo == 0.0:
+        vol = (base.astype(np.float64) / 255.0).astype(dtype)
     else:
-        vol, lo, hi = (base.astype(np.float64) / 255.0).astype(dtype), 0.0, 1.0
+        # [-2.5, 3.5]: values below lo and above hi clamp to the TF's ends
+        vol = (base.astype(np.float64) / 255.0 * 6.0 - 2.5).astype(dtype)
     tf = synth.tf_random(seed, 256)
     mn, mx = oracle.brick_minmax(vol, B)
     flags = oracle.classify(mn, mx, vol.dtype, tf, lo, hi)
@@ -665,14 +741,35 @@ def check_kd(t, flags, B, dims, halting, max_leaf, bins=4):
     assert np.all(np.diff(depth) >= 0)
 
 
+@pytest.mark.parametrize("bins", [2, 3, 4, 8, 16])
 @pytest.mark.parametrize("halting,max_leaf", [(0, 0), (1, 0), (1, 32), (1, 128)])
 @pytest.mark.parametrize("seed,dims,B", [(0, (64, 64, 64), 8), (1, (50, 37, 61), 8), (2, (96, 96, 64), 16)])
-def test_kd_rules(seed, dims, B, halting, max_leaf):
+def test_kd_rules(seed, dims, B, halting, max_leaf, bins):
     vol = synth.blobs_u8(dims, seed=30 + seed, n_blobs=7)
     mn, mx = oracle.brick_minmax(vol, B)
     flags = oracle.classify(mn, mx, vol.dtype, synth.tf_ramp(256, start=0.3))
-    t = oracle.kd(flags, B, dims, halting, max_leaf)
-    check_kd(t, flags, B, dims, halting, max_leaf)
+    t = oracle.kd(flags, B, dims, halting, max_leaf, bins)
+    check_kd(t, flags, B, dims, halting, max_leaf, bins)
+
+
+@pytest.mark.parametrize("bins,split", [(2, False), (3, False), (4, False), (8, True), (16, True)])
+def test_kd_bins_closed_form(bins, split):
+    # 16 x 2 x 2 bricks, all non-empty except the slab x = 2.  Only a plane at
+    # x = 2 or 3 separates the two solid parts (cost 8 + 52 brick volumes
+    # against the root's 64); every other plane, on any axis, costs exactly
+    # the root's volume.  Candidate planes on the x axis are lo + floor(j*16/bins):
+    # bins 2 -> {8}, 3 -> {5, 10}, 4 -> {4, 8, 12}: no split; bins 8 -> {2, 4, ...}
+    # and 16 -> {1, 2, 3, ...}: split at 2 (the smaller plane of the tie 2 / 3)
+    f = np.ones((2, 2, 16), np.uint8)       # [z][y][x]
+    f[:, :, 2] = 0
+    t = oracle.kd(f.reshape(-1), 8, (128, 16, 16), 1, 0, bins)
+    if not split:
+        assert len(t["axis"]) == 1 and t["axis"][0] == -1
+        return
+    assert len(t["axis"]) == 3 and t["height"] == 2
+    assert t["axis"][0] == 0 and t["plane"][0] == 2 and t["first_child"][0] == 1
+    assert list(t["lo"][1]) == [0, 0, 0] and list(t["hi"][1]) == [2, 2, 2]
+    assert list(t["lo"][2]) == [3, 0, 0] and list(t["hi"][2]) == [16, 2, 2]
 
 
 def test_kd_menger_root_only():
