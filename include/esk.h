@@ -26,7 +26,9 @@
  *  - Images are H x W x RGBA float32, row 0 at the top, premultiplied colour.
  *  - Device pointers are HIP device addresses on the context's device.  All
  *    device memory is owned by the caller; the library borrows it and never
- *    allocates device memory.  Host pointers are plain host memory.
+ *    allocates device memory (its one static device array, the argument
+ *    staging of esk_render_batch_noalloc, is part of its code object).  Host
+ *    pointers are plain host memory.
  *
  * Errors: every entry point returns an esk_status.  Arguments are validated on
  * the host before any device work is enqueued; a rejected call changes no
@@ -229,6 +231,25 @@ esk_status esk_render_batch_bytes(int n, size_t *out);
 esk_status esk_render_batch(esk_ctx *const *ctxs, int n, int accel, const esk_camera *cams, const int *widths,
                             const int *heights, float step, float opacity_ref_step, float *const *d_outs,
                             void *d_args, size_t args_bytes);
+
+/* Allocation-free batched rendering, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): esk_render_batch without the caller's argument buffer.  The
+ * per-request arguments go to a static device array inside the library, one
+ * per device, of at most 1024 requests (n above that returns ESK_ELIMIT and
+ * enqueues nothing); the call allocates nothing (no device, host or pinned
+ * memory): the array's device address, a pinned host staging of the same
+ * size and an upload event are set up once per device by the first
+ * esk_create on it and held until the process ends.  Validation, semantics
+ * and results are exactly those of esk_render_batch (bit-identical images).
+ * Every call on a device shares that device's array and staging, which keep
+ * the last call's arguments: successive calls must be ordered on one stream
+ * (or the caller waits for the previous batch to finish); calls that overlap
+ * on one device -- from several host threads, or on different streams while
+ * an earlier batch may still read its arguments -- race. */
+esk_status esk_render_batch_noalloc(esk_ctx *const *ctxs, int n, int accel, const esk_camera *cams,
+                                    const int *widths, const int *heights, float step, float opacity_ref_step,
+                                    float *const *d_outs);
 
 /* Waits for the context's stream; reports device faults. */
 esk_status esk_sync(esk_ctx *ctx);

@@ -105,9 +105,11 @@ def lib() -> ctypes.CDLL:
     L.esk_render_batch_bytes.argtypes = [i32, ctypes.POINTER(sz)]
     L.esk_render_batch.argtypes = [ctypes.POINTER(P), i32, i32, ctypes.POINTER(Camera), ctypes.POINTER(i32),
                                    ctypes.POINTER(i32), f32, f32, ctypes.POINTER(P), P, sz]
+    L.esk_render_batch_noalloc.argtypes = [ctypes.POINTER(P), i32, i32, ctypes.POINTER(Camera),
+                                           ctypes.POINTER(i32), ctypes.POINTER(i32), f32, f32, ctypes.POINTER(P)]
     for name in ("esk_create", "esk_destroy", "esk_workspace_bytes", "esk_set_volume",
                  "esk_set_transfer_function", "esk_render", "esk_sync", "esk_get_stats", "esk_export",
-                 "esk_render_batch_bytes", "esk_render_batch"):
+                 "esk_render_batch_bytes", "esk_render_batch", "esk_render_batch_noalloc"):
         getattr(L, name).restype = i32
     _lib = L
     return L

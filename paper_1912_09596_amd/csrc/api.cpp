@@ -284,6 +284,8 @@ esk_status esk_create(int device, void *hip_stream, esk_ctx **out)
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);  // default priority
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_kd, hipEventDisableTiming);
+        // once per device: the address of the allocation-free batch's argument array
+        if (e == hipSuccess) e = noalloc_init(device);
         if (e != hipSuccess) {
             esk_destroy(c);
             return ESK_EDEVICE;
@@ -652,24 +654,79 @@ esk_status esk_render_batch_bytes(int n, size_t *out)
     return ESK_OK;
 }
 
-esk_status esk_render_batch(esk_ctx *const *ctxs, int n, int accel, const esk_camera *cams, const int *widths,
-                            const int *heights, float step, float opacity_ref_step, float *const *d_outs,
-                            void *d_args, size_t args_bytes)
+}  // extern "C"
+
+// Validates a batch, fills `staging` (host, n entries) with the per-request
+// arguments, uploads them to d_args on ctxs[0]'s stream (recording `done`
+// after the copy) and launches the batched render.  `wait` is called before
+// the staging is overwritten (the previous upload from it must be complete).
+template <typename Wait>
+static esk_status batch_launch(esk_ctx *c0, esk_ctx *const *ctxs, int n, int accel, const esk_camera *cams,
+                               const int *widths, const int *heights, float step, float opacity_ref_step,
+                               float *const *d_outs, RenderArgs *staging, RenderArgs *d_args, hipEvent_t done,
+                               Wait wait)
 {
-    if (!ctxs || n < 1 || n > 65535 || !ctxs[0]) return ESK_EINVAL;
-    esk_ctx *c0 = ctxs[0];
+    esk_status st = wait();
+    if (st != ESK_OK) return st;
+    size_t lds = 0;
+    bool narrow = true, tfl = true;
+    int tx = 1, ty = 1;
+    for (int i = 0; i < n; ++i) {
+        RenderArgs &r = staging[i];
+        st = prepare_render(ctxs[i], accel, &cams[i], widths[i], heights[i], step, opacity_ref_step, d_outs[i],
+                            nullptr, r);
+        if (st != ESK_OK) {
+            if (ctxs[i] != c0) fail(c0, st, "request %d: %s", i, ctxs[i]->err.c_str());
+            return st;
+        }
+        const int64_t nbytes = swz_bytes(r.vol.nq, elem_size(r.vol.dtype));
+        narrow = narrow && nbytes < (int64_t)0xffffffffLL;
+        tfl = tfl && r.N <= 1024;
+        tx = std::max(tx, (r.W + render_tile_for(accel) - 1) / render_tile_for(accel));
+        ty = std::max(ty, (r.H + render_tile_for(accel) - 1) / render_tile_for(accel));
+    }
+    for (int i = 0; i < n; ++i) {
+        const RenderArgs &r = staging[i];
+        lds = std::max(lds, render_lds_bytes(accel, r.N, tfl, r.stack_cap));
+    }
+    hipError_t e = hipSetDevice(c0->device);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_args, staging, (size_t)n * sizeof(RenderArgs), hipMemcpyHostToDevice, c0->stream);
+    if (e == hipSuccess) e = hipEventRecord(done, c0->stream);
+    if (e == hipSuccess)
+        e = launch_render_batch(accel, c0->vol.dtype, d_args, n, tx, ty, lds, narrow, tfl, c0->stream);
+    return hip_check(c0, e, "batched render launch");
+}
+
+// the checks shared by both batched entry points (the request arrays)
+static esk_status batch_check(esk_ctx *c0, esk_ctx *const *ctxs, int n, const esk_camera *cams, const int *widths,
+                              const int *heights, float *const *d_outs)
+{
     if (!cams || !widths || !heights || !d_outs) return fail(c0, ESK_EINVAL, "null request array");
-    if (!d_args || (reinterpret_cast<uintptr_t>(d_args) & 15) != 0)
-        return fail(c0, ESK_EINVAL, "argument buffer must be non-null and 16-byte aligned");
-    if (args_bytes < (size_t)n * sizeof(RenderArgs))
-        return fail(c0, ESK_ENOSPC, "argument buffer has %zu bytes, needs %zu", args_bytes,
-                    (size_t)n * sizeof(RenderArgs));
     for (int i = 0; i < n; ++i) {
         if (!ctxs[i]) return fail(c0, ESK_EINVAL, "request %d has no context", i);
         if (ctxs[i]->device != c0->device) return fail(c0, ESK_EINVAL, "request %d is on another device", i);
         if (ctxs[i]->has_volume && c0->has_volume && ctxs[i]->vol.dtype != c0->vol.dtype)
             return fail(c0, ESK_EINVAL, "request %d has another volume dtype", i);
     }
+    return ESK_OK;
+}
+
+extern "C" {
+
+esk_status esk_render_batch(esk_ctx *const *ctxs, int n, int accel, const esk_camera *cams, const int *widths,
+                            const int *heights, float step, float opacity_ref_step, float *const *d_outs,
+                            void *d_args, size_t args_bytes)
+{
+    if (!ctxs || n < 1 || n > 65535 || !ctxs[0]) return ESK_EINVAL;
+    esk_ctx *c0 = ctxs[0];
+    if (!d_args || (reinterpret_cast<uintptr_t>(d_args) & 15) != 0)
+        return fail(c0, ESK_EINVAL, "argument buffer must be non-null and 16-byte aligned");
+    if (args_bytes < (size_t)n * sizeof(RenderArgs))
+        return fail(c0, ESK_ENOSPC, "argument buffer has %zu bytes, needs %zu", args_bytes,
+                    (size_t)n * sizeof(RenderArgs));
+    esk_status st = batch_check(c0, ctxs, n, cams, widths, heights, d_outs);
+    if (st != ESK_OK) return st;
     if (c0->device < 0) return fail(c0, ESK_ESTATE, "validation-only context");
     if (c0->staging_cap < n) {
         if (c0->staging_done) (void)hipEventSynchronize(c0->staging_done);
@@ -684,37 +741,33 @@ esk_status esk_render_batch(esk_ctx *const *ctxs, int n, int accel, const esk_ca
         hipError_t e = hipEventCreateWithFlags(&c0->staging_done, hipEventDisableTiming);
         if (e != hipSuccess) return hip_check(c0, e, "event creation");
     }
-    hipError_t e = hipEventSynchronize(c0->staging_done);  // previous upload finished with the buffer
-    if (e != hipSuccess) return hip_check(c0, e, "staging wait");
-    size_t lds = 0;
-    bool narrow = true, tfl = true;
-    int tx = 1, ty = 1;
-    for (int i = 0; i < n; ++i) {
-        RenderArgs &r = c0->staging[i];
-        esk_status st = prepare_render(ctxs[i], accel, &cams[i], widths[i], heights[i], step, opacity_ref_step,
-                                       d_outs[i], nullptr, r);
-        if (st != ESK_OK) {
-            if (ctxs[i] != c0) fail(c0, st, "request %d: %s", i, ctxs[i]->err.c_str());
-            return st;
-        }
-        const int64_t nbytes = swz_bytes(r.vol.nq, elem_size(r.vol.dtype));
-        narrow = narrow && nbytes < (int64_t)0xffffffffLL;
-        tfl = tfl && r.N <= 1024;
-        tx = std::max(tx, (r.W + render_tile_for(accel) - 1) / render_tile_for(accel));
-        ty = std::max(ty, (r.H + render_tile_for(accel) - 1) / render_tile_for(accel));
-    }
-    for (int i = 0; i < n; ++i) {
-        const RenderArgs &r = c0->staging[i];
-        lds = std::max(lds, (tfl ? (size_t)r.N * 16 : 0) + (size_t)r.stack_cap * render_threads_for(accel) * sizeof(int));
-    }
-    e = hipSetDevice(c0->device);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(d_args, c0->staging, (size_t)n * sizeof(RenderArgs), hipMemcpyHostToDevice, c0->stream);
-    if (e == hipSuccess) e = hipEventRecord(c0->staging_done, c0->stream);
-    if (e == hipSuccess)
-        e = launch_render_batch(accel, c0->vol.dtype, static_cast<const RenderArgs *>(d_args), n, tx, ty, lds,
-                                narrow, tfl, c0->stream);
-    return hip_check(c0, e, "batched render launch");
+    return batch_launch(c0, ctxs, n, accel, cams, widths, heights, step, opacity_ref_step, d_outs, c0->staging,
+                        static_cast<RenderArgs *>(d_args), c0->staging_done, [&]() {
+                            // the previous upload has finished with the staging
+                            return hip_check(c0, hipEventSynchronize(c0->staging_done), "staging wait");
+                        });
+}
+
+esk_status esk_render_batch_noalloc(esk_ctx *const *ctxs, int n, int accel, const esk_camera *cams,
+                                    const int *widths, const int *heights, float step, float opacity_ref_step,
+                                    float *const *d_outs)
+{
+    if (!ctxs || n < 1 || !ctxs[0]) return ESK_EINVAL;
+    esk_ctx *c0 = ctxs[0];
+    if (n > kNoAllocBatchMax)
+        return fail(c0, ESK_ELIMIT, "%d requests exceed the %d of the allocation-free batch", n, kNoAllocBatchMax);
+    esk_status st = batch_check(c0, ctxs, n, cams, widths, heights, d_outs);
+    if (st != ESK_OK) return st;
+    if (c0->device < 0) return fail(c0, ESK_ESTATE, "validation-only context");
+    NoAllocSlot *slot = noalloc_slot(c0->device);
+    if (!slot) return fail(c0, ESK_EDEVICE, "argument array of device %d is not set up", c0->device);
+    st = batch_launch(c0, ctxs, n, accel, cams, widths, heights, step, opacity_ref_step, d_outs, slot->h_staging,
+                      slot->d_args, slot->done, [&]() {
+                          if (!slot->recorded) return ESK_OK;
+                          return hip_check(c0, hipEventSynchronize(slot->done), "staging wait");
+                      });
+    if (st == ESK_OK) slot->recorded = true;
+    return st;
 }
 
 esk_status esk_sync(esk_ctx *c)

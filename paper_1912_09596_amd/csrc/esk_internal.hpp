@@ -185,7 +185,29 @@ __host__ __device__ constexpr int render_threads_for(int accel)
     return (render_tile_for(accel) / 8) * (render_tile_for(accel) / 8) * 64;
 }
 
+// dynamic LDS of one render workgroup: [TF (N <= 1024)][traversal stack]
+__host__ __device__ constexpr size_t render_lds_bytes(int accel, int N, bool tf_lds, int stack_cap)
+{
+    return (tf_lds ? (size_t)N * 16 : 0) + (size_t)stack_cap * render_threads_for(accel) * sizeof(int);
+}
+
 hipError_t launch_render(int accel, const RenderArgs &r, hipStream_t s);
+
+// Allocation-free batched rendering: the per-request arguments live in a
+// static device array of kNoAllocBatchMax entries (one per device, shared by
+// every call on it); noalloc_init resolves its address (with `device`
+// current) and allocates the pinned host staging and the upload event once
+// per device; noalloc_slot returns the slot, or null before a successful init.
+constexpr int kNoAllocBatchMax = 1024;
+struct NoAllocSlot {
+    RenderArgs *d_args = nullptr;     // device address of the static array
+    RenderArgs *h_staging = nullptr;  // pinned host staging of the same size
+    hipEvent_t done = nullptr;        // recorded after the last upload from h_staging
+    bool recorded = false;
+};
+hipError_t noalloc_init(int device);
+NoAllocSlot *noalloc_slot(int device);
+
 // n requests of one accel and volume dtype; d_args: n RenderArgs in device memory
 hipError_t launch_render_batch(int accel, int dtype, const RenderArgs *d_args, int n, int tiles_x, int tiles_y,
                                size_t lds, bool narrow, bool tfl, hipStream_t s);

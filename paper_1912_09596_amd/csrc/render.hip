@@ -725,8 +725,7 @@ hipError_t launch_accel(const RenderArgs &r, hipStream_t s)
 {
     constexpr int tile = render_tile_for(ACCEL);
     const dim3 grid((r.W + tile - 1) / tile, (r.H + tile - 1) / tile);
-    const size_t lds = (r.N <= 1024 ? (size_t)r.N * sizeof(float4) : 0) +
-                       (size_t)r.stack_cap * render_threads_for(ACCEL) * sizeof(int);
+    const size_t lds = render_lds_bytes(ACCEL, r.N, r.N <= 1024, r.stack_cap);
     const int64_t nbytes = swz_bytes(r.vol.nq, (int)sizeof(T));
     const bool narrow = nbytes < (int64_t)0xffffffffLL;
     const bool tfl = r.N <= 1024;

@@ -129,6 +129,36 @@ def test_tf_and_render_validation():
     v.close()
 
 
+def test_batch_validation_without_a_device():
+    """Both batched entry points check the request arrays and their limits on
+    the host; the allocation-free one refuses more than 1024 requests."""
+    v = _VCtx()
+    L = v.L
+    cam = esk.camera_struct(dict(ortho=0, eye=[0, 0, -10], dir00=[0, 0, 1], du=[0.01, 0, 0], dv=[0, -0.01, 0]))
+    n = 2
+    ctxs = (ctypes.c_void_p * n)(v.c.value, v.c.value)
+    cams = (esk.Camera * n)(cam, cam)
+    ws = (ctypes.c_int * n)(64, 64)
+    hs = (ctypes.c_int * n)(64, 64)
+    outs = (ctypes.c_void_p * n)(FAKE.value, FAKE.value)
+    na = L.esk_render_batch_noalloc
+    assert na(None, n, esk.LBVH, cams, ws, hs, 0.5, 1.0, outs) == esk.EINVAL
+    assert na(ctxs, 0, esk.LBVH, cams, ws, hs, 0.5, 1.0, outs) == esk.EINVAL
+    assert na(ctxs, n, esk.LBVH, None, ws, hs, 0.5, 1.0, outs) == esk.EINVAL
+    assert na(ctxs, n, esk.LBVH, cams, ws, hs, 0.5, 1.0, None) == esk.EINVAL
+    big = 1025
+    bctx = (ctypes.c_void_p * big)(*([v.c.value] * big))
+    bcam = (esk.Camera * big)(*([cam] * big))
+    bw = (ctypes.c_int * big)(*([64] * big))
+    bout = (ctypes.c_void_p * big)(*([FAKE.value] * big))
+    assert na(bctx, big, esk.LBVH, bcam, bw, bw, 0.5, 1.0, bout) == esk.ELIMIT
+    assert "1024" in v.err()
+    assert na(ctxs, n, esk.LBVH, cams, ws, hs, 0.5, 1.0, outs) == esk.ESTATE
+    assert L.esk_render_batch(ctxs, n, esk.LBVH, cams, ws, hs, 0.5, 1.0, outs, None, 0) == esk.EINVAL
+    assert L.esk_render_batch(ctxs, n, esk.LBVH, cams, ws, hs, 0.5, 1.0, outs, FAKE, 16) == esk.ENOSPC
+    v.close()
+
+
 def test_status_strings_and_null_handles():
     L = esk.lib()
     for s in (esk.OK, esk.EINVAL, esk.ENOSPC, esk.ELIMIT, esk.EDEVICE, esk.ESTATE, esk.EINTERNAL):
