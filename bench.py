@@ -69,37 +69,74 @@ def percentile(xs, q):
     return xs[i]
 
 
-def cpu_baseline(vol, tfs, steps=3, stride=1):
+def host_cpu():
+    """What the oracle runs on: logical CPUs, model, threads per core."""
+    info = {"nproc": os.cpu_count(), "model": None, "threads_per_core": None}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["model"] = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        siblings = open("/sys/devices/system/cpu/cpu0/topology/thread_siblings_list").read().strip()
+        n = 0
+        for part in siblings.split(","):
+            a, _, b = part.partition("-")
+            n += int(b) - int(a) + 1 if b else 1
+        info["threads_per_core"] = n
+    except (OSError, ValueError):
+        pass
+    return info
+
+
+def cpu_baseline(vol, tfs, steps=3, stride=1, single_stride=64):
     """The CPU oracle on this host: `steps` steps of the same workload (min/max,
     classification, LBVH, k-d, and the three renders as full-march FP64
-    images of every `stride`-th pixel of the 1080p frame)."""
+    images of every `stride`-th pixel of the 1080p frame) on all OpenMP
+    threads, then one step on one thread over every `single_stride`-th pixel."""
     import numpy as np
 
     import oracle
     import synth
 
-    threads = oracle.lib().orc_threads()
-    idx = np.arange(0, W * H, stride)
-    pix = np.stack([idx % W, idx // W], 1).astype(np.int32)
+    L = oracle.lib()
+    threads = L.orc_threads()
     nb = oracle.brick_grid(DIMS, BRICK)
-    rays = 0
-    t0 = time.perf_counter()
-    for j in range(steps):
-        tf, cam = tfs[j], synth.c2_camera(j)
-        mn, mx = oracle.brick_minmax(vol, BRICK)
-        flags = oracle.classify(mn, mx, vol.dtype, tf)
-        ids = oracle.compact(flags)
-        k, i = oracle.sort_pairs(oracle.morton_keys(ids, nb[0], nb[1]), ids)
-        oracle.lbvh(k, i, BRICK, DIMS)
-        oracle.kd(flags, BRICK, DIMS, KD["halting"], KD["max_leaf"], KD["bins"])
-        for _ in ACCELS:
-            oracle.render(vol, tf, cam, W, H, 0.5, 1.0, pixels=pix)
-            rays += pix.shape[0]
-    dt = time.perf_counter() - t0
+
+    def run(nsteps, pstride):
+        idx = np.arange(0, W * H, pstride)
+        pix = np.stack([idx % W, idx // W], 1).astype(np.int32)
+        rays = 0
+        t0 = time.perf_counter()
+        for j in range(nsteps):
+            tf, cam = tfs[j], synth.c2_camera(j)
+            mn, mx = oracle.brick_minmax(vol, BRICK)
+            flags = oracle.classify(mn, mx, vol.dtype, tf)
+            ids = oracle.compact(flags)
+            k, i = oracle.sort_pairs(oracle.morton_keys(ids, nb[0], nb[1]), ids)
+            oracle.lbvh(k, i, BRICK, DIMS)
+            oracle.kd(flags, BRICK, DIMS, KD["halting"], KD["max_leaf"], KD["bins"])
+            for _ in ACCELS:
+                oracle.render(vol, tf, cam, W, H, 0.5, 1.0, pixels=pix)
+                rays += pix.shape[0]
+        return rays, time.perf_counter() - t0, pix.shape[0]
+
+    rays, dt, npix = run(steps, stride)
+    L.orc_set_threads(1)
+    try:
+        rays1, dt1, npix1 = run(1, single_stride)
+    finally:
+        L.orc_set_threads(threads)
+    host = host_cpu()
     return {"value": rays / dt / 1e6, "unit": "Mrays/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{steps} steps of the same workload (min/max, classify, LBVH, k-d, three "
-                      f"full-march FP64 renders of {pix.shape[0]} of the 1920x1080 pixels each; "
-                      f"{rays} rays) in {dt:.1f} s"}
+                      f"full-march FP64 renders of {npix} of the 1920x1080 pixels each; "
+                      f"{rays} rays) in {dt:.1f} s on {threads} OpenMP threads",
+            "host": host,
+            "one_thread": {"value": rays1 / dt1 / 1e6, "unit": "Mrays/s",
+                           "sample": f"1 step, {npix1} pixels per render ({rays1} rays) in {dt1:.1f} s"}}
 
 
 def batched_vs_plain(esk, torch, count=64, reps=5):
@@ -403,6 +440,50 @@ def statistics_table(esk, torch, noise_vol, reps=3):
             st = ctx.stats()
             rec[f"kd_{vname}"] = {"nodes": st["kd_nodes"], "height": st["kd_height"], "rebuild_ms": ms}
         out[name] = rec
+        ctx.close()
+        del vol, ctx
+        torch.cuda.empty_cache()
+    return out
+
+
+def sort_paths(esk, torch, reps=5):
+    """The sorted Morton keys of the LBVH rebuild (Sec. 3.1) by LSD radix sort
+    on a lopsided brick grid (4096x256x128 u8, 8^3 bricks: 512x32x16 bricks,
+    code domain 2^27 >> 4x the brick count) next to the Morton enumeration on
+    a cube with the same brick count (512^3 u8, 64^3 bricks), both ~10 %
+    blob voxels.  Per case: grid rebuild (classification only) and LBVH
+    rebuild from enqueue to completion; their difference is the sorted keys,
+    the Karras nodes and the boxes."""
+    import numpy as np
+
+    import synth
+
+    tf = torch.from_numpy(synth.tf_ramp(256, start=0.02)).cuda()
+    cases = [("lopsided_4096x256x128_u8", (4096, 256, 128), 64, "radix sort"),
+             ("cube_512_u8", (512, 512, 512), 8, "Morton enumeration")]
+
+    def timed(ctx, build):
+        times = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            ctx.set_tf(tf, build=build)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t) * 1e3)
+        return round(statistics.median(times), 4)
+
+    out = {}
+    for name, dims, blobs, path in cases:
+        rng = np.random.default_rng(11)
+        vol = synth._blob_volume_torch(dims, blobs, 0.1, rng, "cuda", "u8")
+        ctx = esk.Context(0)
+        ctx.set_volume(vol, 8, (0.0, 1.0), max_tf=256)
+        g = timed(ctx, ("grid",))
+        lb = timed(ctx, ("lbvh",))
+        st = ctx.stats()
+        out[name] = {"dims": list(dims), "bricks": st["n_bricks"], "bricks_nonempty": st["n_nonempty"],
+                     "sorted_keys_by": path, "grid_rebuild_ms": g, "lbvh_rebuild_ms": lb,
+                     "keys_nodes_boxes_ms": round(lb - g, 4)}
         ctx.close()
         del vol, ctx
         torch.cuda.empty_cache()
@@ -796,6 +877,8 @@ def main():
     if not args.no_stats:
         log("node/height statistics")
         result["statistics"] = statistics_table(esk, torch, dvol)
+        log("sort paths (radix sort vs Morton enumeration)")
+        result["sort_paths"] = sort_paths(esk, torch)
     if not args.no_large:
         log("large volumes (1024^3 f32/f16, 2048^3 u16)")
         result["large_volumes"] = large_volumes(esk, torch)

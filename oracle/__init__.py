@@ -86,6 +86,8 @@ def lib():
         _lib.orc_ray.argtypes = [ctypes.POINTER(Camera), i32, i32, P, P]
         _lib.orc_sample.argtypes = [P, i32, i32, i32, i32, f32, f32, P, i32, P, i64, P]
         _lib.orc_threads.argtypes = []
+        _lib.orc_set_threads.argtypes = [i32]
+        _lib.orc_set_threads.restype = None
     return _lib
 
 

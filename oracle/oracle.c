@@ -813,3 +813,13 @@ int orc_threads(void)
     return 1;
 #endif
 }
+
+/* sets the thread count of the OpenMP loops (n >= 1; for timing only) */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
