@@ -253,7 +253,6 @@ __device__ void eval_node(const KdArgs &k, SP S, int64_t node, int64_t begin, in
             for (int s = 0; s < 2; ++s)
                 for (int f = 0; f < 6; ++f) k.clo[12 * node + 6 * s + f] = cl[s][f];
         if (axis < 0) k.first[node] = -1;
-        __threadfence();  // the level's emitter may run on another XCD
     }
     wave_lds_sync();
 }
@@ -350,6 +349,10 @@ __global__ __launch_bounds__(256) void k_kd_level(KdArgs k)
          node += (int64_t)gridDim.x * 4) {
         eval_node(k, (const int32_t *)k.S, node, (int64_t)begin, vroot, tb[wave]);
     }
+    // the level's emitter may run on another XCD, whose L2 is not coherent
+    // with this one: every wave waits for its own stores to reach this XCD's
+    // L2, then one release per block (thread 0) writes them back
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
