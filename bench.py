@@ -31,7 +31,13 @@ ACCELS = ("grid", "lbvh", "kd")
 # formulas: lattice t 3, point 6, trilinear 30, normalise 5, TF lerp 13,
 # opacity correction 5, compositing 9)
 FLOP_PER_SAMPLE = 71
-PEAK_FP32_TFLOPS = 157.3
+# FP32 vector peak without packed math (the build turns packed FP32 off):
+# 256 CUs x 2.4 GHz x one wave64 VALU instruction per cycle per CU x 64
+# lanes x 2 FLOP per fused multiply-add
+PEAK_FP32_TFLOPS = 78.6
+# VALU issue peak: one wave64 instruction per cycle per CU
+PEAK_VALU_WAVE_INSTR_PER_S = 256 * 2.4e9
+ISSUE_FILE = os.path.join(ROOT, "profiles", "render_issue_noise512_1080p.md")
 ACCEL_CODE = {"grid": 1, "lbvh": 2, "kd": 4}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_noise512_1080p.md")
 RENDER_SRC = os.path.join(ROOT, "paper_1912_09596_amd", "csrc", "render.hip")
@@ -54,6 +60,30 @@ def measured_traffic(accel):
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
         if cells and cells[0] == key:
             return int(float(cells[-1]))
+    return None
+
+
+def measured_issue(accel):
+    """Per-launch counters of k_render<accel> (f32 volume) from the committed
+    SQ/TCC summary: VALU instructions, lane instructions per composited
+    sample, VALU issue and L2 figures; None when there is none or when the
+    render source has changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(ISSUE_FILE).read()
+        src = hashlib.sha256(open(RENDER_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if f"render.hip sha256: {src}" not in text:
+        return None
+    key = f"`k_render<{ACCEL_CODE[accel]}, float, unsigned int, true>`"
+    header = None
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if cells and cells[0] == "kernel":
+            header = cells
+        elif header and cells and cells[0] == key:
+            return {h: float(v) for h, v in zip(header[1:], cells[1:])}
     return None
 
 
@@ -95,7 +125,8 @@ def cpu_baseline(vol, tfs, steps=3, stride=1, single_stride=64):
     """The CPU oracle on this host: `steps` steps of the same workload (min/max,
     classification, LBVH, k-d, and the three renders as full-march FP64
     images of every `stride`-th pixel of the 1080p frame) on all OpenMP
-    threads, then one step on one thread over every `single_stride`-th pixel."""
+    threads; then one full-march render of every `single_stride`-th pixel
+    on one thread and on all."""
     import numpy as np
 
     import oracle
@@ -124,9 +155,21 @@ def cpu_baseline(vol, tfs, steps=3, stride=1, single_stride=64):
         return rays, time.perf_counter() - t0, pix.shape[0]
 
     rays, dt, npix = run(steps, stride)
+    # the full-march render alone on one thread and on all, over the same
+    # pixel subset (the per-step min/max and hierarchy builds left out)
+    idx = np.arange(0, W * H, single_stride)
+    pix1 = np.stack([idx % W, idx // W], 1).astype(np.int32)
+    tf0, cam0 = tfs[0], synth.c2_camera(0)
+
+    def render_rate():
+        t = time.perf_counter()
+        oracle.render(vol, tf0, cam0, W, H, 0.5, 1.0, pixels=pix1)
+        return pix1.shape[0] / (time.perf_counter() - t) / 1e6
+
+    r_all = render_rate()
     L.orc_set_threads(1)
     try:
-        rays1, dt1, npix1 = run(1, single_stride)
+        r_one = render_rate()
     finally:
         L.orc_set_threads(threads)
     host = host_cpu()
@@ -135,8 +178,9 @@ def cpu_baseline(vol, tfs, steps=3, stride=1, single_stride=64):
                       f"full-march FP64 renders of {npix} of the 1920x1080 pixels each; "
                       f"{rays} rays) in {dt:.1f} s on {threads} OpenMP threads",
             "host": host,
-            "one_thread": {"value": rays1 / dt1 / 1e6, "unit": "Mrays/s",
-                           "sample": f"1 step, {npix1} pixels per render ({rays1} rays) in {dt1:.1f} s"}}
+            "render_only": {"unit": "Mrays/s", "one_thread": round(r_one, 4), "all_threads": round(r_all, 4),
+                            "sample": f"one full-march FP64 render of every {single_stride}th pixel "
+                                      f"({pix1.shape[0]} rays), TF 0, camera 0"}}
 
 
 def batched_vs_plain(esk, torch, count=64, reps=5):
@@ -640,6 +684,94 @@ def counters_markdown(fetch_db, write_db, command):
     return "\n".join(out)
 
 
+ISSUE_COUNTERS_A = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_INSTS_VMEM_RD", "SQ_INSTS_LDS",
+                    "SQ_BUSY_CU_CYCLES", "SQ_WAVE_CYCLES", "SQ_WAIT_INST_ANY"]
+ISSUE_COUNTERS_B = ["TCC_REQ_sum", "TCC_HIT_sum", "TCC_MISS_sum", "TCP_TCC_READ_REQ_sum", "TA_BUSY_avr",
+                    "GRBM_GUI_ACTIVE"]
+
+
+def profile_frames(reps=3):
+    """The frame the render counters are taken on: the 512^3 noise volume
+    with TF 0 and camera 0, each structure rebuilt once and rendered `reps`
+    times at 1920x1080; prints the composited samples per structure."""
+    import torch
+
+    import paper_1912_09596_amd as esk
+    import synth
+
+    vol = synth.fractal_noise(DIMS, seed=2)
+    tf = torch.from_numpy(synth.c2_tfs(1)[0]).cuda()
+    cam = synth.c2_camera(0)
+    ctx = esk.Context(0)
+    ctx.set_volume(torch.from_numpy(vol).cuda(), BRICK, (0.0, 1.0), max_tf=256)
+    ctx.set_tf(tf, build=ACCELS, kd=esk.Kd(**KD))
+    out = torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
+    cnt = torch.empty((H, W), dtype=torch.int32, device="cuda")
+    samples = {}
+    for a in ACCELS + ("none",):
+        for _ in range(reps):
+            ctx.render(cam, W, H, accel=a, out=out)
+        ctx.render(cam, W, H, accel=a, out=out, counts=cnt)
+        samples[a] = int(cnt.sum().item())
+    torch.cuda.synchronize()
+    print(json.dumps({"frame": "512^3 noise, TF 0, camera 0, 1920x1080", "reps": reps, "samples": samples}))
+
+
+def issue_markdown(db_a, db_b, frames_json, command):
+    """Per-launch SQ / TCC / TA counters of the render kernels on the profiled
+    frame (two rocprofv3 --pmc runs of the same command), with the VALU
+    instructions per composited sample and the VALU issue rate."""
+    import collections
+    import hashlib
+    import sqlite3
+
+    def load(db):
+        c = sqlite3.connect(db)
+        per = collections.defaultdict(lambda: collections.defaultdict(list))
+        for k, n, v in c.execute("select kernel_name, counter_name, value from counters_collection"):
+            per[k][n].append(v)
+        return per
+
+    a, b = load(db_a), load(db_b)
+    frames = json.load(open(frames_json))
+    samples = frames["samples"]
+    code = {v: k for k, v in ACCEL_CODE.items()}
+    code[0] = "none"
+    src = hashlib.sha256(open(RENDER_SRC, "rb").read()).hexdigest()
+    out = ["# Render counters: 512^3 f32 noise volume, 1920x1080, TF 0 / camera 0", "",
+           "Commands (from the repository root on the MI355X box; one counter set per run):", "", "```",
+           command, "```", "", f"render.hip sha256: {src}", "",
+           f"Frame: {frames['frame']}; every kernel rendered it {frames['reps'] + 1} times per run and each "
+           "row averages those dispatches.  Composited samples per frame: " +
+           ", ".join(f"{k} {v}" for k, v in samples.items()) + ".  "
+           "`lane instr / sample` = SQ_INSTS_VALU x 64 / composited samples (for the skipping modes the "
+           "samples of non-empty bricks, the grid's count).  `kernel cycles` = GRBM_GUI_ACTIVE / 8 (the "
+           "counter adds up the 8 XCDs).  `VALU issue` = SQ_INSTS_VALU / (kernel cycles x 256 CUs): the "
+           "fraction of the one-wave64-VALU-instruction-per-cycle-per-CU rate the kernel reached.  "
+           "`L2 hit` = TCC_HIT / TCC_REQ.", "",
+           "| kernel | dispatches | waves | VALU instr | lane instr / sample | VALU issue | VMEM rd instr | "
+           "LDS instr | wait cycles | wave cycles | kernel cycles | L2 requests | L2 hit | TCP->L2 reads | "
+           "TA busy |",
+           "|---|" + "---:|" * 14]
+    for k in sorted(a):
+        if "k_render<" not in k or "float, unsigned int, true" not in k or k not in b:
+            continue
+        acc = int(_short_kernel(k).split("<")[1].split(",")[0])
+        m = {n: statistics.mean(v) for n, v in a[k].items()}
+        m.update({n: statistics.mean(v) for n, v in b[k].items()})
+        ns = samples["grid"] if acc != 0 else samples["none"]
+        lane = m["SQ_INSTS_VALU"] * 64 / ns
+        cycles = m["GRBM_GUI_ACTIVE"] / 8
+        issue = m["SQ_INSTS_VALU"] / (cycles * 256)
+        hit = m["TCC_HIT_sum"] / max(1.0, m["TCC_REQ_sum"])
+        out.append(f"| `{_short_kernel(k)[:70]}` | {len(a[k]['SQ_INSTS_VALU'])} | {m['SQ_WAVES']:.0f} | "
+                   f"{m['SQ_INSTS_VALU']:.0f} | {lane:.1f} | {issue:.3f} | {m['SQ_INSTS_VMEM_RD']:.0f} | "
+                   f"{m['SQ_INSTS_LDS']:.0f} | {m['SQ_WAIT_INST_ANY']:.0f} | {m['SQ_WAVE_CYCLES']:.0f} | "
+                   f"{cycles:.0f} | {m['TCC_REQ_sum']:.0f} | {hit:.3f} | "
+                   f"{m['TCP_TCC_READ_REQ_sum']:.0f} | {m['TA_BUSY_avr']:.0f} |")
+    return "\n".join(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -655,6 +787,10 @@ def main():
                     help="print the kernel-trace summary of a rocprofv3 database and exit")
     ap.add_argument("--counters-md", nargs=3, metavar=("FETCH_DB", "WRITE_DB", "COMMAND"),
                     help="print the HBM traffic summary of two rocprofv3 --pmc databases and exit")
+    ap.add_argument("--profile-frames", action="store_true",
+                    help="render the profiled frame with every structure (for rocprofv3 --pmc runs) and exit")
+    ap.add_argument("--issue-md", nargs=4, metavar=("DB_A", "DB_B", "FRAMES_JSON", "COMMAND"),
+                    help="print the render counter summary of two rocprofv3 --pmc databases and exit")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--cpu-stride", type=int, default=1)
     args = ap.parse_args()
@@ -663,6 +799,12 @@ def main():
         return
     if args.counters_md:
         print(counters_markdown(*args.counters_md))
+        return
+    if args.issue_md:
+        print(issue_markdown(*args.issue_md))
+        return
+    if args.profile_frames:
+        profile_frames()
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (run with --gpus 1)",
@@ -821,11 +963,20 @@ def main():
 
     mean_ms = {a: statistics.mean(render_ms[a]) for a in ACCELS}
     dominant = max(ACCELS, key=lambda a: mean_ms[a])
-    # algorithmic work: the samples of the non-empty bricks (what the grid
-    # composites); trees may also march some empty-brick samples, which do
-    # not count.  The same frame stands in for every step.
-    flops = samples["grid"] * FLOP_PER_SAMPLE
-    achieved = flops / (statistics.median(render_ms[dominant]) * 1e-3) / 1e12
+    # algorithmic work of every timed step's frame: the samples of its
+    # non-empty bricks (what the grid composites; trees may also march some
+    # empty-brick samples, which do not count), counted after the timing
+    step_samples = []
+    for i in range(args.steps):
+        j = (args.warmup + i) % 100
+        ctx.set_tf(dtfs[j], build=("grid",))
+        ctx.render(cams[j], W, H, accel="grid", out=outs["grid"], counts=cnt)
+        step_samples.append(int(cnt.sum().item()))
+    flops = sum(step_samples) * FLOP_PER_SAMPLE
+    achieved = flops / (sum(render_ms[dominant]) * 1e-3) / 1e12
+    issue = measured_issue(dominant)
+    # a1's algorithmic bytes: the volume read once, the bricks' min/max written
+    a1_bytes = nvox * 4 + 2 * st["n_bricks"] * 4
     result = {
         "metric": "Mrays/s at 1080p + rebuild ms per TF change; batched vs plain, RGBA err≤1e-3",
         "value": round(value, 2),
@@ -845,8 +996,10 @@ def main():
                    "image": [W, H], "brick": BRICK, "step_voxels": 0.5, "path": "plain"},
         "phases": {
             "set_volume_ms": round(statistics.median(sv), 4),
-            "set_volume_gb_per_s": {"achieved": round(sv_gbs, 1), "bytes": sv_bytes, "peak": 8000.0,
-                                    "measured_copy": round(copy_gbs, 1)},
+            "set_volume_gb_per_s": {"algorithmic": round(a1_bytes / (statistics.median(sv) * 1e-3) / 1e9, 1),
+                                    "algorithmic_bytes": a1_bytes,
+                                    "copy_inclusive": round(sv_gbs, 1), "copy_inclusive_bytes": sv_bytes,
+                                    "peak": 8000.0, "measured_copy": round(copy_gbs, 1)},
             "rebuild": {a: {k: round(v, 4) for k, v in rebuild[a].items()} for a in ACCELS},
             "render_ms": {a: round(statistics.median(render_ms[a]), 4) for a in ACCELS},
             "render_mrays_per_s": {a: round(W * H / statistics.median(render_ms[a]) / 1e3, 1)
@@ -863,7 +1016,16 @@ def main():
         },
         "roofline": {"kernel": f"k_render<{dominant}>", "bound": "alu", "achieved": round(achieved, 3),
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP32_TFLOPS, 5), "traffic": measured_traffic(dominant)},
+                     "frac": round(achieved / PEAK_FP32_TFLOPS, 5), "traffic": measured_traffic(dominant),
+                     "work": {"flop_per_sample": FLOP_PER_SAMPLE, "samples": sum(step_samples),
+                              "launches": args.steps, "ms": round(sum(render_ms[dominant]), 4)},
+                     "issue": None if issue is None else {
+                         "valu_wave_instr_per_launch": issue["VALU instr"],
+                         "lane_instr_per_sample": issue["lane instr / sample"],
+                         "valu_issue_frac": issue["VALU issue"],
+                         "peak_wave_instr_per_s": PEAK_VALU_WAVE_INSTR_PER_S,
+                         "l2_requests_per_launch": issue["L2 requests"], "l2_hit": issue["L2 hit"],
+                         "source": "profiles/render_issue_noise512_1080p.md"}},
     }
     log("small configuration (64^3 u8, 128x128)")
     result["small_config"] = small_config(esk, torch)
