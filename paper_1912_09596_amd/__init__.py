@@ -178,6 +178,14 @@ class Context:
         self._check(self._lib.esk_create(device, handle, ctypes.byref(self._ctx)))
         self._keep = {}
 
+    def _on_stream(self, t):
+        """A tensor allocated here on torch's current stream but used by the
+        library on the context's own stream: the caching allocator must not
+        hand its memory out again before that stream's work on it is done."""
+        import torch
+        if self.stream is not None and self.stream != torch.cuda.current_stream(self.device):
+            t.record_stream(self.stream)
+
     def _check(self, st):
         if st != OK:
             msg = self._lib.esk_last_error(self._ctx).decode() if self._ctx else ""
@@ -207,6 +215,7 @@ class Context:
         need = workspace_bytes((nx, ny, nz), code, brick, max_tf)
         if workspace is None:
             workspace = torch.empty(need, dtype=torch.uint8, device=vol.device)
+            self._on_stream(workspace)
         _require(workspace, "workspace", self.device)
         self._check(self._lib.esk_set_volume(self._ctx, ctypes.c_void_p(vol.data_ptr()), code, nx, ny, nz,
                                              float(value_range[0]), float(value_range[1]), brick, max_tf,
@@ -251,6 +260,7 @@ class Context:
         import torch
         if out is None:
             out = torch.empty((H, W, 4), dtype=torch.float32, device=self._keep["vol"].device)
+            self._on_stream(out)
         _require(out, "out", self.device, torch.float32, (H, W, 4))
         if counts is not None:
             _require(counts, "counts", self.device, torch.int32, (H, W))
