@@ -186,8 +186,9 @@ def cpu_baseline(vol, tfs, steps=3, stride=1, single_stride=64):
 def batched_vs_plain(esk, torch, count=64, reps=5):
     """Many uneven volumes, each with its own TF and camera, 512x512 each:
     the plain path (one request at a time: rebuild, render, wait) against the
-    batched path (all rebuilds enqueued, one batched render launch, one wait).
-    Both produce bit-identical images (checked)."""
+    batched path (one batched rebuild launch chain, one batched render
+    launch, one wait), eager and captured in a graph.  All produce
+    bit-identical images (checked)."""
     import numpy as np
 
     import synth
@@ -212,12 +213,22 @@ def batched_vs_plain(esk, torch, count=64, reps=5):
             c.render(cam, w, h, accel="lbvh", out=o)
             torch.cuda.synchronize()
 
+    rargs = None
+
     def batched():
-        nonlocal args
-        for c, tf in zip(ctxs, tfs):
-            c.set_tf(tf, build=("lbvh",))
+        nonlocal args, rargs
+        rargs = esk.rebuild_batch(ctxs, tfs, build=("lbvh",), args_buffer=rargs)
         esk.render_batch(ctxs, cams, sizes, accel="lbvh", outs=outs_b, args_buffer=args)
         args = ctxs[0]._keep["batch_args"]
+        torch.cuda.synchronize()
+
+    def rebuild_plain():
+        for c, tf in zip(ctxs, tfs):
+            c.set_tf(tf, build=("lbvh",))
+        torch.cuda.synchronize()
+
+    def rebuild_batched():
+        esk.rebuild_batch(ctxs, tfs, build=("lbvh",), args_buffer=rargs)
         torch.cuda.synchronize()
 
     def render_plain():
@@ -241,9 +252,25 @@ def batched_vs_plain(esk, torch, count=64, reps=5):
     rays = sum(w * h for (w, h) in sizes)
     tp, tb = timed(plain), timed(batched)
     rp, rb = timed(render_plain), timed(render_batched)
+    kp, kb = timed(rebuild_plain), timed(rebuild_batched)
     same = all(np.array_equal(a.cpu().numpy(), b.cpu().numpy()) for a, b in zip(outs_p, outs_b))
     for c in ctxs:
         c.close()
+
+    # the batched rebuild + render captured into one graph, replayed with the
+    # TFs refilled (one copy, one graph launch per batch)
+    from paper_1912_09596_amd.graphs import BatchRebuildRenderGraph
+    bricks = [8 if max(r["dims"]) <= 128 else 16 for r in reqs]
+    g = BatchRebuildRenderGraph([r["vol"] for r in reqs], bricks, 256, cams, sizes, accel="lbvh")
+    tf_stack = torch.stack(tfs)
+
+    def graph_batched():
+        g.replay(tf_stack)
+        torch.cuda.synchronize()
+
+    tg = timed(graph_batched)
+    same_graph = all(torch.equal(a, b) for a, b in zip(g.outs, outs_p))
+    g.close()
 
     # the same batch with brick sizes chosen per volume by the autotuner
     # (rebuild + one frame, on each request's own TF and camera); images do
@@ -270,6 +297,10 @@ def batched_vs_plain(esk, torch, count=64, reps=5):
             "speedup": round(tp / tb, 3),
             "render_only": {"plain_mrays_per_s": round(rays / rp / 1e6, 1),
                             "batched_mrays_per_s": round(rays / rb / 1e6, 1), "speedup": round(rp / rb, 3)},
+            "rebuild_only": {"plain_ms": round(kp * 1e3, 3), "batched_ms": round(kb * 1e3, 3),
+                             "speedup": round(kp / kb, 3)},
+            "graph": {"batched_mrays_per_s": round(rays / tg / 1e6, 1), "speedup_vs_eager_batched": round(tb / tg, 3),
+                      "images_identical": bool(same_graph)},
             "images_identical": bool(same),
             "tuned_bricks": {"rule": "8^3 up to 128 voxels per axis, else 16^3 (above); tuned: per volume, "
                                      "the brick of {8,16,32} minimising rebuild + one frame",

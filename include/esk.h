@@ -203,6 +203,28 @@ esk_status esk_set_volume(esk_ctx *ctx, const void *d_vox, int dtype, int nx, in
 esk_status esk_set_transfer_function(esk_ctx *ctx, const float *d_rgba, int n_entries,
                                      int build_mask, const esk_kd_params *kd);
 
+/* Batched rebuild: n requests (each a context with its own volume,
+ * workspace and TF, all on one device) set their TFs and rebuild in one
+ * launch chain on ctxs[0]'s stream: every kernel of the classification and
+ * of the LBVH build (Sec. 3.1, a chain of O(n) kernels) runs once for all
+ * requests, blockIdx.y picking the request.  Per-request semantics are
+ * exactly those of esk_set_transfer_function(ctxs[i], d_tfs[i],
+ * n_entries[i], build_mask, NULL), so every hierarchy is bit-identical to
+ * rebuilding it alone.  build_mask: ESK_ACCEL_GRID and/or ESK_ACCEL_LBVH (no
+ * k-d tree, vote or tight boxes: ESK_EINVAL).  The batch takes the sorted
+ * keys of every request from the Morton enumeration while its code domain
+ * is at most 2^20 codes (or 4x its brick count); larger lopsided grids are
+ * classified in the batch and finish their LBVH (compaction, radix sort,
+ * nodes) with launches of their own inside this call.  Each context appears once.  Every context's
+ * earlier work must be ordered before this call (same stream, or
+ * synchronised by the caller); a pending k-d build of any of them is waited
+ * for on ctxs[0]'s stream.  d_args: caller-owned device buffer of
+ * esk_rebuild_batch_bytes(n) bytes, 16-byte aligned, reusable once the
+ * stream has passed this call.  n in [1, 65535]. */
+esk_status esk_rebuild_batch_bytes(int n, size_t *out);
+esk_status esk_rebuild_batch(esk_ctx *const *ctxs, int n, const float *const *d_tfs, const int *n_entries,
+                             int build_mask, void *d_args, size_t args_bytes);
+
 /* Renders W x H pixels with `accel` (ESK_ACCEL_NONE, or one structure built by
  * the last rebuild): emission-absorption ray marching with post-classification
  * and no early ray termination or shading (Sec. 4.1).  Samples lie at

@@ -107,9 +107,12 @@ def lib() -> ctypes.CDLL:
                                    ctypes.POINTER(i32), f32, f32, ctypes.POINTER(P), P, sz]
     L.esk_render_batch_noalloc.argtypes = [ctypes.POINTER(P), i32, i32, ctypes.POINTER(Camera),
                                            ctypes.POINTER(i32), ctypes.POINTER(i32), f32, f32, ctypes.POINTER(P)]
+    L.esk_rebuild_batch_bytes.argtypes = [i32, ctypes.POINTER(sz)]
+    L.esk_rebuild_batch.argtypes = [ctypes.POINTER(P), i32, ctypes.POINTER(P), ctypes.POINTER(i32), i32, P, sz]
     for name in ("esk_create", "esk_destroy", "esk_workspace_bytes", "esk_set_volume",
                  "esk_set_transfer_function", "esk_render", "esk_sync", "esk_get_stats", "esk_export",
-                 "esk_render_batch_bytes", "esk_render_batch", "esk_render_batch_noalloc"):
+                 "esk_render_batch_bytes", "esk_render_batch", "esk_render_batch_noalloc",
+                 "esk_rebuild_batch_bytes", "esk_rebuild_batch"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -302,6 +305,44 @@ class Context:
         if width > 1:
             return buf.reshape(-1, width)
         return buf
+
+
+def rebuild_batch(contexts, tfs, build=("lbvh",), args_buffer=None):
+    """Sets tfs[i] on contexts[i] and rebuilds (grid and/or LBVH) for all
+    requests in one launch chain on contexts[0]'s stream; each hierarchy is
+    the one set_tf would build alone.  Returns the argument buffer (reusable
+    once the stream has passed the call)."""
+    import torch
+    n = len(contexts)
+    if len(tfs) != n:
+        raise ValueError("contexts and tfs must have one entry per request")
+    L = lib()
+    need = ctypes.c_size_t()
+    st = L.esk_rebuild_batch_bytes(n, ctypes.byref(need))
+    if st != OK:
+        raise EskError(st, "bad batch size")
+    dev = contexts[0]._keep["vol"].device
+    if args_buffer is None or args_buffer.numel() < need.value:
+        args_buffer = torch.empty(need.value, dtype=torch.uint8, device=dev)
+    _require(args_buffer, "args_buffer", contexts[0].device, torch.uint8)
+    for c, tf in zip(contexts, tfs):
+        if not isinstance(tf, torch.Tensor) or tf.dim() != 2 or tf.shape[1] != 4:
+            raise ValueError("TF must be an [N, 4] float32 tensor")
+        _require(tf, "TF", c.device, torch.float32)
+    mask = 0
+    for b in build:
+        mask |= BUILD[b]
+    ctx_arr = (ctypes.c_void_p * n)(*[c._ctx.value for c in contexts])
+    tf_arr = (ctypes.c_void_p * n)(*[t.data_ptr() for t in tfs])
+    n_arr = (ctypes.c_int * n)(*[int(t.shape[0]) for t in tfs])
+    st = L.esk_rebuild_batch(ctx_arr, n, tf_arr, n_arr, mask, ctypes.c_void_p(args_buffer.data_ptr()),
+                             args_buffer.numel())
+    if st != OK:
+        raise EskError(st, L.esk_last_error(contexts[0]._ctx).decode())
+    for c, tf in zip(contexts, tfs):
+        c._keep["tf"] = tf
+    contexts[0]._keep["rebuild_args"] = args_buffer
+    return args_buffer
 
 
 def render_batch(contexts, cams, sizes, accel="lbvh", step=0.5, ref=1.0, outs=None, args_buffer=None):

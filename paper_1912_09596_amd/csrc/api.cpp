@@ -62,7 +62,9 @@ Layout make_layout(int nx, int ny, int nz, int brick, int elem_bytes, int max_tf
     L.skeys = take(n4);
     L.tmpkeys = take(n4);
     L.sids = take(n4);
-    L.hist = take((size_t)L.nsortblk * 256 * 4);
+    // radix-sort histograms, or the block counts of a Morton enumeration of
+    // up to max(4 nb, kBatchEnumCodes) codes (1024 codes per block)
+    L.hist = take((size_t)std::max<int64_t>(L.nsortblk * 256, kBatchEnumCodes / 1024) * 4);
     L.lb_left = take(n4);
     L.lb_right = take(n4);
     L.lb_axis = take(n4);
@@ -121,6 +123,10 @@ struct esk_ctx {
     RenderArgs *staging = nullptr;
     int staging_cap = 0;
     hipEvent_t staging_done = nullptr;
+    // the same for batched rebuild arguments
+    RebuildArgs *rb_staging = nullptr;
+    int rb_staging_cap = 0;
+    hipEvent_t rb_done = nullptr;
     int kd_level_hint = 24;     // levels enqueued per rebuild (adapts to the last height)
     int kd_levels_enqueued = 0;
     // the k-d build runs on an auxiliary stream forked after classification,
@@ -196,6 +202,15 @@ esk_status read_header(esk_ctx *c)
                                   hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     return hip_check(c, e, "reading device header");
+}
+
+// true while `s` is being captured into a graph: the host staging of the
+// batched calls is then neither waited for nor marked (nothing executes
+// during a capture; a replay re-reads the staging the capture recorded)
+bool capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &st) == hipSuccess && st == hipStreamCaptureStatusActive;
 }
 
 // orders the main stream after the last k-d build (before anything that
@@ -307,6 +322,9 @@ esk_status esk_destroy(esk_ctx *c)
         if (c->staging_done) (void)hipEventSynchronize(c->staging_done);
         if (c->staging) (void)hipHostFree(c->staging);
         if (c->staging_done) (void)hipEventDestroy(c->staging_done);
+        if (c->rb_done) (void)hipEventSynchronize(c->rb_done);
+        if (c->rb_staging) (void)hipHostFree(c->rb_staging);
+        if (c->rb_done) (void)hipEventDestroy(c->rb_done);
         if (c->aux) (void)hipStreamSynchronize(c->aux);
         if (c->aux) (void)hipStreamDestroy(c->aux);
         if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
@@ -567,6 +585,140 @@ esk_status esk_set_transfer_function(esk_ctx *c, const float *d_rgba, int n_entr
     return ESK_OK;
 }
 
+// batched rebuild arguments: n RebuildArgs for the classification, up to n
+// for the LBVH chain, then four block-offset tables of n + 1 words
+static size_t rebuild_batch_bytes(int n)
+{
+    return 2 * (size_t)n * sizeof(RebuildArgs) + 4 * (((size_t)n + 1) * 4 + 15) / 16 * 16;
+}
+
+esk_status esk_rebuild_batch_bytes(int n, size_t *out)
+{
+    if (!out || n < 1 || n > 65535) return ESK_EINVAL;
+    *out = rebuild_batch_bytes(n);
+    return ESK_OK;
+}
+
+esk_status esk_rebuild_batch(esk_ctx *const *ctxs, int n, const float *const *d_tfs, const int *n_entries,
+                             int build_mask, void *d_args, size_t args_bytes)
+{
+    if (!ctxs || n < 1 || n > 65535 || !ctxs[0]) return ESK_EINVAL;
+    esk_ctx *c0 = ctxs[0];
+    if (!d_tfs || !n_entries) return fail(c0, ESK_EINVAL, "null request array");
+    if (build_mask & ~(ESK_ACCEL_GRID | ESK_ACCEL_LBVH))
+        return fail(c0, ESK_EINVAL, "batched rebuilds build the grid and the LBVH only (mask 0x%x)", build_mask);
+    if (!d_args || (reinterpret_cast<uintptr_t>(d_args) & 15) != 0)
+        return fail(c0, ESK_EINVAL, "argument buffer must be non-null and 16-byte aligned");
+    if (args_bytes < rebuild_batch_bytes(n))
+        return fail(c0, ESK_ENOSPC, "argument buffer has %zu bytes, needs %zu", args_bytes, rebuild_batch_bytes(n));
+    for (int i = 0; i < n; ++i) {
+        esk_ctx *c = ctxs[i];
+        if (!c) return fail(c0, ESK_EINVAL, "request %d has no context", i);
+        if (c->device != c0->device) return fail(c0, ESK_EINVAL, "request %d is on another device", i);
+        if (!d_tfs[i] || (reinterpret_cast<uintptr_t>(d_tfs[i]) & 15) != 0)
+            return fail(c0, ESK_EINVAL, "request %d: TF must be non-null and 16-byte aligned", i);
+        if (n_entries[i] < 2) return fail(c0, ESK_EINVAL, "request %d: TF needs at least 2 entries", i);
+        if (c->device >= 0 && !c->has_volume) return fail(c0, ESK_ESTATE, "request %d has no volume", i);
+        if (c->device >= 0 && n_entries[i] > c->max_tf)
+            return fail(c0, ESK_ELIMIT, "request %d: TF has %d entries, workspace sized for %d", i, n_entries[i],
+                        c->max_tf);
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == c) return fail(c0, ESK_EINVAL, "request %d repeats the context of request %d", i, j);
+    }
+    if (c0->device < 0) return fail(c0, ESK_ESTATE, "validation-only context");
+    hipError_t e = hipSetDevice(c0->device);
+    if (e != hipSuccess) return hip_check(c0, e, "hipSetDevice");
+    if (c0->rb_staging_cap < n) {
+        if (c0->rb_done) (void)hipEventSynchronize(c0->rb_done);
+        if (c0->rb_staging) (void)hipHostFree(c0->rb_staging);
+        c0->rb_staging = nullptr;
+        c0->rb_staging_cap = 0;
+        e = hipHostMalloc(reinterpret_cast<void **>(&c0->rb_staging), rebuild_batch_bytes(n));
+        if (e != hipSuccess) return hip_check(c0, e, "staging allocation");
+        c0->rb_staging_cap = n;
+    }
+    if (!c0->rb_done) {
+        e = hipEventCreateWithFlags(&c0->rb_done, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_check(c0, e, "event creation");
+    }
+    const bool cap = capturing(c0->stream);
+    if (!cap) {
+        e = hipEventSynchronize(c0->rb_done);  // the previous upload has finished with the staging
+        if (e != hipSuccess) return hip_check(c0, e, "staging wait");
+    }
+    // a pending k-d build of any context reads the flags this batch rewrites
+    for (int i = 0; i < n; ++i) {
+        esk_ctx *c = ctxs[i];
+        if (!c->kd_joined) {
+            e = hipStreamWaitEvent(c0->stream, c->ev_kd, 0);
+            if (e != hipSuccess) return hip_check(c0, e, "joining a k-d stream");
+            if (c == c0) c->kd_joined = true;
+        }
+    }
+    RebuildArgs *all = c0->rb_staging, *lbvh = c0->rb_staging + n;
+    const size_t table = (((size_t)n + 1) * 4 + 15) / 16 * 16;
+    char *offs = reinterpret_cast<char *>(c0->rb_staging + 2 * (size_t)n);
+    std::vector<int> radix;
+    int m = 0;
+    for (int i = 0; i < n; ++i) {
+        esk_ctx *c = ctxs[i];
+        c->has_tf = false;
+        c->built = 0;
+        c->kd_on_device = false;
+        c->N = n_entries[i];
+        c->tight = false;
+        RebuildArgs a = rebuild_args(c);
+        a.tf_src = d_tfs[i];
+        all[i] = a;
+        const bool lb = (build_mask & ESK_ACCEL_LBVH) != 0;
+        // the enumeration also for sparser code domains up to kBatchEnumCodes:
+        // the sorted keys are the same (keys are unique)
+        const bool enumerate = sort_by_enumeration(a) || ((int64_t)1 << a.key_bits) <= kBatchEnumCodes;
+        c->rebuild_compacts = lb && !enumerate;
+        if (lb && enumerate) lbvh[m++] = a;
+        else if (lb) radix.push_back(i);
+    }
+    // block offsets of the flat batched grids (every count is at least 1)
+    RebuildBatch b;
+    char *d_base = static_cast<char *>(d_args);
+    b.all = reinterpret_cast<const RebuildArgs *>(d_base);
+    b.lbvh = b.all + n;
+    b.n_all = n;
+    b.n_lbvh = m;
+    for (int k = 0; k < 4; ++k) {
+        uint32_t *o = reinterpret_cast<uint32_t *>(offs + k * table);
+        const RebuildArgs *src = k == 0 ? all : lbvh;
+        const int cnt = k == 0 ? n : m;
+        uint64_t run = 0;
+        for (int i = 0; i < cnt; ++i) {
+            o[i] = (uint32_t)run;
+            run += (uint64_t)rebuild_batch_blocks(src[i], k);
+        }
+        o[cnt] = (uint32_t)run;
+        if (run > 0x7fffffffu) return fail(c0, ESK_ELIMIT, "batched rebuild grid of %llu blocks",
+                                           (unsigned long long)run);
+        b.blocks[k] = (unsigned)run;
+        b.off[k] = reinterpret_cast<const uint32_t *>(d_base + 2 * (size_t)n * sizeof(RebuildArgs) + k * table);
+    }
+    e = hipMemcpyAsync(d_args, all, rebuild_batch_bytes(n), hipMemcpyHostToDevice, c0->stream);
+    if (e == hipSuccess && !cap) e = hipEventRecord(c0->rb_done, c0->stream);
+    if (e == hipSuccess) e = launch_rebuild_batch(b, c0->stream);
+    // grids whose code domain is too sparse to enumerate: their own compaction,
+    // radix sort and LBVH launches, in this call, on the same stream
+    for (size_t r = 0; r < radix.size() && e == hipSuccess; ++r) {
+        const RebuildArgs &a = all[radix[r]];
+        e = launch_compact(a, c0->stream);
+        if (e == hipSuccess) e = launch_sort(a, c0->stream);
+        if (e == hipSuccess) e = launch_lbvh(a, c0->stream);
+    }
+    if (e != hipSuccess) return hip_check(c0, e, "batched rebuild launch");
+    for (int i = 0; i < n; ++i) {
+        ctxs[i]->built = (build_mask & ESK_ACCEL_LBVH) | ESK_ACCEL_GRID;
+        ctxs[i]->has_tf = true;
+    }
+    return ESK_OK;
+}
+
 }  // extern "C"
 
 // validates one render request and fills its kernel arguments (may
@@ -666,7 +818,8 @@ static esk_status batch_launch(esk_ctx *c0, esk_ctx *const *ctxs, int n, int acc
                                float *const *d_outs, RenderArgs *staging, RenderArgs *d_args, hipEvent_t done,
                                Wait wait)
 {
-    esk_status st = wait();
+    const bool cap = capturing(c0->stream);
+    esk_status st = cap ? ESK_OK : wait();
     if (st != ESK_OK) return st;
     size_t lds = 0;
     bool narrow = true, tfl = true;
@@ -692,7 +845,7 @@ static esk_status batch_launch(esk_ctx *c0, esk_ctx *const *ctxs, int n, int acc
     hipError_t e = hipSetDevice(c0->device);
     if (e == hipSuccess)
         e = hipMemcpyAsync(d_args, staging, (size_t)n * sizeof(RenderArgs), hipMemcpyHostToDevice, c0->stream);
-    if (e == hipSuccess) e = hipEventRecord(done, c0->stream);
+    if (e == hipSuccess && !cap) e = hipEventRecord(done, c0->stream);
     if (e == hipSuccess)
         e = launch_render_batch(accel, c0->vol.dtype, d_args, n, tx, ty, lds, narrow, tfl, c0->stream);
     return hip_check(c0, e, "batched render launch");
@@ -766,7 +919,7 @@ esk_status esk_render_batch_noalloc(esk_ctx *const *ctxs, int n, int accel, cons
                           if (!slot->recorded) return ESK_OK;
                           return hip_check(c0, hipEventSynchronize(slot->done), "staging wait");
                       });
-    if (st == ESK_OK) slot->recorded = true;
+    if (st == ESK_OK && !capturing(c0->stream)) slot->recorded = true;
     return st;
 }
 

@@ -17,6 +17,12 @@ constexpr uint32_t kLeaf = 0x80000000u;
 constexpr int kClassifyBlock = 1024;  // bricks per classification / compaction block
 constexpr int kSortSingleMax = 32768; // keys one workgroup sorts in LDS
 constexpr int kSortBlockKeys = 4096;  // keys per block of the multi-block sort
+// Batched rebuilds take the sorted keys from the Morton enumeration while the
+// code domain is at most this many codes (or 4x the brick count, the rule of
+// a single rebuild): one launch chain for every request instead of a sort
+// per request.  The enumeration's 1024-code block counts go to `hist`, which
+// the workspace sizes for it.
+constexpr int64_t kBatchEnumCodes = (int64_t)1 << 20;
 constexpr int kMaxKdStack = 128;      // deepest k-d tree the renderer traverses
 constexpr int64_t kMaxBricks = (int64_t)1 << 28;  // node indices fit the 29-bit fields of RNode
 constexpr uint32_t kIndexMask = 0x1fffffffu;
@@ -130,6 +136,21 @@ hipError_t launch_compact(const RebuildArgs &a, hipStream_t s);
 bool sort_by_enumeration(const RebuildArgs &a);
 hipError_t launch_sort(const RebuildArgs &a, hipStream_t s);
 hipError_t launch_lbvh(const RebuildArgs &a, hipStream_t s);
+// Many requests in one launch chain: classification (+ block scan) of the
+// n_all requests of `all`, then the Morton enumeration and the LBVH kernels
+// of the n_lbvh requests of `lbvh` (device arrays of arguments).  Each
+// batched kernel runs the requests' own grids end to end in one flat grid:
+// off[k] (device, n + 1 entries) holds the first block of every request for
+// block-count kind k (0 classification, 1 Morton enumeration, 2 Karras /
+// height, 3 boxes; rebuild_batch_blocks gives the count), blocks[k] the total.
+struct RebuildBatch {
+    const RebuildArgs *all, *lbvh;
+    int n_all, n_lbvh;
+    const uint32_t *off[4];
+    unsigned blocks[4];
+};
+hipError_t launch_rebuild_batch(const RebuildBatch &b, hipStream_t s);
+int64_t rebuild_batch_blocks(const RebuildArgs &a, int kind);
 
 struct KdArgs {
     int nb[3], B, n[3];

@@ -235,7 +235,7 @@ template <typename T> hipError_t launch_tight_typed(const RebuildArgs &a, hipStr
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_classify(RebuildArgs a)
+__device__ __forceinline__ void k_classify_body(const RebuildArgs &a, uint32_t bx)
 {
     __shared__ int32_t P[kMaxTF + 1];
     __shared__ uint32_t scratch[8];
@@ -255,7 +255,7 @@ __global__ __launch_bounds__(256) void k_classify(RebuildArgs a)
         }
         if (threadIdx.x == 0) P[N] = (int32_t)tot;
         __syncthreads();
-        if (blockIdx.x == 0) {
+        if (bx == 0) {
             for (int i = threadIdx.x; i <= N; i += 256) a.tfP[i] = P[i];
             // the renderer's copy of the TF (both 16-byte aligned), opacity clamped
             for (int i = threadIdx.x; i < N; i += 256) {
@@ -265,7 +265,7 @@ __global__ __launch_bounds__(256) void k_classify(RebuildArgs a)
             }
         }
     }
-    const int64_t base = (int64_t)blockIdx.x * kClassifyBlock;
+    const int64_t base = (int64_t)bx * kClassifyBlock;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int j = 0; j < 4; ++j) {
         const int64_t b = base + 256 * j + threadIdx.x;
@@ -294,12 +294,12 @@ __global__ __launch_bounds__(256) void k_classify(RebuildArgs a)
     if (threadIdx.x == 0) {
         uint32_t t = 0;
         for (int i = 0; i < 16; ++i) t += wcount[i];
-        a.blkcnt[blockIdx.x] = t;
+        a.blkcnt[bx] = t;
     }
 }
 
 // exclusive scan of the per-block counts (single workgroup); total -> hdr->n
-__global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t *cnt, int64_t nblk, DevHeader *hdr)
+__device__ __forceinline__ void k_scan_blocks_body(uint32_t *cnt, int64_t nblk, DevHeader *hdr)
 {
     __shared__ uint32_t scratch[17];
     const int64_t per = (nblk + 1023) / 1024;
@@ -373,10 +373,10 @@ __device__ inline bool morton_flag(const RebuildArgs &a, uint32_t m)
     return a.flags[bx + (int64_t)a.vol.nb[0] * (by + (int64_t)a.vol.nb[1] * bz)] != 0;
 }
 
-__global__ __launch_bounds__(256) void k_morton_count(RebuildArgs a, uint32_t *cnt, int64_t codes)
+__device__ __forceinline__ void k_morton_count_body(const RebuildArgs &a, uint32_t *cnt, int64_t codes, uint32_t bx)
 {
     __shared__ uint32_t wcount[4];
-    const int64_t base = (int64_t)blockIdx.x * kMortonBlock;
+    const int64_t base = (int64_t)bx * kMortonBlock;
     uint32_t c = 0;
     for (int j = 0; j < 4; ++j) {
         const int64_t m = base + 256 * j + threadIdx.x;
@@ -385,14 +385,14 @@ __global__ __launch_bounds__(256) void k_morton_count(RebuildArgs a, uint32_t *c
     }
     if ((threadIdx.x & 63) == 0) wcount[threadIdx.x >> 6] = c;
     __syncthreads();
-    if (threadIdx.x == 0) cnt[blockIdx.x] = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+    if (threadIdx.x == 0) cnt[bx] = wcount[0] + wcount[1] + wcount[2] + wcount[3];
 }
 
 // cnt: exclusive block offsets (k_scan_blocks)
-__global__ __launch_bounds__(256) void k_morton_scatter(RebuildArgs a, const uint32_t *cnt, int64_t codes)
+__device__ __forceinline__ void k_morton_scatter_body(const RebuildArgs &a, const uint32_t *cnt, int64_t codes, uint32_t bx)
 {
     __shared__ uint32_t woff[16];
-    const int64_t base = (int64_t)blockIdx.x * kMortonBlock;
+    const int64_t base = (int64_t)bx * kMortonBlock;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     bool f[4];
     uint64_t mk[4];
@@ -405,7 +405,7 @@ __global__ __launch_bounds__(256) void k_morton_scatter(RebuildArgs a, const uin
     __syncthreads();
     if (threadIdx.x == 0) {
         // codes ascend with j, then wave, then lane
-        uint32_t run = cnt[blockIdx.x];
+        uint32_t run = cnt[bx];
         for (int q = 0; q < 16; ++q) {
             const uint32_t t = woff[q];
             woff[q] = run;
@@ -624,12 +624,12 @@ __device__ inline void box12_wave(Box12 &x)
 // kLeafChunk sorted keys: the block also writes the chunk's union boxes
 // (read by k_lbvh_boxes for long ranges).
 static_assert(kLeafChunk == 256, "one k_karras block per leaf chunk");
-__global__ __launch_bounds__(256) void k_karras(RebuildArgs a)
+__device__ __forceinline__ void k_karras_body(const RebuildArgs &a, uint32_t bx)
 {
     __shared__ int red[4][12];
     const int n = (int)a.hdr->n;
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if ((int64_t)blockIdx.x * kLeafChunk >= n) return;   // uniform per block
+    const int i = bx * 256 + threadIdx.x;
+    if ((int64_t)bx * kLeafChunk >= n) return;   // uniform per block
     const uint32_t *k = a.skeys;
     Box12 x;
     box12_empty(x);
@@ -682,7 +682,7 @@ __global__ __launch_bounds__(256) void k_karras(RebuildArgs a)
         const int q = threadIdx.x, qq = q % 6;
         int v = red[0][q];
         for (int w = 1; w < 4; ++w) v = qq < 3 ? min(v, red[w][q]) : max(v, red[w][q]);
-        a.lb_chunk[12 * (int64_t)blockIdx.x + q] = v;
+        a.lb_chunk[12 * (int64_t)bx + q] = v;
     }
     if (i >= n - 1) return;
     const int d = (delta(k, n, i, i + 1) - delta(k, n, i, i - 1)) > 0 ? 1 : -1;
@@ -713,11 +713,11 @@ __global__ __launch_bounds__(256) void k_karras(RebuildArgs a)
     a.lb_range[i] = make_int2(lo, hi);
 }
 
-__global__ __launch_bounds__(256) void k_lbvh_boxes(RebuildArgs a)
+__device__ __forceinline__ void k_lbvh_boxes_body(const RebuildArgs &a, uint32_t bx)
 {
     const int n = (int)a.hdr->n;
     const int lane = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t i = (int64_t)bx * 4 + (threadIdx.x >> 6);
     if (i >= n - 1) return;
     const int2 rg = a.lb_range[i];
     const uint32_t l = a.lb_left[i], r = a.lb_right[i];
@@ -775,10 +775,10 @@ __global__ __launch_bounds__(256) void k_lbvh_boxes(RebuildArgs a)
 }
 
 // height in levels = 1 + the deepest leaf's number of ancestors
-__global__ __launch_bounds__(256) void k_lbvh_height(RebuildArgs a)
+__device__ __forceinline__ void k_lbvh_height_body(const RebuildArgs &a, uint32_t bx)
 {
     const int n = (int)a.hdr->n;
-    const int j = blockIdx.x * 256 + threadIdx.x;
+    const int j = bx * 256 + threadIdx.x;
     uint32_t depth = 0;
     if (j < n) {
         const int u = (n - 1) + j;
@@ -794,6 +794,97 @@ __global__ __launch_bounds__(256) void k_lbvh_height(RebuildArgs a)
     }
     for (int o = 32; o >= 1; o >>= 1) depth = max(depth, (uint32_t)__shfl_xor((int)depth, o, 64));
     if ((threadIdx.x & 63) == 0 && depth > 0) atomicMax(&a.hdr->lbvh_height, depth);
+}
+
+// ---------------------------------------------------------------------------
+// Kernel entry points.  Each body above runs either for one request (the
+// arguments by value) or batched: blockIdx.y picks the request from a
+// device array of arguments and the blocks past that request's own grid
+// (the same count its single launch uses) exit at once.
+// ---------------------------------------------------------------------------
+
+__device__ inline int64_t morton_codes(const RebuildArgs &a) { return (int64_t)1 << a.key_bits; }
+__device__ inline int64_t morton_blocks(const RebuildArgs &a) { return (morton_codes(a) + kMortonBlock - 1) / kMortonBlock; }
+
+__global__ __launch_bounds__(256) void k_classify(RebuildArgs a) { k_classify_body(a, blockIdx.x); }
+__global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t *cnt, int64_t nblk, DevHeader *hdr)
+{
+    k_scan_blocks_body(cnt, nblk, hdr);
+}
+__global__ __launch_bounds__(256) void k_morton_count(RebuildArgs a, uint32_t *cnt, int64_t codes)
+{
+    k_morton_count_body(a, cnt, codes, blockIdx.x);
+}
+__global__ __launch_bounds__(256) void k_morton_scatter(RebuildArgs a, const uint32_t *cnt, int64_t codes)
+{
+    k_morton_scatter_body(a, cnt, codes, blockIdx.x);
+}
+__global__ __launch_bounds__(256) void k_karras(RebuildArgs a) { k_karras_body(a, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_lbvh_boxes(RebuildArgs a) { k_lbvh_boxes_body(a, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_lbvh_height(RebuildArgs a) { k_lbvh_height_body(a, blockIdx.x); }
+
+// The batched launches run one flat grid: the requests' own grids laid end
+// to end, off[r] = the first block of request r (off[n] = the total); a
+// block finds its request by binary search over off (uniform, scalar loads).
+__device__ inline int batch_request(const uint32_t *__restrict__ off, int n, uint32_t b)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_classify_batch(const RebuildArgs *__restrict__ args,
+                                                        const uint32_t *__restrict__ off, int n)
+{
+    const int r = batch_request(off, n, blockIdx.x);
+    const RebuildArgs a = args[r];
+    k_classify_body(a, blockIdx.x - off[r]);
+}
+// which = 0: the classification block counts (total -> hdr->n); 1: the
+// Morton enumeration block counts.  One workgroup per request (blockIdx.y).
+__global__ __launch_bounds__(1024) void k_scan_blocks_batch(const RebuildArgs *__restrict__ args, int which)
+{
+    const RebuildArgs a = args[blockIdx.y];
+    if (which == 0) k_scan_blocks_body(a.blkcnt, a.nblk, a.hdr);
+    else k_scan_blocks_body(a.hist, morton_blocks(a), a.hdr);
+}
+__global__ __launch_bounds__(256) void k_morton_count_batch(const RebuildArgs *__restrict__ args,
+                                                            const uint32_t *__restrict__ off, int n)
+{
+    const int r = batch_request(off, n, blockIdx.x);
+    const RebuildArgs a = args[r];
+    k_morton_count_body(a, a.hist, morton_codes(a), blockIdx.x - off[r]);
+}
+__global__ __launch_bounds__(256) void k_morton_scatter_batch(const RebuildArgs *__restrict__ args,
+                                                              const uint32_t *__restrict__ off, int n)
+{
+    const int r = batch_request(off, n, blockIdx.x);
+    const RebuildArgs a = args[r];
+    k_morton_scatter_body(a, a.hist, morton_codes(a), blockIdx.x - off[r]);
+}
+__global__ __launch_bounds__(256) void k_karras_batch(const RebuildArgs *__restrict__ args,
+                                                      const uint32_t *__restrict__ off, int n)
+{
+    const int r = batch_request(off, n, blockIdx.x);
+    const RebuildArgs a = args[r];
+    k_karras_body(a, blockIdx.x - off[r]);
+}
+__global__ __launch_bounds__(256) void k_lbvh_boxes_batch(const RebuildArgs *__restrict__ args,
+                                                          const uint32_t *__restrict__ off, int n)
+{
+    const int r = batch_request(off, n, blockIdx.x);
+    const RebuildArgs a = args[r];
+    k_lbvh_boxes_body(a, blockIdx.x - off[r]);
+}
+__global__ __launch_bounds__(256) void k_lbvh_height_batch(const RebuildArgs *__restrict__ args,
+                                                           const uint32_t *__restrict__ off, int n)
+{
+    const int r = batch_request(off, n, blockIdx.x);
+    const RebuildArgs a = args[r];
+    k_lbvh_height_body(a, blockIdx.x - off[r]);
 }
 
 }  // namespace
@@ -882,6 +973,34 @@ hipError_t launch_lbvh(const RebuildArgs &a, hipStream_t s)
     hipLaunchKernelGGL(k_lbvh_boxes, dim3((unsigned)((a.nb + 3) / 4)), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_lbvh_height, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
+}
+
+hipError_t launch_rebuild_batch(const RebuildBatch &b, hipStream_t s)
+{
+    if (b.n_all > 0) {
+        hipLaunchKernelGGL(k_classify_batch, dim3(b.blocks[0]), dim3(256), 0, s, b.all, b.off[0], b.n_all);
+        hipLaunchKernelGGL(k_scan_blocks_batch, dim3(1, (unsigned)b.n_all), dim3(1024), 0, s, b.all, 0);
+    }
+    if (b.n_lbvh > 0) {
+        hipLaunchKernelGGL(k_morton_count_batch, dim3(b.blocks[1]), dim3(256), 0, s, b.lbvh, b.off[1], b.n_lbvh);
+        hipLaunchKernelGGL(k_scan_blocks_batch, dim3(1, (unsigned)b.n_lbvh), dim3(1024), 0, s, b.lbvh, 1);
+        hipLaunchKernelGGL(k_morton_scatter_batch, dim3(b.blocks[1]), dim3(256), 0, s, b.lbvh, b.off[1], b.n_lbvh);
+        hipLaunchKernelGGL(k_karras_batch, dim3(b.blocks[2]), dim3(256), 0, s, b.lbvh, b.off[2], b.n_lbvh);
+        hipLaunchKernelGGL(k_lbvh_boxes_batch, dim3(b.blocks[3]), dim3(256), 0, s, b.lbvh, b.off[3], b.n_lbvh);
+        hipLaunchKernelGGL(k_lbvh_height_batch, dim3(b.blocks[2]), dim3(256), 0, s, b.lbvh, b.off[2], b.n_lbvh);
+    }
+    return hipGetLastError();
+}
+
+int64_t rebuild_batch_blocks(const RebuildArgs &a, int kind)
+{
+    switch (kind) {
+    case 0: return a.nblk;
+    case 1: return (((int64_t)1 << a.key_bits) + kMortonBlock - 1) / kMortonBlock;
+    case 2: return (a.nb + 255) / 256;
+    case 3: return (a.nb + 3) / 4;
+    }
+    return 0;
 }
 
 }  // namespace esk

@@ -155,6 +155,27 @@ def test_batch_validation_without_a_device():
     assert "1024" in v.err()
     assert na(ctxs, n, esk.LBVH, cams, ws, hs, 0.5, 1.0, outs) == esk.ESTATE
     assert L.esk_render_batch(ctxs, n, esk.LBVH, cams, ws, hs, 0.5, 1.0, outs, None, 0) == esk.EINVAL
+    # batched rebuild: request arrays, mask, buffer, repeated contexts
+    rb = L.esk_rebuild_batch
+    need = ctypes.c_size_t()
+    assert L.esk_rebuild_batch_bytes(2, ctypes.byref(need)) == esk.OK and need.value > 0
+    assert L.esk_rebuild_batch_bytes(0, ctypes.byref(need)) == esk.EINVAL
+    one = (ctypes.c_void_p * 1)(v.c.value)
+    tfp = (ctypes.c_void_p * 1)(FAKE.value)
+    ne = (ctypes.c_int * 1)(256)
+    big_buf = ctypes.c_void_p(0x200000)
+    assert rb(None, 1, tfp, ne, esk.LBVH, big_buf, 1 << 20) == esk.EINVAL
+    assert rb(one, 1, None, ne, esk.LBVH, big_buf, 1 << 20) == esk.EINVAL
+    assert rb(one, 1, tfp, ne, esk.KD, big_buf, 1 << 20) == esk.EINVAL
+    assert rb(one, 1, tfp, ne, esk.LBVH | esk.TIGHT_BOXES, big_buf, 1 << 20) == esk.EINVAL
+    assert rb(one, 1, tfp, ne, esk.LBVH, None, 1 << 20) == esk.EINVAL
+    assert rb(one, 1, tfp, ne, esk.LBVH, big_buf, 16) == esk.ENOSPC
+    assert rb(one, 1, (ctypes.c_void_p * 1)(0x100004), ne, esk.LBVH, big_buf, 1 << 20) == esk.EINVAL
+    assert rb(one, 1, tfp, (ctypes.c_int * 1)(1), esk.LBVH, big_buf, 1 << 20) == esk.EINVAL
+    two = (ctypes.c_void_p * 2)(v.c.value, v.c.value)
+    assert rb(two, 2, (ctypes.c_void_p * 2)(FAKE.value, FAKE.value), (ctypes.c_int * 2)(256, 256), esk.LBVH,
+              big_buf, 1 << 20) == esk.EINVAL
+    assert rb(one, 1, tfp, ne, esk.LBVH, big_buf, 1 << 20) == esk.ESTATE
     assert L.esk_render_batch(ctxs, n, esk.LBVH, cams, ws, hs, 0.5, 1.0, outs, FAKE, 16) == esk.ENOSPC
     v.close()
 

@@ -120,3 +120,87 @@ def test_rebuild_render_graph_replays():
             assert np.array_equal(g.ctx.export("keys"), oracle.morton_keys(ids, nb[0], nb[1])), (accel, seed)
         eager.close()
         g.close()
+
+
+def test_batched_rebuild_equals_alone():
+    """All requests set their TFs and rebuild in one launch chain: the flags,
+    the sorted keys and the LBVH of every context, and every image rendered
+    from them, equal rebuilding each context alone, bit for bit; two images
+    match the FP64 oracle within 1e-3.  The mix holds grids whose keys come
+    from the Morton enumeration and lopsided ones that take the radix sort
+    alone (and in the batch, the largest); a second round with new TFs
+    reuses the argument buffer."""
+    torch = _torch()
+    import paper_1912_09596_amd as esk
+    reqs = make_requests(10, 21)
+    # lopsided brick grids: alone they take the radix sort (code domain above
+    # 4x the brick count); in the batch the first two take the Morton
+    # enumeration (domain <= 2^20 codes) and the third the radix sort too
+    for i, dims in enumerate([(200, 24, 24), (24, 176, 16), (2048, 8, 8)]):
+        vol = synth.blobs_u8(dims, n_blobs=4, seed=700 + i, cut=40)
+        cam = synth.perspective(dims, 64, 48, synth.view_direction(700 + i))
+        reqs.append(dict(dims=dims, vol=vol, tf=synth.tf_random(700 + i, 256), W=64, H=48, cam=cam, B=4))
+    print(f"case: batched rebuild of {len(reqs)} requests", flush=True)
+    batch, alone = [], []
+    for r in reqs:
+        for group in (batch, alone):
+            c = esk.Context(0)
+            c.set_volume(torch.from_numpy(r["vol"]).cuda(), r["B"], max_tf=256)
+            group.append(c)
+    args = None
+    for rnd in range(2):
+        tfs = [torch.from_numpy(r["tf"] if rnd == 0 else synth.tf_random(900 + i, 256)).cuda()
+               for i, r in enumerate(reqs)]
+        args = esk.rebuild_batch(batch, tfs, build=("grid", "lbvh"), args_buffer=args)
+        imgs = esk.render_batch(batch, [r["cam"] for r in reqs], [(r["W"], r["H"]) for r in reqs], accel="lbvh")
+        torch.cuda.synchronize()
+        for i, (c, r) in enumerate(zip(alone, reqs)):
+            c.set_tf(tfs[i], build=("grid", "lbvh"))
+            want = c.render(r["cam"], r["W"], r["H"], accel="lbvh").cpu().numpy()
+            assert np.array_equal(imgs[i].cpu().numpy(), want), (rnd, i)
+            grid = c.render(r["cam"], r["W"], r["H"], accel="grid").cpu().numpy()
+            got_grid = batch[i].render(r["cam"], r["W"], r["H"], accel="grid").cpu().numpy()
+            assert np.array_equal(got_grid, grid), (rnd, i)
+            for what in ("flags", "grid", "sorted_keys", "sorted_ids", "lbvh_left", "lbvh_right", "lbvh_axis",
+                         "lbvh_lo", "lbvh_hi"):
+                assert np.array_equal(batch[i].export(what), c.export(what)), (rnd, i, what)
+            assert batch[i].stats() == c.stats(), (rnd, i)
+        for i in (0, len(reqs) - 1):
+            r = reqs[i]
+            tf_np = tfs[i].cpu().numpy()
+            ref = oracle.render(r["vol"], tf_np, r["cam"], r["W"], r["H"])
+            assert np.abs(imgs[i].cpu().numpy().astype(np.float64) - ref).max() <= 1e-3, (rnd, i)
+    for c in batch + alone:
+        c.close()
+
+
+def test_batched_rebuild_render_graph_replays():
+    """The batched rebuild + render captured into one graph and replayed with
+    three TF sets (eager work and synchronisations between the replays):
+    every image equals rebuilding and rendering its request alone."""
+    torch = _torch()
+    import paper_1912_09596_amd as esk
+    from paper_1912_09596_amd.graphs import BatchRebuildRenderGraph
+    reqs = make_requests(6, 31)
+    vols = [torch.from_numpy(r["vol"]).cuda() for r in reqs]
+    print(f"case: batched graph of {len(reqs)} requests", flush=True)
+    g = BatchRebuildRenderGraph(vols, [r["B"] for r in reqs], 256, [r["cam"] for r in reqs],
+                                [(r["W"], r["H"]) for r in reqs], accel="lbvh")
+    alone = []
+    for r, v in zip(reqs, vols):
+        c = esk.Context(0)
+        c.set_volume(v, r["B"], max_tf=256)
+        alone.append(c)
+    for rnd in range(3):
+        tfs = [torch.from_numpy(synth.tf_random(1300 + 10 * rnd + i, 256)).cuda() for i in range(len(reqs))]
+        outs = g.replay(torch.stack(tfs))
+        g.stream.synchronize()
+        got = [o.cpu().numpy().copy() for o in outs]
+        for i, (c, r) in enumerate(zip(alone, reqs)):
+            c.set_tf(tfs[i], build=("lbvh",))
+            want = c.render(r["cam"], r["W"], r["H"], accel="lbvh").cpu().numpy()
+            torch.cuda.synchronize()
+            assert np.array_equal(got[i], want), (rnd, i)
+    g.close()
+    for c in alone:
+        c.close()
