@@ -315,7 +315,9 @@ def graph_replay(esk, torch, count=200):
     """Launch-bound requests: a 64^3 u8 volume rendered at 256x256 with the
     LBVH, rebuilt for a new TF before every frame; eager calls against one
     HIP graph holding the rebuild and the render (replayed with the TF
-    buffer refilled).  Requests per second, both issued back to back."""
+    buffer refilled); then sixteen such requests per launch: plain calls,
+    the batched calls, and the batched calls in one graph.  Requests per
+    second, issued back to back."""
     import synth
     from paper_1912_09596_amd.graphs import RebuildRenderGraph
 
@@ -350,6 +352,54 @@ def graph_replay(esk, torch, count=200):
     res["workload"] = "64^3 u8 blobs, 8^3 bricks, LBVH rebuild + 256x256 render per request"
     g.close()
     ctx.close()
+
+    # the same requests sixteen at a time: plain calls, the batched calls,
+    # and the batched calls captured in one graph
+    from paper_1912_09596_amd.graphs import BatchRebuildRenderGraph
+    nb = 16
+    ctxs = []
+    for _ in range(nb):
+        c = esk.Context(0)
+        c.set_volume(vol, 8, max_tf=256)
+        ctxs.append(c)
+    outs = [torch.empty((256, 256, 4), dtype=torch.float32, device="cuda") for _ in range(nb)]
+    stacks = [torch.stack([tfs[(k + i) % 8] for i in range(nb)]) for k in range(8)]
+    gb = BatchRebuildRenderGraph([vol] * nb, [8] * nb, 256, [cam] * nb, [(256, 256)] * nb, accel="lbvh")
+    bufs = {}
+
+    def plain16(n):
+        for k in range(n):
+            for i, c in enumerate(ctxs):
+                c.set_tf(tfs[(k + i) % 8], build=("lbvh",))
+                c.render(cam, 256, 256, accel="lbvh", out=outs[i])
+        torch.cuda.synchronize()
+
+    def batched16(n):
+        for k in range(n):
+            bufs["r"] = esk.rebuild_batch(ctxs, list(stacks[k % 8].unbind(0)), build=("lbvh",),
+                                          args_buffer=bufs.get("r"))
+            esk.render_batch(ctxs, [cam] * nb, [(256, 256)] * nb, accel="lbvh", outs=outs,
+                             args_buffer=bufs.get("b"))
+            bufs["b"] = ctxs[0]._keep["batch_args"]
+        torch.cuda.synchronize()
+
+    def graph16(n):
+        for k in range(n):
+            gb.replay(stacks[k % 8])
+        torch.cuda.synchronize()
+
+    b16 = {}
+    for name, fn in (("plain", plain16), ("batched", batched16), ("graph", graph16)):
+        fn(3)
+        t = time.perf_counter()
+        fn(count // nb)
+        b16[name + "_requests_per_s"] = round((count // nb) * nb / (time.perf_counter() - t), 1)
+    b16["graph_vs_plain"] = round(b16["graph_requests_per_s"] / b16["plain_requests_per_s"], 3)
+    b16["graph_vs_batched"] = round(b16["graph_requests_per_s"] / b16["batched_requests_per_s"], 3)
+    res["sixteen_per_launch"] = b16
+    gb.close()
+    for c in ctxs:
+        c.close()
     return res
 
 
