@@ -77,10 +77,12 @@ def _log(msg):
 def test_large_volume_storage_sampled(case):
     """1024^3 tubes stored as f32 and f16, 2048^3 tubes stored as u16 (8^3
     bricks; the 2048^3 copy exceeds 4 GiB, so it runs the 64-bit-offset
-    render path).  Rebuild products are exact against the oracle; on sampled
-    pixels of 1080p frames the error against the FP64 render of the stored
-    volume stays within 1e-3 and against the FP32 source within 4e-3; every
-    skipping mode reproduces the full march bit for bit."""
+    render path).  Rebuild products are exact against the oracle; the error
+    against the FP64 render of the stored volume stays within 1e-3 and
+    against the FP32 source within 4e-3, on every pixel of a 192x108 image of
+    the view and on sampled pixels of the 1080p frame (random ones and the
+    64 with the most composited samples); every skipping mode reproduces the
+    full march bit for bit."""
     torch = _torch()
     import paper_1912_09596_amd as esk
     w = {c["name"]: c for c in synth.c3_workloads()}[case]
@@ -94,9 +96,23 @@ def test_large_volume_storage_sampled(case):
     W, H = 1920, 1080
     cam = synth.perspective(dims, W, H, synth.view_direction(w["seed"]))
     rng = np.random.default_rng(w["seed"])
-    pix = np.stack([rng.integers(0, W, 160), rng.integers(0, H, 160)], 1).astype(np.int32)
-    _log(f"case: {case} oracle of the FP32 source on {len(pix)} pixels")
+    # sampled pixels: random ones plus the 64 with the most composited
+    # samples (the longest sums, where FP32 compositing error grows)
+    cnt_ctx = esk.Context(0)
+    cnt_ctx.set_volume(src, 8, (0.0, 1.0), max_tf=256)
+    cnt_ctx.set_tf(dtf, build=("grid",))
+    counts = torch.empty((H, W), dtype=torch.int32, device="cuda")
+    cnt_ctx.render(cam, W, H, accel="grid", counts=counts)
+    top = torch.topk(counts.view(-1), 64).indices.cpu().numpy()
+    cnt_ctx.close()
+    pix = np.concatenate([np.stack([rng.integers(0, W, 160), rng.integers(0, H, 160)], 1),
+                          np.stack([top % W, top // W], 1)]).astype(np.int32)
+    # the whole image at a reduced resolution of the same view (every pixel)
+    Ws, Hs = 192, 108
+    cam_s = synth.perspective(dims, Ws, Hs, synth.view_direction(w["seed"]))
+    _log(f"case: {case} oracle of the FP32 source on {len(pix)} pixels and a full {Ws}x{Hs} image")
     ref_src = oracle.render(src_host, tf, cam, W, H, pixels=pix)
+    ref_src_s = oracle.render(src_host, tf, cam_s, Ws, Hs)
     for storage in w["storage"]:
         if storage == "f32":
             dv, stored = src, src_host
@@ -132,6 +148,14 @@ def test_large_volume_storage_sampled(case):
             assert np.array_equal(ctx.export("kd_" + name), k[name]), name
         _log(f"case: {case} {storage}: {ids.size} non-empty bricks of {flags.size}; renders + oracle")
         ref_stored = ref_src if storage == "f32" else oracle.render(stored, tf, cam, W, H, pixels=pix)
+        ref_stored_s = ref_src_s if storage == "f32" else oracle.render(stored, tf, cam_s, Ws, Hs)
+        small = ctx.render(cam_s, Ws, Hs, accel="lbvh").cpu().numpy().astype(np.float64)
+        e_stored = np.abs(small - ref_stored_s).max()
+        e_src = np.abs(small - ref_src_s).max()
+        _log(f"  {storage} whole {Ws}x{Hs} image: max|err| vs FP64 of stored {e_stored:.2e}, "
+             f"of FP32 source {e_src:.2e}")
+        assert e_stored <= TOL_ARITH
+        assert e_src <= TOL_STORAGE
         full = None
         for accel in ("none", "grid", "lbvh", "kd"):
             img = ctx.render(cam, W, H, accel=accel).cpu().numpy()
