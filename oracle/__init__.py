@@ -76,7 +76,7 @@ def lib():
         _lib.orc_sort_pairs.argtypes = [P, P, i64]
         _lib.orc_lbvh.argtypes = [P, P, i64, i32, i32, i32, i32, i32, i32, P, P, P, P, P]
         _lib.orc_kd.argtypes = [P, i32, i32, i32, i32, i32, i32, i32, i32, i32, i32, i64,
-                                P, P, P, P, P, P]
+                                P, P, P, P, P, P, P]
         _lib.orc_kd.restype = i64
         _lib.orc_render.argtypes = [P, i32, i32, i32, i32, f32, f32, P, i32,
                                     ctypes.POINTER(Camera), i32, i32, f32, f32, i32, P, i32,
@@ -221,8 +221,11 @@ def lbvh(sorted_keys, sorted_ids, B, dims_xyz):
                 hi=hi[:m], height=int(h))
 
 
-def kd(flags, B, dims_xyz, halting=1, max_leaf=0, bins=4):
-    """a10: binned k-d tree over brick occupancy, BFS order (Sec. 3.2, 4.3)."""
+def kd(flags, B, dims_xyz, halting=1, max_leaf=0, bins=4, tight_boxes=None):
+    """a10: binned k-d tree over brick occupancy, BFS order (Sec. 3.2, 4.3).
+    tight_boxes: None for the brick-granular cost, else the (nb, 6) voxel-
+    tight boxes of tight_boxes(): the split cost and every volume the build
+    compares use the unions of those boxes (Sec. 3.2.2)."""
     flags = np.ascontiguousarray(flags, np.uint8)
     nx, ny, nz = dims_xyz
     nbx, nby, nbz = brick_grid(dims_xyz, B)
@@ -233,8 +236,12 @@ def kd(flags, B, dims_xyz, halting=1, max_leaf=0, bins=4):
     plane = np.zeros(cap, np.int32)
     first = np.zeros(cap, np.int32)
     height = np.zeros(1, np.int32)
+    tb = None if tight_boxes is None else np.ascontiguousarray(tight_boxes, np.int32).reshape(-1, 6)
+    if tb is not None and tb.shape[0] != flags.shape[0]:
+        raise ValueError("tight_boxes needs one box per brick")
     n = lib().orc_kd(_p(flags), nbx, nby, nbz, B, nx, ny, nz, halting, max_leaf, bins, cap,
-                     _p(lo), _p(hi), _p(axis), _p(plane), _p(first), _p(height))
+                     _p(lo), _p(hi), _p(axis), _p(plane), _p(first), _p(height),
+                     _p(tb) if tb is not None else None)
     if n < 0:
         raise RuntimeError("orc_kd: capacity exceeded")
     return dict(lo=lo[:n], hi=hi[:n], axis=axis[:n], plane=plane[:n], first_child=first[:n],

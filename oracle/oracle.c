@@ -479,15 +479,46 @@ static int64_t kd_volume(const kd_ctx *c, const int lo[3], const int hi[3])
     return v;
 }
 
+/* Voxel-tight cost (the GPU builder of Sec. 3.2.2 keeps one voxel-tight box */
+/* per macro cell and, for a region spanning several cells, reduces over     */
+/* them): the tight box of a region is the union of the voxel-tight boxes    */
+/* (half-voxel units, as orc_tight_boxes gives them) of the bricks inside    */
+/* it, and its volume is measured in half-voxel units (eight per voxel).     */
+/* Returns that volume, 0 when no brick of the region has a visible cell.   */
+static int64_t kd_tight_volume(const kd_ctx *c, const int32_t *tbox, const int rlo[3], const int rhi[3])
+{
+    int found = 0, ulo[3] = {0, 0, 0}, uhi[3] = {0, 0, 0};
+    for (int z = rlo[2]; z < rhi[2]; ++z)
+        for (int y = rlo[1]; y < rhi[1]; ++y)
+            for (int x = rlo[0]; x < rhi[0]; ++x) {
+                const int32_t *b = tbox + 6 * ((size_t)x + (size_t)c->nb[0] * ((size_t)y + (size_t)c->nb[1] * z));
+                if (!(b[3] > b[0] && b[4] > b[1] && b[5] > b[2])) continue;   /* no visible cell */
+                for (int a = 0; a < 3; ++a) {
+                    if (!found || b[a] < ulo[a]) ulo[a] = b[a];
+                    if (!found || b[3 + a] > uhi[a]) uhi[a] = b[3 + a];
+                }
+                found = 1;
+            }
+    if (!found) return 0;
+    return (int64_t)(uhi[0] - ulo[0]) * (uhi[1] - ulo[1]) * (uhi[2] - ulo[2]);
+}
+
 /* out arrays sized `cap` nodes: lo/hi [cap][3] (bricks), axis (-1 = leaf),
  * plane (bricks, 0 for leaves), first_child (-1 for leaves).  Returns the
  * node count (0 for an empty occupancy), or -1 if cap is too small; the
- * height in levels goes to *height. */
+ * height in levels goes to *height.  tbox: NULL for the brick-granular cost,
+ * else the voxel-tight box of every brick ([nb][6], half-voxel units): every
+ * volume the build compares (a side's cost, the node, the root, the 8^3 and
+ * maximum-leaf-size limits) is then the half-voxel volume of the union of
+ * the voxel-tight boxes inside the region; node regions, candidate planes
+ * and children stay on the brick raster. */
 int64_t orc_kd(const uint8_t *flags, int nbx, int nby, int nbz, int B, int nx, int ny, int nz,
                int halting, int max_leaf, int bins, int64_t cap, int32_t *lo, int32_t *hi,
-               int32_t *axis, int32_t *plane, int32_t *first_child, int32_t *height)
+               int32_t *axis, int32_t *plane, int32_t *first_child, int32_t *height, const int32_t *tbox)
 {
     kd_ctx c = {flags, {nbx, nby, nbz}, B, {nx, ny, nz}};
+    /* units of the volumes compared: voxels, or half-voxels (8 per voxel) */
+    const int64_t unit = tbox ? 8 : 1;
     int glo[3] = {0, 0, 0}, ghi[3] = {nbx, nby, nbz};
     int rlo[3], rhi[3];
     *height = 0;
@@ -498,14 +529,14 @@ int64_t orc_kd(const uint8_t *flags, int nbx, int nby, int nbz, int B, int nx, i
     int64_t count = 1, head = 0;
     for (int a = 0; a < 3; ++a) { lo[a] = rlo[a]; hi[a] = rhi[a]; }
     depth[0] = 1;
-    int64_t vroot = kd_volume(&c, rlo, rhi);
+    int64_t vroot = tbox ? kd_tight_volume(&c, tbox, rlo, rhi) : kd_volume(&c, rlo, rhi);
     while (head < count) {
         int64_t i = head++;
         int blo[3], bhi[3];
         for (int a = 0; a < 3; ++a) { blo[a] = lo[3 * i + a]; bhi[a] = hi[3 * i + a]; }
         if (depth[i] > *height) *height = depth[i];
-        int64_t V = kd_volume(&c, blo, bhi);
-        int allowed = halting == 0 ? (10 * V > vroot) : (V > 512);
+        int64_t V = tbox ? kd_tight_volume(&c, tbox, blo, bhi) : kd_volume(&c, blo, bhi);
+        int allowed = halting == 0 ? (10 * V > vroot) : (V > 512 * unit);
         int best_axis = -1, best_plane = 0;
         int64_t best_cost = 0;
         if (allowed) {
@@ -522,8 +553,12 @@ int64_t orc_kd(const uint8_t *flags, int nbx, int nby, int nbz, int B, int nx, i
                     lhi[a] = p;
                     ulo[a] = p;
                     int64_t cost = 0;
-                    if (kd_tight(&c, llo, lhi, tl, th)) cost += kd_volume(&c, tl, th);
-                    if (kd_tight(&c, ulo, uhi, tu, tv)) cost += kd_volume(&c, tu, tv);
+                    if (tbox) {
+                        cost = kd_tight_volume(&c, tbox, llo, lhi) + kd_tight_volume(&c, tbox, ulo, uhi);
+                    } else {
+                        if (kd_tight(&c, llo, lhi, tl, th)) cost += kd_volume(&c, tl, th);
+                        if (kd_tight(&c, ulo, uhi, tu, tv)) cost += kd_volume(&c, tu, tv);
+                    }
                     if (best_axis < 0 || cost < best_cost) {
                         best_axis = a;
                         best_plane = p;
@@ -533,7 +568,7 @@ int64_t orc_kd(const uint8_t *flags, int nbx, int nby, int nbz, int B, int nx, i
             }
             if (best_axis >= 0 && !(best_cost < V)) {
                 best_axis = -1;
-                if (max_leaf > 0 && V > (int64_t)max_leaf * max_leaf * max_leaf) {
+                if (max_leaf > 0 && V > (int64_t)max_leaf * max_leaf * max_leaf * unit) {
                     int64_t best_ext = -1;
                     for (int a = 0; a < 3; ++a) {
                         int e = bhi[a] - blo[a];

@@ -29,7 +29,7 @@ int orc_sort_pairs(uint32_t *, uint32_t *, int64_t);
 int orc_lbvh(const uint32_t *, const uint32_t *, int64_t, int, int, int, int, int, int, uint32_t *, uint32_t *,
              int32_t *, int32_t *, int32_t *);
 int64_t orc_kd(const uint8_t *, int, int, int, int, int, int, int, int, int, int, int64_t, int32_t *, int32_t *,
-               int32_t *, int32_t *, int32_t *, int32_t *);
+               int32_t *, int32_t *, int32_t *, int32_t *, const int32_t *);
 int orc_render(const void *, int, int, int, int, float, float, const float *, int, const orc_camera *, int, int,
                float, float, int, const uint8_t *, int, const int32_t *, int64_t, double *, int64_t *,
                const int32_t *);
@@ -100,9 +100,9 @@ static int run(int dtype, int nx, int ny, int nz, int B, int N)
     int32_t *kax = malloc(sizeof(int32_t) * cap), *kpl = malloc(sizeof(int32_t) * cap),
             *kfc = malloc(sizeof(int32_t) * cap), height = 0;
     const int variants[6][3] = {{0, 0, 4}, {1, 0, 4}, {1, 16, 4}, {1, 0, 2}, {0, 0, 3}, {1, 8, 16}};
-    for (int v = 0; v < 6; ++v)
-        bad += check(orc_kd(flags, nbx, nby, nbz, B, nx, ny, nz, variants[v][0], variants[v][1], variants[v][2], cap,
-                            klo, khi, kax, kpl, kfc, &height) >= 0,
+    for (int v = 0; v < 12; ++v)
+        bad += check(orc_kd(flags, nbx, nby, nbz, B, nx, ny, nz, variants[v % 6][0], variants[v % 6][1],
+                            variants[v % 6][2], cap, klo, khi, kax, kpl, kfc, &height, v < 6 ? NULL : boxes) >= 0,
                      "kd");
     orc_camera cam = {0, {-30.0f, (float)ny * 0.5f, -40.0f}, {0.6f, -0.05f, 0.8f}, {0.01f, 0.0f, -0.008f},
                       {0.0f, -0.012f, 0.0f}};

@@ -938,3 +938,150 @@ def test_render_pixel_list_matches_full_image():
     pix = np.array([[0, 0], [127, 127], [64, 60], [3, 100]], np.int32)
     sub = oracle.render(w["vol"], w["tf"], w["cam"], w["W"], w["H"], pixels=pix)
     assert np.array_equal(sub, img[pix[:, 1], pix[:, 0]])
+
+
+# ---------------------------------------------------------------------------
+# k-d tree with the voxel-tight split cost (Sec. 3.2.2: one tight box per
+# macro cell, unions of them for regions spanning several cells)
+# ---------------------------------------------------------------------------
+
+def _tight_union_volume(tb3, lo, hi):
+    """half-voxel volume of the union of the boxes of bricks [lo, hi) (tb3:
+    [z][y][x][6] boxes, empty = no visible cell), 0 without one"""
+    sub = tb3[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].reshape(-1, 6)
+    sub = sub[(sub[:, 3] > sub[:, 0]) & (sub[:, 4] > sub[:, 1]) & (sub[:, 5] > sub[:, 2])]
+    if len(sub) == 0:
+        return 0
+    ext = sub[:, 3:].max(0).astype(np.int64) - sub[:, :3].min(0).astype(np.int64)
+    return int(np.prod(ext))
+
+
+def check_kd_tight(t, flags, tboxes, B, dims, halting, max_leaf, bins=4):
+    """Every rule of the build with the tight cost, recomputed by brute force
+    over the boxes: regions and children stay brick-tight (prefix counts),
+    every compared volume is the union volume in half-voxel units."""
+    nb = oracle.brick_grid(dims, B)
+    pc = PrefixCount(flags, nb)
+    tb3 = np.asarray(tboxes, np.int64).reshape(nb[2], nb[1], nb[0], 6)
+    m = len(t["axis"])
+    if flags.sum() == 0:
+        assert m == 0
+        return
+    assert m % 2 == 1
+    vroot = _tight_union_volume(tb3, t["lo"][0], t["hi"][0])
+    cover = np.zeros(nb[::-1], int)
+    for i in range(m):
+        lo, hi = [int(v) for v in t["lo"][i]], [int(v) for v in t["hi"][i]]
+        V = _tight_union_volume(tb3, lo, hi)
+        allowed = (10 * V > vroot) if halting == 0 else (V > 512 * 8)
+        cands = []
+        if allowed:
+            for a in range(3):
+                e = hi[a] - lo[a]
+                if e < 2:
+                    continue
+                for p in sorted({lo[a] + (j * e) // bins for j in range(1, bins)} - {lo[a], hi[a]}):
+                    l1, r0 = list(hi), list(lo)
+                    l1[a], r0[a] = p, p
+                    cands.append((_tight_union_volume(tb3, lo, l1) + _tight_union_volume(tb3, r0, hi), a, p))
+        best = min(cands) if cands else None
+        if t["axis"][i] < 0:
+            assert best is None or best[0] >= V
+            if best is not None and max_leaf > 0:
+                assert V <= max_leaf ** 3 * 8
+            cover[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] += 1
+            continue
+        a, p, c = int(t["axis"][i]), int(t["plane"][i]), int(t["first_child"][i])
+        assert best is not None
+        if best[0] < V:
+            assert (a, p) == (best[1], best[2])
+        else:
+            assert max_leaf > 0 and V > max_leaf ** 3 * 8
+            ext = [min(B * hi[q], dims[q]) - B * lo[q] if hi[q] - lo[q] >= 2 else -1 for q in range(3)]
+            assert a == int(np.argmax(ext)) and p == lo[a] + (hi[a] - lo[a]) // 2
+        for side, child in ((0, c), (1, c + 1)):
+            rlo, rhi = list(lo), list(hi)
+            if side == 0:
+                rhi[a] = p
+            else:
+                rlo[a] = p
+            tl, th = pc.tight(rlo, rhi)
+            assert list(t["lo"][child]) == tl and list(t["hi"][child]) == th
+    f3 = flags.reshape(nb[::-1]).astype(bool)
+    assert np.all(cover <= 1) and np.all(cover[f3] == 1)
+
+
+def test_kd_tight_cost_changes_the_plane():
+    # four 8^3 bricks along x (32 x 8 x 8 voxels), bricks 0, 1 and 3 non-empty.
+    # Brick cost: planes 1, 2, 3 cost 4, 3, 3 bricks against the root's 4 ->
+    # split at 2 (tie with 3: smaller plane); the child [0, 2) would cost 2
+    # bricks = its own volume -> leaf.  Voxel-tight boxes: brick 0 visible only
+    # in x [0, 1), brick 1 only in x [15, 16), brick 3 everywhere (y, z full):
+    # per unit of y-z area the root's union is [0, 32) = 32, plane 1 costs
+    # 1 + (32 - 15) = 18, planes 2 and 3 cost 16 + 8 = 24 -> split at 1; the
+    # right child [1, 4) (union [15, 32) = 17 > 512 / 64 = 8 voxels deep)
+    # splits at 2 (1 + 8 = 9 < 17, tie with 3), and both its children
+    # ([1, 2): 1, [3, 4): 8, not above 8) are leaves.
+    flags = np.array([1, 1, 0, 1], np.uint8)
+    tb = np.zeros((4, 6), np.int32)
+    tb[0] = [0, 0, 0, 2, 16, 16]          # half-voxel units
+    tb[1] = [30, 0, 0, 32, 16, 16]
+    tb[3] = [48, 0, 0, 64, 16, 16]
+    dims = (32, 8, 8)
+    brick = oracle.kd(flags, 8, dims, 1, 0, 4)
+    assert len(brick["axis"]) == 3 and brick["height"] == 2
+    assert brick["axis"][0] == 0 and brick["plane"][0] == 2
+    assert list(brick["lo"][1]) == [0, 0, 0] and list(brick["hi"][1]) == [2, 1, 1]
+    assert list(brick["lo"][2]) == [3, 0, 0] and list(brick["hi"][2]) == [4, 1, 1]
+    tight = oracle.kd(flags, 8, dims, 1, 0, 4, tight_boxes=tb)
+    assert len(tight["axis"]) == 5 and tight["height"] == 3
+    assert list(tight["axis"]) == [0, -1, 0, -1, -1]
+    assert list(tight["plane"]) == [1, 0, 2, 0, 0]
+    assert list(tight["first_child"]) == [1, -1, 3, -1, -1]
+    assert [list(v) for v in tight["lo"]] == [[0, 0, 0], [0, 0, 0], [1, 0, 0], [1, 0, 0], [3, 0, 0]]
+    assert [list(v) for v in tight["hi"]] == [[4, 1, 1], [1, 1, 1], [4, 1, 1], [2, 1, 1], [4, 1, 1]]
+    check_kd_tight(tight, flags, tb, 8, dims, 1, 0)
+
+
+def test_kd_tight_cost_without_visible_cells_is_one_leaf():
+    # flagged bricks whose cells are all invisible: every tight volume is 0,
+    # so nothing splits (0 is not below 0) and the root is the only node
+    flags = np.ones(8, np.uint8)
+    tb = np.zeros((8, 6), np.int32)
+    for halting in (0, 1):
+        t = oracle.kd(flags, 8, (16, 16, 16), halting, 0, 4, tight_boxes=tb)
+        assert len(t["axis"]) == 1 and t["axis"][0] == -1
+
+
+def test_kd_tight_cost_full_boxes_equal_brick_cost():
+    # when every flagged brick's tight box is the whole brick, the unions are
+    # the brick-tight boxes and every volume is 8x the brick cost's: the trees
+    # are identical
+    vol = synth.blobs_u8((48, 40, 56), seed=41, n_blobs=5)
+    mn, mx = oracle.brick_minmax(vol, 8)
+    flags = oracle.classify(mn, mx, vol.dtype, synth.tf_ramp(256, start=0.3))
+    nb = oracle.brick_grid((48, 40, 56), 8)
+    tb = np.zeros((flags.size, 6), np.int32)
+    for b in np.flatnonzero(flags):
+        x, y, z = b % nb[0], (b // nb[0]) % nb[1], b // (nb[0] * nb[1])
+        lo = np.array([x, y, z]) * 8
+        hi = np.minimum(lo + 8, [48, 40, 56])
+        tb[b] = np.concatenate([2 * lo, 2 * hi])
+    for halting, mls in ((0, 0), (1, 0), (1, 16)):
+        a = oracle.kd(flags, 8, (48, 40, 56), halting, mls)
+        b = oracle.kd(flags, 8, (48, 40, 56), halting, mls, tight_boxes=tb)
+        for k in ("lo", "hi", "axis", "plane", "first_child"):
+            assert np.array_equal(a[k], b[k]), (halting, mls, k)
+
+
+@pytest.mark.parametrize("bins", [2, 4, 8])
+@pytest.mark.parametrize("halting,max_leaf", [(0, 0), (1, 0), (1, 16)])
+@pytest.mark.parametrize("seed,dims,B", [(0, (48, 40, 56), 8), (1, (37, 29, 33), 4), (2, (64, 48, 40), 16)])
+def test_kd_tight_cost_rules(seed, dims, B, halting, max_leaf, bins):
+    vol = synth.blobs_u8(dims, seed=60 + seed, n_blobs=6)
+    tf = synth.tf_random(70 + seed, 256)
+    mn, mx = oracle.brick_minmax(vol, B)
+    flags = oracle.classify(mn, mx, vol.dtype, tf)
+    tb = oracle.tight_boxes(vol, B, tf, flags)
+    t = oracle.kd(flags, B, dims, halting, max_leaf, bins, tight_boxes=tb)
+    check_kd_tight(t, flags, tb, B, dims, halting, max_leaf, bins)
