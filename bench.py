@@ -524,9 +524,10 @@ def large_volumes(esk, torch, reps=3):
 
 def statistics_table(esk, torch, noise_vol, reps=3):
     """Node counts, heights and rebuild times of the LBVH and of the k-d
-    variants (shallow, deep, deep + MLS 32, deep + MLS 128; 4 bins) on the
-    synthetic stand-ins, 8^3 bricks, one ramp TF (alpha > 0 above s = 0.02):
-    the quantities of the paper's statistics table (Sec. 4.3)."""
+    variants (shallow, deep, deep + MLS 32, deep + MLS 128; 4 bins), each
+    with the brick-tight and the voxel-tight split cost, on the synthetic
+    stand-ins, 8^3 bricks, one ramp TF (alpha > 0 above s = 0.02): the
+    quantities of the paper's statistics table (Sec. 4.3)."""
     import numpy as np
 
     import synth
@@ -540,12 +541,12 @@ def statistics_table(esk, torch, noise_vol, reps=3):
              ("tubes1024_f32", lambda: synth.tubes_torch((1024, 1024, 1024), 0.02, 31)),
              ("menger243_u8", lambda: torch.from_numpy(synth.menger_sponge(4, 3)).cuda())]
 
-    def timed(ctx, build, kd=None):
+    def timed(ctx, build, kd=None, kd_cost="brick"):
         times = []
         for _ in range(reps):
             torch.cuda.synchronize()
             t = time.perf_counter()
-            ctx.set_tf(tf, build=build, kd=kd)
+            ctx.set_tf(tf, build=build, kd=kd, kd_cost=kd_cost)
             torch.cuda.synchronize()
             times.append((time.perf_counter() - t) * 1e3)
         return round(statistics.median(times), 4)
@@ -564,6 +565,11 @@ def statistics_table(esk, torch, noise_vol, reps=3):
             ms = timed(ctx, ("kd",), kd)
             st = ctx.stats()
             rec[f"kd_{vname}"] = {"nodes": st["kd_nodes"], "height": st["kd_height"], "rebuild_ms": ms}
+            # the voxel-tight split cost (Sec. 3.2.2): same rules, union volumes
+            # of the bricks' voxel-tight boxes (the rebuild includes those boxes)
+            ms = timed(ctx, ("kd",), kd, kd_cost="tight")
+            st = ctx.stats()
+            rec[f"kd_{vname}_tight_cost"] = {"nodes": st["kd_nodes"], "height": st["kd_height"], "rebuild_ms": ms}
         out[name] = rec
         ctx.close()
         del vol, ctx
@@ -1008,6 +1014,25 @@ def main():
         ctx.sync()
         times.append((time.perf_counter() - t) * 1e3)
     tight["rebuild_all_ms"] = round(statistics.median(times), 4)
+    times = []
+    for i in range(5):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ctx.set_tf(dtfs[j], build=("kd",), kd=kd, kd_cost="tight")
+        ctx.sync()
+        times.append((time.perf_counter() - t) * 1e3)
+    tight["kd_tight_cost_rebuild_ms"] = round(statistics.median(times), 4)
+    st_t = ctx.stats()
+    tight["kd_tight_cost_nodes"], tight["kd_tight_cost_height"] = st_t["kd_nodes"], st_t["kd_height"]
+    rt = []
+    for _ in range(3):
+        e0.record(stream)
+        ctx.render(cams[j], W, H, accel="kd", out=outs["lbvh"])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        rt.append(e0.elapsed_time(e1))
+    tight["kd_tight_cost_render_ms"] = round(statistics.median(rt), 4)
+    ctx.set_tf(dtfs[j], build=ACCELS, kd=kd, tight=True)
     for a in ("lbvh", "kd"):
         rt = []
         for _ in range(3):

@@ -99,6 +99,17 @@ enum { ESK_CLASSIFY_VOXEL = 0x100 };
  * voxel of the non-empty bricks per TF change. */
 enum { ESK_TIGHT_BOXES = 0x200 };
 
+/* Voxel-tight split cost of the k-d build, OR-ed into the build mask with
+ * ESK_ACCEL_KD (implies ESK_TIGHT_BOXES): the cost of a candidate plane is
+ * the volume of the union of the voxel-tight boxes of the bricks left of it
+ * plus that of the bricks right of it -- the GPU builder of Sec. 3.2.2,
+ * which keeps one tight box per macro cell -- and every other volume the
+ * build compares (the node's, against which a split must win; the root's,
+ * for shallow halting; the 8^3-voxel and max_leaf^3 limits) is such a union
+ * volume too.  Node regions, candidate planes, the maximum-leaf-size plane
+ * and the children stay on the brick raster (brick-tight boxes). */
+enum { ESK_KD_TIGHT_COST = 0x400 };
+
 /* k-d build parameters (Sec. 4.3).
  *  halting:  0 = shallow: split only while 10*V(node) > V(root);
  *            1 = deep:    split only while V(node) > 8^3 voxels.

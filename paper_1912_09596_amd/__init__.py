@@ -25,6 +25,7 @@ U8, U16, F16, F32 = 0, 1, 2, 3
 NONE, GRID, LBVH, KD, HYBRID = 0, 1, 2, 4, 8
 CLASSIFY_VOXEL = 0x100      # build-mask bit: per-voxel vote instead of brick min/max
 TIGHT_BOXES = 0x200         # build-mask bit: march LBVH/k-d leaves inside voxel-tight boxes
+KD_TIGHT_COST = 0x400       # build-mask bit: k-d split cost from the voxel-tight boxes (implies TIGHT_BOXES)
 ACCEL = {"none": NONE, "grid": GRID, "lbvh": LBVH, "kd": KD, "hybrid": HYBRID}
 # what a rebuild must build for each render mode (the hybrid grid renders the k-d tree + grid)
 BUILD = {"grid": GRID, "lbvh": LBVH, "kd": KD, "hybrid": KD}
@@ -231,18 +232,23 @@ class Context:
         return self
 
     def set_tf(self, tf, build=("grid", "lbvh", "kd"), kd: Kd | None = None, classify: str = "minmax",
-               tight: bool = False):
+               tight: bool = False, kd_cost: str = "brick"):
         """tf: contiguous [N, 4] float32 device tensor; rebuilds the requested
         structures.  classify: "minmax" (conservative brick value ranges) or
         "voxel" (the per-voxel vote).  tight: march LBVH and k-d leaves inside
-        voxel-tight boxes."""
+        voxel-tight boxes.  kd_cost: "brick" (brick-tight boxes) or "tight"
+        (the voxel-tight boxes' unions, which also turns `tight` on)."""
         import torch
         if not isinstance(tf, torch.Tensor) or tf.dim() != 2 or tf.shape[1] != 4:
             raise ValueError("TF must be an [N, 4] float32 tensor")
         _require(tf, "TF", self.device, torch.float32)
         if classify not in ("minmax", "voxel"):
             raise ValueError("classify must be 'minmax' or 'voxel'")
+        if kd_cost not in ("brick", "tight"):
+            raise ValueError("kd_cost must be 'brick' or 'tight'")
         mask = (CLASSIFY_VOXEL if classify == "voxel" else 0) | (TIGHT_BOXES if tight else 0)
+        if kd_cost == "tight" and "kd" in build:
+            mask |= KD_TIGHT_COST
         for b in build:
             mask |= BUILD[b]
         kp = None

@@ -118,6 +118,7 @@ struct esk_ctx {
     uint32_t kd_count = 0;
     bool kd_on_device = false;  // k-d build enqueued; completion and height not yet read back
     esk_kd_params kd_params{1, 0, 4};
+    bool kd_tight_cost = false; // the last k-d build used the voxel-tight split cost
     // host staging of batched render arguments (pinned; reused once the
     // previous upload has completed)
     RenderArgs *staging = nullptr;
@@ -486,6 +487,7 @@ static KdArgs kd_args(esk_ctx *c, const esk_kd_params *p)
     k.cap = 2 * L.nb;
     k.tight = c->tight ? 1 : 0;
     k.tbox = at<uint4>(c, L.tbox);
+    k.tight_cost = c->kd_tight_cost ? 1 : 0;
     if (p) {
         k.halting = p->halting;
         k.max_leaf = p->max_leaf;
@@ -501,8 +503,13 @@ esk_status esk_set_transfer_function(esk_ctx *c, const float *d_rgba, int n_entr
     if (!d_rgba) return fail(c, ESK_EINVAL, "TF pointer is null");
     if ((reinterpret_cast<uintptr_t>(d_rgba) & 15) != 0) return fail(c, ESK_EINVAL, "TF must be 16-byte aligned");
     if (n_entries < 2) return fail(c, ESK_EINVAL, "TF needs at least 2 entries (got %d)", n_entries);
-    if (build_mask & ~(ESK_ACCEL_GRID | ESK_ACCEL_LBVH | ESK_ACCEL_KD | ESK_CLASSIFY_VOXEL | ESK_TIGHT_BOXES))
+    if (build_mask &
+        ~(ESK_ACCEL_GRID | ESK_ACCEL_LBVH | ESK_ACCEL_KD | ESK_CLASSIFY_VOXEL | ESK_TIGHT_BOXES | ESK_KD_TIGHT_COST))
         return fail(c, ESK_EINVAL, "unknown bits in build_mask 0x%x", build_mask);
+    if ((build_mask & ESK_KD_TIGHT_COST) && !(build_mask & ESK_ACCEL_KD))
+        return fail(c, ESK_EINVAL, "ESK_KD_TIGHT_COST needs ESK_ACCEL_KD");
+    // the tight split cost reads the bricks' voxel-tight boxes
+    if (build_mask & ESK_KD_TIGHT_COST) build_mask |= ESK_TIGHT_BOXES;
     if (build_mask & ESK_ACCEL_KD) {
         if (!kd) return fail(c, ESK_EINVAL, "k-d build requested without parameters");
         if (kd->halting != 0 && kd->halting != 1) return fail(c, ESK_EINVAL, "kd halting must be 0 or 1");
@@ -552,6 +559,7 @@ esk_status esk_set_transfer_function(esk_ctx *c, const float *d_rgba, int n_entr
         if (e != hipSuccess) return hip_check(c, e, "LBVH launch");
     }
     if (build_mask & ESK_ACCEL_KD) {
+        c->kd_tight_cost = (build_mask & ESK_KD_TIGHT_COST) != 0;
         KdArgs k = kd_args(c, kd);
         c->kd_params = *kd;
         // fork: the k-d build needs the flags only; it runs on the auxiliary

@@ -46,7 +46,9 @@ struct DevHeader {
     uint32_t kd_begin;     // current level [begin, end)
     uint32_t kd_end;
     uint32_t kd_ticket;    // blocks of the current k-d level launch that finished
-    uint32_t pad[57];
+    uint32_t kd_vroot_lo;  // voxel-tight split cost: the root's union volume
+    uint32_t kd_vroot_hi;  //   (half-voxel units, 64 bits)
+    uint32_t pad[55];
 };
 static_assert(sizeof(DevHeader) == 256, "header is one 256-byte slot");
 
@@ -165,6 +167,7 @@ struct KdArgs {
     int64_t cap;           // node capacity of the k-d arrays (2 nb)
     int tight;             // 1: leaf render boxes are unions of the bricks' voxel-tight boxes
     const uint4 *tbox;     // per brick: packed voxel-tight box
+    int tight_cost;        // 1: split cost and compared volumes from the unions of the voxel-tight boxes
 };
 
 bool kd_small(const KdArgs &k);

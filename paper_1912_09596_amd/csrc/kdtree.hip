@@ -333,44 +333,19 @@ inline int kd_level_blocks(const KdArgs &k)
     return (int)std::min<int64_t>(1024, std::max<int64_t>(32, nb / 1024));
 }
 
-// The binary searches read the prefix count through L2 (staging the whole
-// table in LDS per workgroup was measured slower: every busy workgroup of a
-// level copies it again).
-__global__ __launch_bounds__(256) void k_kd_level(KdArgs k)
+// Breadth-first numbering of the children of level [begin, end) by one
+// 256-thread workgroup, the last of the level's launch to finish (every
+// split flag of the level is visible to it): children in parent order, the
+// first child of each splitting parent, the ordered list of splitting
+// parents, and the next level's bounds in the header.
+__device__ void number_children(const KdArgs &k, uint32_t begin, uint32_t end, uint32_t *scratch)
 {
-    __shared__ int16_t tb[4][kMaxCand + 1][2][6];
-    __shared__ uint32_t scratch[5];
-    __shared__ uint32_t last;
-    const uint32_t begin = k.hdr->kd_begin, end = k.hdr->kd_end;
-    if (begin == end) return;
-    const int wave = threadIdx.x >> 6;
-    const int64_t vroot = root_volume(k);
-    for (int64_t node = (int64_t)begin + (int64_t)blockIdx.x * 4 + wave; node < end;
-         node += (int64_t)gridDim.x * 4) {
-        eval_node(k, (const int32_t *)k.S, node, (int64_t)begin, vroot, tb[wave]);
-    }
-    // the level's emitter may run on another XCD, whose L2 is not coherent
-    // with this one: every wave waits for its own stores to reach this XCD's
-    // L2, then one release per block (thread 0) writes them back
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t old = __hip_atomic_fetch_add(&k.hdr->kd_ticket, 1u, __ATOMIC_ACQ_REL,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-        last = (old == gridDim.x - 1) ? 1u : 0u;
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    // breadth-first numbering of the children, 256 threads
     const int64_t width = (int64_t)end - begin;
     const int64_t per = (width + 255) / 256;
     const int64_t i0 = begin + threadIdx.x * per;
     const int64_t i1 = min((int64_t)end, i0 + per);
-    // plain loads: the fence above (acquire, agent scope) follows the other
-    // blocks' release through the ticket, so their flags are visible; eight
-    // at a time so the loads overlap instead of waiting one by one
+    // plain loads of the flags (the caller's acquire made them visible),
+    // eight at a time so the loads overlap instead of waiting one by one
     constexpr int U = 8;
     uint32_t c = 0;
     {
@@ -424,6 +399,216 @@ __global__ __launch_bounds__(256) void k_kd_level(KdArgs k)
         k.hdr->kd_ticket = 0;
         __threadfence();
     }
+}
+
+// The last workgroup of a level launch to arrive (ticket counter) numbers
+// the children.  Every wave first waits for its own stores; one agent-scope
+// release per workgroup then publishes them (on a multi-XCD part a release
+// writes back the XCD's L2, so it is not issued per node).
+__device__ inline bool last_of_level(const KdArgs &k, uint32_t *last)
+{
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t old = __hip_atomic_fetch_add(&k.hdr->kd_ticket, 1u, __ATOMIC_ACQ_REL,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        *last = (old == gridDim.x - 1) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (!*last) return false;
+    // plain loads of the flags follow: this acquire (agent scope) follows the
+    // other blocks' release through the ticket, so their flags are visible
+    __threadfence();
+    return true;
+}
+
+// The binary searches read the prefix count through L2 (staging the whole
+// table in LDS per workgroup was measured slower: every busy workgroup of a
+// level copies it again).
+__global__ __launch_bounds__(256) void k_kd_level(KdArgs k)
+{
+    __shared__ int16_t tb[4][kMaxCand + 1][2][6];
+    __shared__ uint32_t scratch[5];
+    __shared__ uint32_t last;
+    const uint32_t begin = k.hdr->kd_begin, end = k.hdr->kd_end;
+    if (begin == end) return;
+    const int wave = threadIdx.x >> 6;
+    const int64_t vroot = root_volume(k);
+    for (int64_t node = (int64_t)begin + (int64_t)blockIdx.x * 4 + wave; node < end;
+         node += (int64_t)gridDim.x * 4) {
+        eval_node(k, (const int32_t *)k.S, node, (int64_t)begin, vroot, tb[wave]);
+    }
+    if (last_of_level(k, &last)) number_children(k, begin, end, scratch);
+}
+
+// ---------------------------------------------------------------------------
+// The voxel-tight split cost (Sec. 3.2.2: the GPU builder keeps one tight box
+// per macro cell and reduces over the cells of a region).  One workgroup per
+// node: the voxel-tight boxes of the flagged bricks in the node's brick box
+// are reduced into per-slab unions along each axis (LDS, 6 ints per brick
+// slab, atomics), so the union left and right of every candidate plane is a
+// prefix / suffix over one axis's slabs.  Every volume the rules compare is
+// the half-voxel volume of such a union (0 without a visible cell): a side's
+// cost, the node's own (split iff the best cost is below it), the root's
+// (shallow halting), 8^3 and MLS^3 voxels (x 8).  Regions, candidate planes,
+// the maximum-leaf-size plane and the children (brick-tight, from the prefix
+// count) stay on the brick raster.
+// ---------------------------------------------------------------------------
+
+__device__ inline int64_t half_volume(const int l[3], const int h[3])
+{
+    if (h[0] <= l[0] || h[1] <= l[1] || h[2] <= l[2]) return 0;
+    return (int64_t)(h[0] - l[0]) * (h[1] - l[1]) * (h[2] - l[2]);
+}
+
+// union of the slab boxes [s0, s1) (6 ints each); empty -> l > h
+__device__ inline void slab_union(const int32_t *slab, int s0, int s1, int l[3], int h[3])
+{
+    for (int q = 0; q < 3; ++q) {
+        l[q] = 0x7fffffff;
+        h[q] = -0x7fffffff;
+    }
+    for (int s = s0; s < s1; ++s)
+        for (int q = 0; q < 3; ++q) {
+            l[q] = min(l[q], slab[6 * s + q]);
+            h[q] = max(h[q], slab[6 * s + 3 + q]);
+        }
+}
+
+__global__ __launch_bounds__(256) void k_kd_level_tight(KdArgs k)
+{
+    extern __shared__ int32_t slab[];   // [nbx + nby + nbz][6]
+    __shared__ int32_t box[6];
+    __shared__ int64_t cost[kMaxCand];
+    __shared__ int64_t vnode;
+    __shared__ int32_t choice[2];
+    __shared__ int32_t child[2][6];
+    __shared__ uint32_t scratch[5];
+    __shared__ uint32_t last;
+    const uint32_t begin = k.hdr->kd_begin, end = k.hdr->kd_end;
+    if (begin == end) return;
+    const int t = threadIdx.x;
+    const int64_t vroot_prev = (int64_t)(((uint64_t)k.hdr->kd_vroot_hi << 32) | k.hdr->kd_vroot_lo);
+    const int32_t *S = k.S;
+    for (int64_t node = (int64_t)begin + blockIdx.x; node < end; node += gridDim.x) {
+        if (t == 0) {
+            if (node == 0) {
+                for (int q = 0; q < 3; ++q) {
+                    box[q] = k.lo[q];
+                    box[3 + q] = k.hi[q];
+                }
+            } else {
+                // child of the (r/2)-th splitting node of the level above
+                const int64_t r = node - begin;
+                const int64_t p = k.plist[r >> 1];
+                const int32_t *cb = &k.clo[12 * p + 6 * (r & 1)];
+                for (int q = 0; q < 6; ++q) box[q] = cb[q];
+                for (int q = 0; q < 3; ++q) {
+                    k.lo[3 * node + q] = box[q];
+                    k.hi[3 * node + q] = box[3 + q];
+                }
+            }
+        }
+        __syncthreads();
+        const int lo[3] = {box[0], box[1], box[2]}, hi[3] = {box[3], box[4], box[5]};
+        const int e[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
+        const int off[3] = {0, e[0], e[0] + e[1]};
+        const int nsl = e[0] + e[1] + e[2];
+        for (int i = t; i < 6 * nsl; i += 256) slab[i] = (i % 6) < 3 ? 0x7fffffff : -0x7fffffff;
+        __syncthreads();
+        const int64_t bricks = (int64_t)e[0] * e[1] * e[2];
+        for (int64_t i = t; i < bricks; i += 256) {
+            const int c[3] = {lo[0] + (int)(i % e[0]), lo[1] + (int)((i / e[0]) % e[1]),
+                              lo[2] + (int)(i / ((int64_t)e[0] * e[1]))};
+            const int64_t b = c[0] + (int64_t)k.nb[0] * (c[1] + (int64_t)k.nb[1] * c[2]);
+            if (!k.flags[b]) continue;
+            const uint4 w = k.tbox[b];
+            int l2[3], h2[3];
+            unpack_box_u(w.x, w.y, w.z, l2, h2);
+            if (!(h2[0] > l2[0] && h2[1] > l2[1] && h2[2] > l2[2])) continue;   // no visible cell
+            for (int a = 0; a < 3; ++a) {
+                int32_t *sl = &slab[6 * (off[a] + c[a] - lo[a])];
+                for (int q = 0; q < 3; ++q) {
+                    atomicMin(&sl[q], l2[q]);
+                    atomicMax(&sl[3 + q], h2[q]);
+                }
+            }
+        }
+        __syncthreads();
+        if (t == 0) {
+            int l[3], h[3];
+            slab_union(slab, 0, e[0], l, h);
+            vnode = half_volume(l, h);
+        }
+        __syncthreads();
+        const int64_t V = vnode;
+        const int64_t vroot = node == 0 ? V : vroot_prev;
+        const bool allowed = k.halting == 0 ? (10 * V > vroot) : (V > 512 * 8);
+        int da = 0, dp = 0;
+        const int ncand = allowed ? candidate(lo, hi, k.bins, -1, &da, &dp) : 0;
+        if (t < ncand) {
+            int a = 0, p = 0;
+            candidate(lo, hi, k.bins, t, &a, &p);
+            int l[3], h[3];
+            slab_union(slab, off[a], off[a] + p - lo[a], l, h);
+            int64_t c2 = half_volume(l, h);
+            slab_union(slab, off[a] + p - lo[a], off[a] + e[a], l, h);
+            cost[t] = c2 + half_volume(l, h);
+        }
+        __syncthreads();
+        if (t == 0) {
+            int axis = -1, plane = 0;
+            if (ncand > 0) {
+                int best = 0;
+                for (int i = 1; i < ncand; ++i)
+                    if (cost[i] < cost[best]) best = i;   // ties: the lower index
+                if (cost[best] < V) {
+                    candidate(lo, hi, k.bins, best, &axis, &plane);
+                } else if (k.max_leaf > 0 && V > (int64_t)k.max_leaf * k.max_leaf * k.max_leaf * 8) {
+                    // maximum leaf size: middle of the axis with the largest voxel extent
+                    int64_t best_ext = -1;
+                    for (int a = 0; a < 3; ++a) {
+                        if (e[a] < 2) continue;
+                        const int64_t ext = (int64_t)min(k.B * hi[a], k.n[a]) - (int64_t)k.B * lo[a];
+                        if (ext > best_ext) {
+                            best_ext = ext;
+                            axis = a;
+                            plane = lo[a] + e[a] / 2;
+                        }
+                    }
+                }
+            }
+            choice[0] = axis;
+            choice[1] = plane;
+            if (node == 0) {
+                k.hdr->kd_vroot_lo = (uint32_t)(uint64_t)V;
+                k.hdr->kd_vroot_hi = (uint32_t)((uint64_t)V >> 32);
+            }
+        }
+        __syncthreads();
+        const int axis = choice[0], plane = choice[1];
+        if (axis >= 0 && t < 12) {
+            // the children: brick-tight boxes of the two sides (prefix count)
+            const int side = t / 6, face = t % 6;
+            int rl[3] = {lo[0], lo[1], lo[2]}, rh[3] = {hi[0], hi[1], hi[2]};
+            if (side == 0) rh[axis] = plane; else rl[axis] = plane;
+            child[side][face] = tight_face(k, S, rl, rh, face);
+        }
+        __syncthreads();
+        if (t == 0) {
+            k.axis[node] = axis;
+            k.plane[node] = axis >= 0 ? plane : 0;
+            k.split[node] = axis >= 0 ? 1 : 0;
+            if (axis >= 0)
+                for (int sd = 0; sd < 2; ++sd)
+                    for (int f = 0; f < 6; ++f) k.clo[12 * node + 6 * sd + f] = child[sd][f];
+            else
+                k.first[node] = -1;
+        }
+        __syncthreads();   // box, slabs and shared results are reused by the next node
+    }
+    if (last_of_level(k, &last)) number_children(k, begin, end, scratch);
 }
 
 // render box of node m from its brick box: voxels clipped to the volume, in
@@ -565,6 +750,18 @@ hipError_t launch_kd_prefix_root_small(const KdArgs &k, hipStream_t s)
 hipError_t launch_kd_levels(const KdArgs &k, int count, hipStream_t s)
 {
     const int blocks = kd_level_blocks(k);
+    if (k.tight_cost) {
+        // per-slab unions of one node: 6 ints per brick slab of each axis
+        const size_t lds = sizeof(int32_t) * 6 * ((size_t)k.nb[0] + k.nb[1] + k.nb[2]);
+        if (lds > 65536) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_kd_level_tight),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        for (int i = 0; i < count; ++i)
+            hipLaunchKernelGGL(k_kd_level_tight, dim3(blocks), dim3(256), lds, s, k);
+        return hipGetLastError();
+    }
     for (int i = 0; i < count; ++i) hipLaunchKernelGGL(k_kd_level, dim3(blocks), dim3(256), 0, s, k);
     return hipGetLastError();
 }

@@ -105,7 +105,9 @@ def test_tf_and_render_validation():
     assert st(v.c, FAKE, 256, esk.KD | esk.LBVH, ctypes.byref(kd)) == esk.ESTATE
     # option bits: per-voxel vote and voxel-tight boxes are accepted, others not
     assert st(v.c, FAKE, 256, esk.LBVH | esk.CLASSIFY_VOXEL | esk.TIGHT_BOXES, None) == esk.ESTATE
-    assert st(v.c, FAKE, 256, esk.LBVH | 0x400, None) == esk.EINVAL
+    assert st(v.c, FAKE, 256, esk.LBVH | 0x800, None) == esk.EINVAL
+    assert st(v.c, FAKE, 256, esk.LBVH | esk.KD_TIGHT_COST, None) == esk.EINVAL     # needs the k-d tree
+    assert st(v.c, FAKE, 256, esk.KD | esk.KD_TIGHT_COST, ctypes.byref(kd)) == esk.ESTATE
     assert st(v.c, FAKE, 256, esk.HYBRID, None) == esk.EINVAL      # a render mode, not a structure
     cam = esk.camera_struct(dict(ortho=0, eye=[0, 0, -10], dir00=[0, 0, 1], du=[0.01, 0, 0], dv=[0, -0.01, 0]))
     r = L.esk_render

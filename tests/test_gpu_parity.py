@@ -491,3 +491,53 @@ def test_compaction_on_export():
             sk, si = oracle.sort_pairs(keys, ids)
             assert np.array_equal(ctx.export("sorted_keys"), sk)
             assert np.array_equal(ctx.export("sorted_ids"), si)
+
+
+@pytest.mark.parametrize("dims,B,dtype,seed", [
+    ((64, 64, 64), 8, np.uint8, 0), ((61, 47, 53), 4, np.uint16, 1), ((96, 80, 72), 16, np.float32, 2),
+    ((130, 66, 40), 8, np.float16, 3),
+])
+def test_kd_tight_split_cost(dims, B, dtype, seed):
+    """The k-d build with the voxel-tight split cost (Sec. 3.2.2): every node
+    bit-exact against the oracle's build from its own tight boxes, for
+    shallow, deep and MLS trees and 4 or 8 bins; it differs from the
+    brick-cost tree somewhere in the set; every mode still reproduces the
+    full march bit for bit."""
+    torch = _torch()
+    log(f"case: k-d tight cost {dims} B={B} {np.dtype(dtype).name}")
+    base = synth.blobs_u8(dims, seed=140 + seed, n_blobs=7, cut=30)
+    if dtype == np.uint8:
+        vol = base
+    elif dtype == np.uint16:
+        vol = (base.astype(np.uint16) * 257).astype(np.uint16)
+    else:
+        vol = (base.astype(np.float64) / 255.0).astype(dtype)
+    tf = synth.tf_random(seed + 90, 256)
+    esk, ctx = make_ctx()
+    ctx.set_volume(to_dev(vol), B, max_tf=256)
+    mn, mx = oracle.brick_minmax(vol, B)
+    flags = oracle.classify(mn, mx, vol.dtype, tf)
+    boxes = oracle.tight_boxes(vol, B, tf, flags)
+    W, H = 64, 48
+    cam = synth.perspective(dims, W, H, synth.view_direction(seed + 21))
+    differs = False
+    for halting, mls, bins in ((1, 0, 4), (0, 0, 4), (1, 16, 4), (1, 0, 8)):
+        ctx.set_tf(to_dev(tf), build=("grid", "lbvh", "kd"), kd=esk.Kd(halting, mls, bins), kd_cost="tight")
+        torch.cuda.synchronize()
+        assert np.array_equal(ctx.export("tight"), boxes)
+        k = oracle.kd(flags, B, dims, halting, mls, bins, tight_boxes=boxes)
+        kb = oracle.kd(flags, B, dims, halting, mls, bins)
+        differs = differs or len(k["axis"]) != len(kb["axis"]) or not np.array_equal(k["plane"], kb["plane"])
+        for name in ("lo", "hi", "axis", "plane"):
+            assert np.array_equal(ctx.export("kd_" + name), k[name]), (halting, mls, bins, name)
+        st = ctx.stats()
+        assert st["kd_nodes"] == len(k["axis"]) and st["kd_height"] == k["height"]
+        full = ctx.render(cam, W, H, accel="none").cpu().numpy()
+        for accel in ("kd", "hybrid"):
+            img = ctx.render(cam, W, H, accel=accel).cpu().numpy()
+            assert np.array_equal(img, full), (halting, mls, bins, accel)
+        log(f"  halting={halting} mls={mls} bins={bins}: tight-cost nodes {len(k['axis'])} (height "
+            f"{k['height']}), brick-cost nodes {len(kb['axis'])} (height {kb['height']})")
+    ref = oracle.render(vol, tf, cam, W, H)
+    assert np.abs(full.astype(np.float64) - ref).max() <= TOL
+    assert differs
