@@ -198,16 +198,21 @@ struct RenderArgs {
     int stack_cap;
 };
 
-// Render workgroups cover tile^2 pixels, one wave per 8x8 pixels: one-wave
-// 8x8 tiles for every mode (fine-grained scheduling balances the very
-// uneven per-tile work, and small images still spread over every CU; 16x16
-// tiles of four waves measured the same for the trees at 1080p and up to 3x
-// slower at 128x128).
+// Render workgroups cover one 8x8-pixel tile (fine-grained scheduling
+// balances the very uneven per-tile work, and small images still spread over
+// every CU; 16x16 tiles measured the same for the trees at 1080p and up to
+// 3x slower at 128x128).  A workgroup holds kRaySegments waves: the sample
+// sequence of every ray of a long tile is split into that many consecutive
+// segments, one per wave, composited separately and combined front to back,
+// so a tile whose rays cross much non-empty space no longer bounds the whole
+// frame on one wave's instruction stream; a short tile keeps one wave and the
+// other ends at once.  Every mode splits alike.
+constexpr int kRaySegments = 2;
+// a tile is split in S = clamp(K / kRaySegLen, 1, kRaySegments) segments,
+// K the lattice samples of its longest ray
+constexpr int kRaySegLen = 256;
 __host__ __device__ constexpr int render_tile_for(int) { return 8; }
-__host__ __device__ constexpr int render_threads_for(int accel)
-{
-    return (render_tile_for(accel) / 8) * (render_tile_for(accel) / 8) * 64;
-}
+__host__ __device__ constexpr int render_threads_for(int) { return 64 * kRaySegments; }
 
 // dynamic LDS of one render workgroup: [TF (N <= 1024)][traversal stack]
 __host__ __device__ constexpr size_t render_lds_bytes(int accel, int N, bool tf_lds, int stack_cap)

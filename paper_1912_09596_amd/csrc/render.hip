@@ -40,6 +40,7 @@ struct Ray {
     float o[3], d[3];
     float inv[3];   // 1/d (0 where d == 0): conservative tests only
     float t0, tx;
+    float clo, chi;   // the t range of the samples this wave marches (its segment)
     // the ray in half-voxel units (o2 = 2 o, inv2 = inv / 2): slab values
     // against half-unit box bounds equal the voxel-unit ones bit for bit
     // (scaling by 2 commutes with rounding), without converting each bound
@@ -286,7 +287,7 @@ __device__ inline bool hit_box(const Ray &r, float dt, const int lo[3], const in
     }
     float tn, tf;
     slab_half(r, l, h, tn, tf);
-    return tn <= tf + dt && tf >= r.t0 - dt && tn <= r.tx + dt;
+    return tn <= tf + dt && tf >= r.clo - dt && tn <= r.chi + dt;
 }
 
 struct GridRef {
@@ -417,12 +418,15 @@ __device__ inline void leaf_range(const Ray &r, float dt, const int lo[3], const
 // samples of the lattice that fall in the leaf box [lo/2, hi/2), found with
 // the macrocell grid (hybrid grid): only those in non-empty bricks
 template <typename T, typename IDX>
-__device__ inline void march_leaf_grid(const Ray &r, float dt, const int lo[3], const int hi[3], const GridRef &gr,
-                                       const T *__restrict__ vol, const Vol &v, const Shade &s, Accum &acc)
+__device__ inline void march_leaf_grid(const Ray &r, float dt, int ks, int ke, const int lo[3], const int hi[3],
+                                       const GridRef &gr, const T *__restrict__ vol, const Vol &v, const Shade &s,
+                                       Accum &acc)
 {
     int ka, kb;
     float bl[3], bh[3];
     leaf_range(r, dt, lo, hi, ka, kb, bl, bh);
+    ka = max(ka, ks);
+    kb = min(kb, ke);
     if (ka < kb) march_grid<T, IDX>(r, dt, ka, kb, bl, bh, gr, vol, v, s, acc);
 }
 
@@ -446,10 +450,9 @@ struct Trav {
 
 // Ordered traversal of a binary hierarchy stored as RNode records (LBVH or
 // k-d): near child first by the sign of the direction along the node's
-// split axis, far child on an LDS stack (lane-interleaved).  Descends to the
+// split axis, far child on the wave's LDS stack (lane-interleaved).  Descends to the
 // lane's next leaf (lo/hi: its box; popped leaves fetch their packed box);
 // false once the hierarchy is exhausted.
-template <int NT>
 __device__ inline bool next_leaf(const Ray &r, float dt, const RNode *__restrict__ nodes,
                                  const uint4 *__restrict__ leafbox, int *stk, int cap, Trav &tr, int lo[3],
                                  int hi[3])
@@ -458,7 +461,7 @@ __device__ inline bool next_leaf(const Ray &r, float dt, const RNode *__restrict
         if (!tr.have) {
             if (tr.sp == 0) return false;
             --tr.sp;
-            tr.cur = (uint32_t)stk[tr.sp * NT + threadIdx.x];
+            tr.cur = (uint32_t)stk[tr.sp * 64 + (threadIdx.x & 63)];
             if (tr.cur & kLeaf) {
                 const uint4 b = leafbox[tr.cur & kIndexMask];
                 unpack_box(b.x, b.y, b.z, lo, hi);
@@ -484,7 +487,7 @@ __device__ inline bool next_leaf(const Ray &r, float dt, const RNode *__restrict
         const uint32_t nr = flip ? c1 : c0, fr = flip ? c0 : c1;
         if (hn || hf) {
             if (hn && hf && tr.sp < cap) {
-                stk[tr.sp * NT + threadIdx.x] = (int)fr;
+                stk[tr.sp * 64 + (threadIdx.x & 63)] = (int)fr;
                 ++tr.sp;
             }
             tr.cur = hn ? nr : fr;
@@ -506,8 +509,8 @@ __device__ inline bool next_leaf(const Ray &r, float dt, const RNode *__restrict
 // leaves rather than its longest leaf twice (measured: three or four leaves
 // per round gain nothing more).  HYB: each leaf is marched with the
 // macrocell grid inside it (hybrid grid).
-template <typename T, typename IDX, bool HYB, int NT>
-__device__ inline void traverse(const Ray &r, float dt, const RNode *__restrict__ nodes,
+template <typename T, typename IDX, bool HYB>
+__device__ inline void traverse(const Ray &r, float dt, int ks, int ke, const RNode *__restrict__ nodes,
                                 const uint4 *__restrict__ leafbox, const GridRef &gr, uint32_t root, int lo[3], int hi[3],
                                 int *stk, int cap, const T *__restrict__ vol, const Vol &v, const Shade &s,
                                 Accum &acc)
@@ -515,17 +518,22 @@ __device__ inline void traverse(const Ray &r, float dt, const RNode *__restrict_
     if (!hit_box(r, dt, lo, hi)) return;
     Trav tr{root, true, 0};
     while (true) {
-        if (!next_leaf<NT>(r, dt, nodes, leafbox, stk, cap, tr, lo, hi)) return;
+        if (!next_leaf(r, dt, nodes, leafbox, stk, cap, tr, lo, hi)) return;
         int lo2[3], hi2[3];
-        const bool two = next_leaf<NT>(r, dt, nodes, leafbox, stk, cap, tr, lo2, hi2);
+        const bool two = next_leaf(r, dt, nodes, leafbox, stk, cap, tr, lo2, hi2);
         if constexpr (HYB) {
-            march_leaf_grid<T, IDX>(r, dt, lo, hi, gr, vol, v, s, acc);
-            if (two) march_leaf_grid<T, IDX>(r, dt, lo2, hi2, gr, vol, v, s, acc);
+            march_leaf_grid<T, IDX>(r, dt, ks, ke, lo, hi, gr, vol, v, s, acc);
+            if (two) march_leaf_grid<T, IDX>(r, dt, ks, ke, lo2, hi2, gr, vol, v, s, acc);
         } else {
             int ka1, kb1, ka2 = 0, kb2 = 0;
             float bl1[3], bh1[3], bl2[3] = {0.0f, 0.0f, 0.0f}, bh2[3] = {0.0f, 0.0f, 0.0f};
             leaf_range(r, dt, lo, hi, ka1, kb1, bl1, bh1);
             if (two) leaf_range(r, dt, lo2, hi2, ka2, kb2, bl2, bh2);
+            // the wave's segment of the sample sequence
+            ka1 = max(ka1, ks);
+            kb1 = min(kb1, ke);
+            ka2 = max(ka2, ks);
+            kb2 = min(kb2, ke);
             const int n1 = max(0, kb1 - ka1), n = n1 + max(0, kb2 - ka2);
             for (int i = 0; i < n; i += kGroup) {
                 // a group of the sequence: the points first, then every
@@ -561,32 +569,38 @@ __device__ inline void traverse(const Ray &r, float dt, const RNode *__restrict_
 // Waves per SIMD the render kernels are compiled for.  The scheduler
 // otherwise trades latency hiding for occupancy: aiming at 5-8 waves it
 // waits on each sample's gathers in turn instead of issuing a whole group
-// before the first wait (measured 20-40 % slower marches).  2 for the
-// full march, 3 for the others (measured best of 2..6).
-constexpr int render_waves_for(int accel) { return accel == ESK_ACCEL_NONE ? 2 : 3; }
+// before the first wait (measured 20-40 % slower marches).  2 for the full
+// march, 4 for the others (with two-wave tiles: measured best of 2..6; 3
+// and 4 for the full march measured the same or slower).
+constexpr int render_waves_for(int accel) { return accel == ESK_ACCEL_NONE ? 2 : 4; }
 
-// One kRenderTile^2 pixel tile (tbx, tby) of one request.  TFL: the TF (N <= 1024
+// One 8x8-pixel tile (tbx, tby) of one request.  TFL: the TF (N <= 1024
 // entries) is staged in LDS; otherwise read from global memory.
+//
+// Every wave computes the tile's rays and K, the lattice samples before the
+// exit of its longest ray; the tile takes S = clamp(K / kRaySegLen, 1, max)
+// waves and the others end at once.  Wave j marches the samples
+// [K_r j / S, K_r (j + 1) / S) of each ray r (the last wave to the ray's
+// end) in any mode, from zero colour and opacity; wave 0 then combines the
+// partial results front to back.  K depends on the camera and the volume
+// only, so every mode splits a tile the same way and every skipping mode
+// still reproduces the full march bit for bit.
 template <int ACCEL, typename T, typename IDX, bool TFL>
 __device__ inline void render_tile(const RenderArgs &ra, int tbx, int tby)
 {
     extern __shared__ float4 lds[];
+    constexpr int kSegMax = kRaySegments;
+    __shared__ float4 part_c[kSegMax > 1 ? kSegMax - 1 : 1][64];
+    __shared__ int part_n[kSegMax > 1 ? kSegMax - 1 : 1][64];
     constexpr bool tf_lds = TFL;
-    constexpr int kRenderTile = render_tile_for(ACCEL), kRenderThreads = render_threads_for(ACCEL);
-    if (tf_lds) {
-        const float4 *src = reinterpret_cast<const float4 *>(ra.tf);
-        for (int i = threadIdx.x; i < ra.N; i += kRenderThreads) lds[i] = src[i];
-        __syncthreads();
-    }
-    int *stk = reinterpret_cast<int *>(lds + (tf_lds ? ra.N : 0));
 
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    constexpr int wx = kRenderTile / 8;   // waves per tile row
-    const int px = tbx * kRenderTile + (wave % wx) * 8 + (lane & 7);
-    const int py = tby * kRenderTile + (wave / wx) * 8 + (lane >> 3);
-    if (px >= ra.W || py >= ra.H) return;
+    const int lane = threadIdx.x & 63;
+    // wave-uniform (scalar) values: whole waves leave or branch together
+    const int seg = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int px = tbx * 8 + (lane & 7);
+    const int py = tby * 8 + (lane >> 3);
+    const bool live = px < ra.W && py < ra.H;
 
-    const T *__restrict__ vol = static_cast<const T *>(ra.vol.swz);
     Vol v;
     v.n[0] = ra.vol.nx; v.n[1] = ra.vol.ny; v.n[2] = ra.vol.nz;
     for (int a = 0; a < 3; ++a) {
@@ -595,6 +609,30 @@ __device__ inline void render_tile(const RenderArgs &ra, int tbx, int tby)
     }
     v.nq0 = (uint32_t)ra.vol.nq[0];
     v.nq1 = (uint32_t)ra.vol.nq[1];
+    const float dt = ra.dt;
+
+    Ray r;
+    make_ray(ra.cam, px, py, r);
+    const float zero[3] = {0.0f, 0.0f, 0.0f};
+    float tn = 0.0f, tx = 0.0f;
+    const bool hit = live && slab(r, zero, v.fn, tn, tx);
+    r.t0 = hit ? (tn > 0.0f ? tn : 0.0f) : 0.0f;
+    r.tx = hit ? tx : 0.0f;
+    int K = 0;
+    if (hit) K = (int)fminf(fmaxf((r.tx - r.t0) * __builtin_amdgcn_rcpf(dt), 0.0f), 1.0e9f);
+    int kmax = K;
+    for (int o = 32; o >= 1; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, 64));
+    const int S = __builtin_amdgcn_readfirstlane(min(kSegMax, max(1, kmax / kRaySegLen)));
+    if (seg >= S) return;
+
+    if (tf_lds) {
+        const float4 *src = reinterpret_cast<const float4 *>(ra.tf);
+        for (int i = threadIdx.x; i < ra.N; i += 64 * S) lds[i] = src[i];
+        __syncthreads();
+    }
+    int *stk = reinterpret_cast<int *>(lds + (tf_lds ? ra.N : 0)) + seg * ra.stack_cap * 64;
+
+    const T *__restrict__ vol = static_cast<const T *>(ra.vol.swz);
     Shade s;
     s.tf = tf_lds ? lds : reinterpret_cast<const float4 *>(ra.tf);
     s.N = ra.N;
@@ -602,18 +640,17 @@ __device__ inline void render_tile(const RenderArgs &ra, int tbx, int tby)
     s.vscale = ra.vscale;
     s.expo = ra.expo;
     s.correct = ra.correct;
-    const float dt = ra.dt;
+
+    // this wave's samples [ks, ke) and their t range (culling slack covers rounding)
+    const int ks = (int)(((int64_t)K * seg) / S);
+    const int ke = seg == S - 1 ? (1 << 30) : (int)(((int64_t)K * (seg + 1)) / S);
+    r.clo = fmaf((float)ks, dt, r.t0);
+    r.chi = seg == S - 1 ? r.tx : fmaf((float)ke, dt, r.t0);
 
     Accum acc = {{0.0f, 0.0f, 0.0f}, 0.0f, 0};
-    Ray r;
-    make_ray(ra.cam, px, py, r);
-    const float zero[3] = {0.0f, 0.0f, 0.0f};
-    float tn, tx;
-    if (slab(r, zero, v.fn, tn, tx)) {
-        r.t0 = tn > 0.0f ? tn : 0.0f;
-        r.tx = tx;
+    if (hit) {
         if (ACCEL == ESK_ACCEL_NONE) {
-            for (int k = 0;; k += kGroup) {
+            for (int k = ks;; k += kGroup) {
                 Corners g[kGroup];
                 bool ok[kGroup];
                 bool more = true;
@@ -622,10 +659,10 @@ __device__ inline void render_tile(const RenderArgs &ra, int tbx, int tby)
                     const float t = lattice_t(r, dt, k + j);
                     float p[3];
                     point_at(r, t, p);
-                    const bool live = t < r.tx;
-                    ok[j] = live & inside(v, p);
+                    const bool in_seg = (t < r.tx) & (k + j < ke);
+                    ok[j] = in_seg & inside(v, p);
                     gather<T, IDX>(vol, v, p, g[j]);
-                    more = live;
+                    more = in_seg;
                 }
                 group_fence();
 #pragma unroll
@@ -634,15 +671,15 @@ __device__ inline void render_tile(const RenderArgs &ra, int tbx, int tby)
             }
         } else if (ACCEL == ESK_ACCEL_GRID) {
             const float zero3[3] = {0.0f, 0.0f, 0.0f};
-            march_grid<T, IDX>(r, dt, 0, 1 << 30, zero3, v.fn, grid_ref(ra), vol, v, s, acc);
+            march_grid<T, IDX>(r, dt, ks, ke, zero3, v.fn, grid_ref(ra), vol, v, s, acc);
         } else if (ACCEL == ESK_ACCEL_LBVH) {
             const int N = (int)ra.hdr->n;
             if (N > 0) {
                 int lo[3], hi[3];
                 const uint4 b = ra.lb_root[0];
                 unpack_box(b.x, b.y, b.z, lo, hi);
-                traverse<T, IDX, false, kRenderThreads>(r, dt, ra.lb_rnode, ra.lb_leafbox, grid_ref(ra), N == 1 ? kLeaf : 0u, lo, hi, stk,
-                                 ra.stack_cap, vol, v, s, acc);
+                traverse<T, IDX, false>(r, dt, ks, ke, ra.lb_rnode, ra.lb_leafbox, grid_ref(ra), N == 1 ? kLeaf : 0u,
+                                        lo, hi, stk, ra.stack_cap, vol, v, s, acc);
             }
         } else if (ACCEL == ESK_ACCEL_KD || ACCEL == ESK_ACCEL_HYBRID) {
             const int M = (int)ra.hdr->kd_count;
@@ -650,12 +687,30 @@ __device__ inline void render_tile(const RenderArgs &ra, int tbx, int tby)
                 int lo[3], hi[3];
                 const uint4 b = ra.kd_box[0];
                 unpack_box(b.x, b.y, b.z, lo, hi);
-                traverse<T, IDX, ACCEL == ESK_ACCEL_HYBRID, kRenderThreads>(r, dt, ra.kd_rnode, ra.kd_box, grid_ref(ra),
-                                                            M == 1 ? kLeaf : 0u, lo, hi, stk,
-                                 ra.stack_cap, vol, v, s, acc);
+                traverse<T, IDX, ACCEL == ESK_ACCEL_HYBRID>(r, dt, ks, ke, ra.kd_rnode, ra.kd_box, grid_ref(ra),
+                                                            M == 1 ? kLeaf : 0u, lo, hi, stk, ra.stack_cap, vol, v,
+                                                            s, acc);
             }
         }
     }
+    if (kSegMax > 1 && S > 1) {
+        if (seg > 0) {
+            part_c[seg - 1][lane] = make_float4(acc.c[0], acc.c[1], acc.c[2], acc.a);
+            part_n[seg - 1][lane] = acc.n;
+        }
+        __syncthreads();
+        if (seg > 0) return;
+        for (int j = 1; j < S; ++j) {
+            const float4 q = part_c[j - 1][lane];
+            const float t = 1.0f - acc.a;
+            acc.c[0] = fmaf(t, q.x, acc.c[0]);
+            acc.c[1] = fmaf(t, q.y, acc.c[1]);
+            acc.c[2] = fmaf(t, q.z, acc.c[2]);
+            acc.a = fmaf(t, q.w, acc.a);
+            acc.n += part_n[j - 1][lane];
+        }
+    }
+    if (!live) return;
     const int64_t pix = (int64_t)py * ra.W + px;
     reinterpret_cast<float4 *>(ra.out)[pix] = make_float4(acc.c[0], acc.c[1], acc.c[2], acc.a);
     if (ra.count) ra.count[pix] = acc.n;
