@@ -729,6 +729,50 @@ esk_status esk_rebuild_batch(esk_ctx *const *ctxs, int n, const float *const *d_
 
 }  // extern "C"
 
+// The tile the centre of the volume projects to, clamped to the image: the
+// render dispatches tiles outwards from it, so the tiles whose rays cross the
+// most of the volume start first.  Perspective: C - eye = s (dir00 + fx du +
+// fy dv); orthographic: C - eye = t dir00 + fx du + fy dv; solved for
+// (s, s fx, s fy) or (t, fx, fy) by Cramer's rule.  Any answer is correct
+// (it orders the work only); the image centre where the system is singular
+// or the centre lies behind the eye.
+static void centre_tile(const VolumeDesc &v, const esk_camera &cam, int W, int H, int &tx, int &ty)
+{
+    const int ntx = (W + 7) / 8, nty = (H + 7) / 8;
+    tx = ntx / 2;
+    ty = nty / 2;
+    const double C[3] = {0.5 * v.nx, 0.5 * v.ny, 0.5 * v.nz};
+    double A[3][3], b[3];
+    for (int a = 0; a < 3; ++a) {
+        A[a][0] = cam.dir00[a];
+        A[a][1] = cam.du[a];
+        A[a][2] = cam.dv[a];
+        b[a] = C[a] - cam.eye[a];
+    }
+    auto det3 = [](const double M[3][3]) {
+        return M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+               M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+    };
+    const double d = det3(A);
+    if (!(std::fabs(d) > 1e-300)) return;
+    double u[3];
+    for (int k = 0; k < 3; ++k) {
+        double M[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int j = 0; j < 3; ++j) M[a][j] = j == k ? b[a] : A[a][j];
+        u[k] = det3(M) / d;
+    }
+    double fx = u[1], fy = u[2];
+    if (!cam.ortho) {
+        if (!(u[0] > 0.0)) return;
+        fx /= u[0];
+        fy /= u[0];
+    }
+    if (!(std::isfinite(fx) && std::isfinite(fy))) return;
+    tx = (int)std::min<double>(ntx - 1, std::max(0.0, std::floor((fx - 0.5) / 8.0)));
+    ty = (int)std::min<double>(nty - 1, std::max(0.0, std::floor((fy - 0.5) / 8.0)));
+}
+
 // validates one render request and fills its kernel arguments (may
 // synchronise once to finish a pending k-d build)
 static esk_status prepare_render(esk_ctx *c, int accel, const esk_camera *cam, int width, int height, float step,
@@ -779,6 +823,7 @@ static esk_status prepare_render(esk_ctx *c, int accel, const esk_camera *cam, i
     r.kd_rnode = at<RNode>(c, L.kd_rnode);
     r.kd_box = at<uint4>(c, L.kd_box);
     r.hdr = at<DevHeader>(c, L.header);
+    centre_tile(c->vol, *cam, width, height, r.ctx, r.cty);
     r.stack_cap = 0;
     // a Karras tree splits on a strictly lower key bit at every level, so a
     // root-to-leaf path holds at most key_bits internal nodes

@@ -196,6 +196,7 @@ struct RenderArgs {
     const uint4 *kd_box;
     const DevHeader *hdr;
     int stack_cap;
+    int ctx, cty;          // the tile the volume's centre projects to (dispatch starts there)
 };
 
 // Render workgroups cover one 8x8-pixel tile (fine-grained scheduling

@@ -716,14 +716,30 @@ __device__ inline void render_tile(const RenderArgs &ra, int tbx, int tby)
     if (ra.count) ra.count[pix] = acc.n;
 }
 
+// The i-th of the n indices [0, n) in the order c, c + 1, c - 1, c + 2,
+// c - 2, ..., then the rest of the longer side: workgroups are dispatched in
+// block order, so tiles start from the centre tile outwards (rows, and
+// within a row columns).
+__device__ inline int centre_out(int i, int c, int n)
+{
+    const int m = min(c, n - 1 - c);
+    if (i <= 2 * m) {
+        const int h = (i + 1) >> 1;
+        return (i & 1) ? c + h : c - h;
+    }
+    const int rest = i - 2 * m;
+    return c - m == 0 ? c + m + rest : c - m - rest;
+}
+
 template <int ACCEL, typename T, typename IDX, bool TFL>
 __global__ __launch_bounds__(render_threads_for(ACCEL)) __attribute__((amdgpu_waves_per_eu(1, render_waves_for(ACCEL)))) void
 k_render(RenderArgs ra)
 {
-    // plain row-major tiles: the round-robin spread over the XCDs balances
-    // the very uneven per-tile work (giving each XCD a band of tiles was
-    // measured 1.5-2x slower)
-    render_tile<ACCEL, T, IDX, TFL>(ra, blockIdx.x, blockIdx.y);
+    // block order spreads consecutive tiles round-robin over the XCDs, which
+    // balances the very uneven per-tile work (giving each XCD a band of
+    // tiles was measured 1.5-2x slower)
+    render_tile<ACCEL, T, IDX, TFL>(ra, centre_out((int)blockIdx.x, ra.ctx, (int)gridDim.x),
+                                    centre_out((int)blockIdx.y, ra.cty, (int)gridDim.y));
 }
 
 // Many requests in one launch: blockIdx.z picks the request, whose tiles
@@ -733,9 +749,9 @@ __global__ __launch_bounds__(render_threads_for(ACCEL)) __attribute__((amdgpu_wa
 k_render_batch(const RenderArgs *__restrict__ args)
 {
     const RenderArgs ra = args[blockIdx.z];
-    if ((int)blockIdx.x * render_tile_for(ACCEL) >= ra.W || (int)blockIdx.y * render_tile_for(ACCEL) >= ra.H)
-        return;  // uniform per block
-    render_tile<ACCEL, T, IDX, TFL>(ra, blockIdx.x, blockIdx.y);
+    const int ntx = (ra.W + 7) / 8, nty = (ra.H + 7) / 8;
+    if ((int)blockIdx.x >= ntx || (int)blockIdx.y >= nty) return;  // uniform per block
+    render_tile<ACCEL, T, IDX, TFL>(ra, centre_out((int)blockIdx.x, ra.ctx, ntx), centre_out((int)blockIdx.y, ra.cty, nty));
 }
 
 template <int ACCEL, typename T, typename IDX, bool TFL>
