@@ -472,6 +472,7 @@ static KdArgs kd_args(esk_ctx *c, const esk_kd_params *p)
     k.n[1] = c->vol.ny;
     k.n[2] = c->vol.nz;
     k.flags = at<uint8_t>(c, L.flags);
+    k.grid = at<uint32_t>(c, L.grid);
     k.S = at<int32_t>(c, L.kd_S);
     k.lo = at<int32_t>(c, L.kd_lo);
     k.hi = at<int32_t>(c, L.kd_hi);

@@ -157,6 +157,7 @@ int64_t rebuild_batch_blocks(const RebuildArgs &a, int kind);
 struct KdArgs {
     int nb[3], B, n[3];
     const uint8_t *flags;
+    const uint32_t *grid;  // the same flags as a bitmask (bit b of word b / 32, b the linear brick id)
     int32_t *S;
     int32_t *lo, *hi, *axis, *plane, *first, *split, *clo;  // clo: [node][side][6 faces]
     int32_t *plist;        // the splitting nodes of the last level, in order (parents of the next level)

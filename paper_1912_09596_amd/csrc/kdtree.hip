@@ -157,11 +157,147 @@ __device__ inline int candidate(const int lo[3], const int hi[3], int bins, int 
 
 constexpr int kMaxCand = 45;   // 3 axes x (16 bins - 1)
 
-// Decides the split of one node (one wave): every (candidate plane, side,
-// face) binary search runs on its own lane; lane 0 writes axis, plane, split
-// flag and the two children's tight boxes.  tb: this wave's scratch.
+// Occupancy projections of a node whose brick box is at most 32 bricks along
+// every axis, relative to the box: X[y] = the x-bitmask of the flagged bricks
+// of row y (any z), XZ[z] = the x-bitmask of slab z (any y), YZ[z] = the
+// y-bitmask of slab z (bit y set where row (y, z) holds a flagged brick).
+// With them the tight box of either side of any plane is a few bitmask
+// reductions, instead of six binary searches over the prefix count (each step
+// a dependent round of eight loads).
+struct Proj {
+    uint32_t X[32], XZ[32], YZ[32];
+    uint32_t T[32][33];            // T[z][y]: the x-bitmask of row (y, z) (padded: conflict-free columns)
+    int16_t ca[kMaxCand], cp[kMaxCand];   // the node's candidate planes: axis, plane
+};
+
+__device__ inline uint32_t low_bits(int n) { return n >= 32 ? 0xffffffffu : ((1u << n) - 1u); }
+
+// one wave: lane (y, h) reads the rows (y, z) with z of parity h from the
+// grid bitmask, eight slabs' loads in flight per round; X accumulates in
+// registers, YZ is a ballot per slab, XZ an OR over the rows of the slab
+__device__ inline void build_proj(const KdArgs &k, const int lo[3], const int hi[3], Proj *P)
+{
+    const int lane = threadIdx.x & 63;
+    const int y = lane & 31, h = lane >> 5;
+    const int ex = hi[0] - lo[0], ey = hi[1] - lo[1], ez = hi[2] - lo[2];
+    const uint32_t full = low_bits(ex);
+    uint32_t xacc = 0u;
+    for (int z0 = 0; z0 < ez; z0 += 8) {
+        uint32_t m[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int z = z0 + 2 * u + h;
+            m[u] = 0u;
+            if (y < ey && z < ez) {
+                // bits [base, base + ex) of the bitmask: the row's bricks lo_x .. hi_x - 1
+                const uint64_t base =
+                    (uint64_t)k.nb[0] * ((uint64_t)(lo[1] + y) + (uint64_t)k.nb[1] * (uint64_t)(lo[2] + z)) +
+                    (uint64_t)lo[0];
+                const uint64_t wi = base >> 5;
+                const int sh = (int)(base & 31u);
+                uint64_t w = k.grid[wi];
+                if (sh + ex > 32) w |= (uint64_t)k.grid[wi + 1] << 32;   // the row's last brick lies there
+                m[u] = (uint32_t)(w >> sh) & full;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int z = z0 + 2 * u + h;
+            xacc |= m[u];
+            const uint64_t bal = __ballot(m[u] != 0u);
+            if (z < ez) {
+                P->T[z][y] = m[u];
+                if (y == 0) P->YZ[z] = (uint32_t)(bal >> (32 * h));
+            }
+        }
+    }
+    wave_lds_sync();
+    const uint32_t xo = xacc | __shfl_xor(xacc, 32, 64);   // even and odd slabs
+    if (lane < 32) P->X[lane] = xo;
+    if (lane < ez) {
+        uint32_t o = 0u;
+        for (int yy = 0; yy < ey; ++yy) o |= P->T[lane][yy];
+        P->XZ[lane] = o;
+    }
+    wave_lds_sync();
+}
+
+// The candidate planes of box [lo, hi) in order (axes x, y, z; planes
+// lo + floor(i e / bins), i = 1 .. bins - 1, strictly inside, a plane equal
+// to the one before it on its axis dropped), one per lane, compacted into
+// P->ca / P->cp; returns their count.  The same list as candidate().
+__device__ inline int candidates_lds(const int lo[3], const int hi[3], int bins, Proj *P)
+{
+    const int lane = threadIdx.x & 63;
+    const int per = bins - 1;
+    bool ok = false;
+    int a = 0, p = 0;
+    if (lane < 3 * per) {
+        a = lane / per;
+        const int i = lane % per + 1;
+        const int e = hi[a] - lo[a];
+        p = lo[a] + (i * e) / bins;
+        const int prev = i > 1 ? lo[a] + ((i - 1) * e) / bins : -1;
+        ok = e >= 2 && p > lo[a] && p < hi[a] && p != prev;
+    }
+    const uint64_t bal = __ballot(ok);
+    if (ok) {
+        const int rank = __popcll(bal & ((1ull << lane) - 1ull));
+        P->ca[rank] = (int16_t)a;
+        P->cp[rank] = (int16_t)p;
+    }
+    wave_lds_sync();
+    return __popcll(bal);
+}
+
+// faces (absolute brick coordinates: lower bounds, then exclusive upper
+// bounds) of the tight box of the node's bricks below (side 0) or at and
+// above (side 1) plane p on axis a; both sides of a plane strictly inside a
+// tight box hold a flagged brick
+__device__ inline void proj_child(const Proj *P, const int lo[3], const int hi[3], int a, int p, int side, int f[6])
+{
+    const int ey = hi[1] - lo[1], ez = hi[2] - lo[2];
+    const int ea = hi[a] - lo[a];
+    const uint32_t below = low_bits(p - lo[a]);
+    const uint32_t am = side == 0 ? below : (low_bits(ea) & ~below);
+    uint32_t mx = 0u, my = 0u, mz = 0u;
+    if (a == 0) {
+        for (int y = 0; y < ey; ++y) {
+            const uint32_t q = P->X[y] & am;
+            mx |= q;
+            my |= q ? (1u << y) : 0u;
+        }
+        for (int z = 0; z < ez; ++z) mz |= (P->XZ[z] & am) ? (1u << z) : 0u;
+    } else if (a == 1) {
+        for (int y = 0; y < ey; ++y) mx |= ((am >> y) & 1u) ? P->X[y] : 0u;
+        for (int z = 0; z < ez; ++z) {
+            const uint32_t q = P->YZ[z] & am;
+            my |= q;
+            mz |= q ? (1u << z) : 0u;
+        }
+    } else {
+        for (int z = 0; z < ez; ++z)
+            if ((am >> z) & 1u) {
+                mx |= P->XZ[z];
+                my |= P->YZ[z];
+                mz |= P->YZ[z] ? (1u << z) : 0u;
+            }
+    }
+    const uint32_t m[3] = {mx, my, mz};
+    for (int q = 0; q < 3; ++q) {
+        f[q] = lo[q] + (int)__builtin_ctz(m[q]);
+        f[3 + q] = lo[q] + 32 - (int)__builtin_clz(m[q]);
+    }
+}
+
+// Decides the split of one node (one wave): the children's tight boxes come
+// from the node's occupancy projections where the node spans at most 32
+// bricks per axis, else every (candidate plane, side, face) binary search
+// over the prefix count runs on its own lane; lane 0 writes axis, plane,
+// split flag and the two children's tight boxes.  tb, P: this wave's scratch.
 template <typename SP>
-__device__ void eval_node(const KdArgs &k, SP S, int64_t node, int64_t begin, int64_t vroot, int16_t (*tb)[2][6])
+__device__ void eval_node(const KdArgs &k, SP S, int64_t node, int64_t begin, int64_t vroot, int16_t (*tb)[2][6],
+                          Proj *P)
 {
     const int lane = threadIdx.x & 63;
     int lo[3], hi[3];
@@ -188,18 +324,28 @@ __device__ void eval_node(const KdArgs &k, SP S, int64_t node, int64_t begin, in
     }
     const int64_t V = box_volume(k, lo, hi);
     const bool allowed = k.halting == 0 ? (10 * V > vroot) : (V > 512);
-    int dummy_a = 0, dummy_p = 0;
-    const int ncand = allowed ? candidate(lo, hi, k.bins, -1, &dummy_a, &dummy_p) : 0;
+    // wave-uniform: the box is the same on every lane
+    const bool proj = hi[0] - lo[0] <= 32 && hi[1] - lo[1] <= 32 && hi[2] - lo[2] <= 32;
+    const int ncand = allowed ? candidates_lds(lo, hi, k.bins, P) : 0;
+    if (proj && ncand > 0) build_proj(k, lo, hi, P);
     int best = -1;
     int64_t best_cost = 0;
     if (ncand > 0) {
-        for (int t = lane; t < ncand * 12; t += 64) {
-            const int c = t / 12, side = (t / 6) & 1, face = t % 6;
-            int a = 0, p = 0;
-            candidate(lo, hi, k.bins, c, &a, &p);
-            int rl[3] = {lo[0], lo[1], lo[2]}, rh[3] = {hi[0], hi[1], hi[2]};
-            if (side == 0) rh[a] = p; else rl[a] = p;
-            tb[c][side][face] = (int16_t)tight_face(k, S, rl, rh, face);
+        if (proj) {
+            for (int t = lane; t < ncand * 2; t += 64) {
+                const int c = t >> 1, side = t & 1;
+                int f[6];
+                proj_child(P, lo, hi, P->ca[c], P->cp[c], side, f);
+                for (int q = 0; q < 6; ++q) tb[c][side][q] = (int16_t)f[q];
+            }
+        } else {
+            for (int t = lane; t < ncand * 12; t += 64) {
+                const int c = t / 12, side = (t / 6) & 1, face = t % 6;
+                const int a = P->ca[c], p = P->cp[c];
+                int rl[3] = {lo[0], lo[1], lo[2]}, rh[3] = {hi[0], hi[1], hi[2]};
+                if (side == 0) rh[a] = p; else rl[a] = p;
+                tb[c][side][face] = (int16_t)tight_face(k, S, rl, rh, face);
+            }
         }
         wave_lds_sync();
         int64_t cost = 0x7fffffffffffffffLL;
@@ -221,7 +367,8 @@ __device__ void eval_node(const KdArgs &k, SP S, int64_t node, int64_t begin, in
     int axis = -1, plane = 0;
     int cl[2][6];
     if (best >= 0 && best_cost < V) {
-        candidate(lo, hi, k.bins, best, &axis, &plane);
+        axis = P->ca[best];
+        plane = P->cp[best];
         for (int s = 0; s < 2; ++s)
             for (int f = 0; f < 6; ++f) cl[s][f] = tb[best][s][f];
     } else if (best >= 0 && k.max_leaf > 0 &&
@@ -235,7 +382,13 @@ __device__ void eval_node(const KdArgs &k, SP S, int64_t node, int64_t begin, in
             if (ext > best_ext) { best_ext = ext; axis = a; plane = lo[a] + e / 2; }
         }
         wave_lds_sync();
-        if (lane < 12) {
+        if (proj) {
+            if (lane < 2) {
+                int f[6];
+                proj_child(P, lo, hi, axis, plane, lane, f);
+                for (int q = 0; q < 6; ++q) tb[kMaxCand][lane][q] = (int16_t)f[q];
+            }
+        } else if (lane < 12) {
             const int side = lane / 6, face = lane % 6;
             int rl[3] = {lo[0], lo[1], lo[2]}, rh[3] = {hi[0], hi[1], hi[2]};
             if (side == 0) rh[axis] = plane; else rl[axis] = plane;
@@ -429,6 +582,7 @@ __device__ inline bool last_of_level(const KdArgs &k, uint32_t *last)
 __global__ __launch_bounds__(256) void k_kd_level(KdArgs k)
 {
     __shared__ int16_t tb[4][kMaxCand + 1][2][6];
+    __shared__ Proj proj[4];
     __shared__ uint32_t scratch[5];
     __shared__ uint32_t last;
     const uint32_t begin = k.hdr->kd_begin, end = k.hdr->kd_end;
@@ -437,7 +591,7 @@ __global__ __launch_bounds__(256) void k_kd_level(KdArgs k)
     const int64_t vroot = root_volume(k);
     for (int64_t node = (int64_t)begin + (int64_t)blockIdx.x * 4 + wave; node < end;
          node += (int64_t)gridDim.x * 4) {
-        eval_node(k, (const int32_t *)k.S, node, (int64_t)begin, vroot, tb[wave]);
+        eval_node(k, (const int32_t *)k.S, node, (int64_t)begin, vroot, tb[wave], &proj[wave]);
     }
     if (last_of_level(k, &last)) number_children(k, begin, end, scratch);
 }
