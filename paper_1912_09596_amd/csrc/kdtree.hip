@@ -164,7 +164,7 @@ constexpr int kMaxCand = 45;   // 3 axes x (16 bins - 1)
 // With them the tight box of either side of any plane is a few bitmask
 // reductions, instead of six binary searches over the prefix count (each step
 // a dependent round of eight loads).
-struct Proj {
+struct __align__(16) Proj {
     uint32_t X[32], XZ[32], YZ[32];
     uint32_t T[32][33];            // T[z][y]: the x-bitmask of row (y, z) (padded: conflict-free columns)
     int16_t ca[kMaxCand], cp[kMaxCand];   // the node's candidate planes: axis, plane
@@ -216,6 +216,7 @@ __device__ inline void build_proj(const KdArgs &k, const int lo[3], const int hi
     if (lane < 32) P->X[lane] = xo;
     if (lane < ez) {
         uint32_t o = 0u;
+#pragma unroll 8
         for (int yy = 0; yy < ey; ++yy) o |= P->T[lane][yy];
         P->XZ[lane] = o;
     }
@@ -253,35 +254,43 @@ __device__ inline int candidates_lds(const int lo[3], const int hi[3], int bins,
 // faces (absolute brick coordinates: lower bounds, then exclusive upper
 // bounds) of the tight box of the node's bricks below (side 0) or at and
 // above (side 1) plane p on axis a; both sides of a plane strictly inside a
-// tight box hold a flagged brick
+// tight box hold a flagged brick.  One loop over the projection entries for
+// every axis, with selects (lanes of a wave take different axes), the
+// entries read four at a time.
 __device__ inline void proj_child(const Proj *P, const int lo[3], const int hi[3], int a, int p, int side, int f[6])
 {
     const int ey = hi[1] - lo[1], ez = hi[2] - lo[2];
     const int ea = hi[a] - lo[a];
     const uint32_t below = low_bits(p - lo[a]);
     const uint32_t am = side == 0 ? below : (low_bits(ea) & ~below);
+    const bool ax = a == 0, ay = a == 1, az = a == 2;
+    const int n = max(ey, ez);
     uint32_t mx = 0u, my = 0u, mz = 0u;
-    if (a == 0) {
-        for (int y = 0; y < ey; ++y) {
-            const uint32_t q = P->X[y] & am;
-            mx |= q;
-            my |= q ? (1u << y) : 0u;
+    const uint4 *X4 = reinterpret_cast<const uint4 *>(P->X);
+    const uint4 *XZ4 = reinterpret_cast<const uint4 *>(P->XZ);
+    const uint4 *YZ4 = reinterpret_cast<const uint4 *>(P->YZ);
+    for (int i0 = 0; i0 < n; i0 += 4) {
+        const uint4 xq = X4[i0 >> 2], xzq = XZ4[i0 >> 2], yzq = YZ4[i0 >> 2];
+        const uint32_t xv[4] = {xq.x, xq.y, xq.z, xq.w};
+        const uint32_t xzv[4] = {xzq.x, xzq.y, xzq.z, xzq.w};
+        const uint32_t yzv[4] = {yzq.x, yzq.y, yzq.z, yzq.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u;
+            const uint32_t bit = 1u << (i & 31);
+            // entries past the box's extent hold an earlier node's values
+            const uint32_t X = i < ey ? xv[u] : 0u;
+            const uint32_t XZ = i < ez ? xzv[u] : 0u;
+            const uint32_t YZ = i < ez ? yzv[u] : 0u;
+            const bool in = ((am >> (i & 31)) & 1u) != 0u;
+            // split along x: i is y for X, z for XZ
+            const uint32_t qx = X & am;
+            // split along y: i is y for X, z for YZ
+            const uint32_t qy = YZ & am;
+            mx |= ax ? qx : (ay ? (in ? X : 0u) : (in ? XZ : 0u));
+            my |= ax ? (qx ? bit : 0u) : (ay ? qy : (in ? YZ : 0u));
+            mz |= ax ? ((XZ & am) ? bit : 0u) : (ay ? (qy ? bit : 0u) : ((in && YZ) ? bit : 0u));
         }
-        for (int z = 0; z < ez; ++z) mz |= (P->XZ[z] & am) ? (1u << z) : 0u;
-    } else if (a == 1) {
-        for (int y = 0; y < ey; ++y) mx |= ((am >> y) & 1u) ? P->X[y] : 0u;
-        for (int z = 0; z < ez; ++z) {
-            const uint32_t q = P->YZ[z] & am;
-            my |= q;
-            mz |= q ? (1u << z) : 0u;
-        }
-    } else {
-        for (int z = 0; z < ez; ++z)
-            if ((am >> z) & 1u) {
-                mx |= P->XZ[z];
-                my |= P->YZ[z];
-                mz |= P->YZ[z] ? (1u << z) : 0u;
-            }
     }
     const uint32_t m[3] = {mx, my, mz};
     for (int q = 0; q < 3; ++q) {
