@@ -73,7 +73,7 @@ Layout make_layout(int nx, int ny, int nz, int brick, int elem_bytes, int max_tf
     L.lb_hi = take(2 * n4 * 3);
     L.lb_range = take(2 * n4);
     L.lb_rnode = take((size_t)nb * sizeof(RNode));
-    L.lb_leafbox = take((size_t)nb * 16);
+    L.lb_leafbox = take((size_t)nb * 2 * 16);   // leaf boxes, then boxes of subtrees traversed as one leaf
     L.lb_root = take(16);
     L.lb_chunk = take((size_t)((nb + 255) / 256) * 48);
     L.tbox = take((size_t)nb * 16);

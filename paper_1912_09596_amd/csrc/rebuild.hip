@@ -763,11 +763,33 @@ __device__ __forceinline__ void k_lbvh_boxes_body(const RebuildArgs &a, uint32_t
             pack_box(l2, h2, w);
             a.lb_root[0] = make_uint4(w[0], w[1], w[2], 0u);
         }
+        // A child subtree whose bricks fill its box (every brick of the box
+        // non-empty) is traversed as one leaf with that box: its samples are
+        // exactly those of its bricks, so the render and the counts do not
+        // change.  Its box goes after the n leaf boxes, for popped links.
+        // Not with voxel-tight leaf boxes (their union holds samples no leaf
+        // box holds).
+        uint32_t link[2] = {l, r};
+        if (!a.tight) {
+            const int B = a.vol.B;
+            for (int side = 0; side < 2; ++side) {
+                if (link[side] & kLeaf) continue;
+                const int j0 = side == 0 ? rg.x : g + 1, j1 = side == 0 ? g : rg.y;
+                int64_t bricks = 1;
+                for (int q = 0; q < 3; ++q) bricks *= (int64_t)((box[side][3 + q] + B - 1) / B - box[side][q] / B);
+                if (bricks == (int64_t)(j1 - j0 + 1)) {
+                    uint32_t w[3];
+                    pack_box(&rbox[side][0], &rbox[side][3], w);
+                    a.lb_leafbox[n + (int64_t)link[side]] = make_uint4(w[0], w[1], w[2], 0u);
+                    link[side] = kLeaf | (uint32_t)(n + (int64_t)link[side]);
+                }
+            }
+        }
         RNode rec;
         pack_box(&rbox[0][0], &rbox[0][3], &rec.w[0]);
         pack_box(&rbox[1][0], &rbox[1][3], &rec.w[3]);
-        rec.w[6] = l | ((uint32_t)a.lb_axis[i] << 29);
-        rec.w[7] = r;
+        rec.w[6] = link[0] | ((uint32_t)a.lb_axis[i] << 29);
+        rec.w[7] = link[1];
         uint4 *dst = reinterpret_cast<uint4 *>(&a.lb_rnode[i]);
         dst[0] = make_uint4(rec.w[0], rec.w[1], rec.w[2], rec.w[3]);
         dst[1] = make_uint4(rec.w[4], rec.w[5], rec.w[6], rec.w[7]);
