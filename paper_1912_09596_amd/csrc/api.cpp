@@ -825,6 +825,8 @@ static esk_status prepare_render(esk_ctx *c, int accel, const esk_camera *cam, i
     r.kd_box = at<uint4>(c, L.kd_box);
     r.hdr = at<DevHeader>(c, L.header);
     centre_tile(c->vol, *cam, width, height, r.ctx, r.cty);
+    const int64_t tiles = (int64_t)((width + 7) / 8) * ((height + 7) / 8);
+    r.seg_len = tiles >= kRaySegFewTiles ? kRaySegLen : kRaySegLenFew;
     r.stack_cap = 0;
     // a Karras tree splits on a strictly lower key bit at every level, so a
     // root-to-leaf path holds at most key_bits internal nodes

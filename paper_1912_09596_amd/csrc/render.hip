@@ -578,7 +578,7 @@ constexpr int render_waves_for(int accel) { return accel == ESK_ACCEL_NONE ? 2 :
 // entries) is staged in LDS; otherwise read from global memory.
 //
 // Every wave computes the tile's rays and K, the lattice samples before the
-// exit of its longest ray; the tile takes S = clamp(K / kRaySegLen, 1, max)
+// exit of its longest ray; the tile takes S = clamp(K / seg_len, 1, max)
 // waves and the others end at once.  Wave j marches the samples
 // [K_r j / S, K_r (j + 1) / S) of each ray r (the last wave to the ray's
 // end) in any mode, from zero colour and opacity; wave 0 then combines the
@@ -622,7 +622,7 @@ __device__ inline void render_tile(const RenderArgs &ra, int tbx, int tby)
     if (hit) K = (int)fminf(fmaxf((r.tx - r.t0) * __builtin_amdgcn_rcpf(dt), 0.0f), 1.0e9f);
     int kmax = K;
     for (int o = 32; o >= 1; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, 64));
-    const int S = __builtin_amdgcn_readfirstlane(min(kSegMax, max(1, kmax / kRaySegLen)));
+    const int S = __builtin_amdgcn_readfirstlane(min(kSegMax, max(1, kmax / ra.seg_len)));
     if (seg >= S) return;
 
     if (tf_lds) {
