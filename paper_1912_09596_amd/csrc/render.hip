@@ -2,12 +2,13 @@
 //
 // Emission-absorption, post-classification (interpolate, then look up the
 // TF), no gradient shading, no early ray termination.  One lane per pixel,
-// one wave per 8x8 pixel tile, four waves per 16x16 tile.
+// one workgroup per 8x8 pixel tile; a long tile splits each ray's samples
+// into two consecutive segments, one per wave, combined front to back.
 //
 // Every accelerator visits a subset of one global sample lattice per ray,
 // t_k = t0 + (k+1/2) dt, and only ever drops samples that lie in empty
-// bricks (alpha exactly 0), so every mode produces the same image as the
-// full march, bit for bit:
+// bricks (alpha exactly 0); every mode splits a tile the same way, so every
+// mode produces the same image as the full march, bit for bit:
 //  - NONE: every k with t_k < t_exit whose point lies in [0,n)^3.
 //  - GRID: the same loop, but a sample in an empty macrocell (= brick) jumps
 //    to the last sample still inside that brick.  Sample points are
@@ -17,7 +18,8 @@
 //    direction along the node's split axis; children are separated by that
 //    plane, so leaves come out in sample order).  For each leaf, a
 //    conservative k range comes from an expanded slab test and each sample is
-//    kept iff its point lies inside the leaf's box (half-open).
+//    kept iff its point lies inside the leaf's box (half-open).  An LBVH
+//    subtree whose bricks fill its box is one leaf with that box.
 //  - HYBRID (Sec. 3.3): the KD traversal, but inside each leaf the samples
 //    are marched with the GRID rule restricted to the leaf's box and k range,
 //    so exactly the samples of non-empty bricks are composited.
