@@ -208,9 +208,12 @@ esk_status esk_set_volume(esk_ctx *ctx, const void *d_vox, int dtype, int nx, in
  * is always built.  d_rgba: N x RGBA float32 on the device (16-byte
  * aligned), read by the enqueued work and copied into the workspace (the
  * caller may reuse it once the stream reaches this point).
- * kd may be NULL when ESK_ACCEL_KD is not requested.  Asynchronous: the k-d
- * build runs on an internal stream of the context and is checked for
- * completion (one synchronisation) when the tree is first used. */
+ * kd may be NULL when ESK_ACCEL_KD is not requested.  Asynchronous: the
+ * k-d build (and, when it is requested too, the LBVH build) runs on internal
+ * streams of the context, forked from its stream after the classification;
+ * a render of the LBVH waits for its build on the device, the k-d tree is
+ * checked for completion (one synchronisation) when it is first used, and
+ * the next esk_set_volume / esk_set_transfer_function waits for both. */
 esk_status esk_set_transfer_function(esk_ctx *ctx, const float *d_rgba, int n_entries,
                                      int build_mask, const esk_kd_params *kd);
 
@@ -284,7 +287,8 @@ esk_status esk_render_batch_noalloc(esk_ctx *const *ctxs, int n, int accel, cons
                                     const int *widths, const int *heights, float step, float opacity_ref_step,
                                     float *const *d_outs);
 
-/* Waits for the context's stream; reports device faults. */
+/* Waits for the context's stream and its internal build streams; reports
+ * device faults. */
 esk_status esk_sync(esk_ctx *ctx);
 
 /* Synchronises and fills *out. */

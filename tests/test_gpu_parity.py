@@ -286,6 +286,35 @@ def test_rebuild_is_deterministic():
             assert np.array_equal(o[k], outs[0][k]), k
 
 
+def test_back_to_back_rebuilds_and_renders():
+    """Rebuilds of every structure and LBVH / grid / k-d renders enqueued back
+    to back with no synchronisation (the LBVH and k-d builds run on internal
+    streams): every image equals the one of the same TF rendered in a fresh
+    context with a synchronisation after each call."""
+    w = synth.c1_workload()
+    esk, ctx = make_ctx()
+    torch = _torch()
+    vol = to_dev(w["vol"])
+    ctx.set_volume(vol, 8, max_tf=256)
+    tfs = [to_dev(synth.tf_random(40 + i, 256)) for i in range(6)]
+    log("case: back-to-back rebuilds and renders")
+    got = []
+    for tf in tfs:
+        ctx.set_tf(tf, build=("grid", "lbvh", "kd"), kd=esk.Kd(1, 32, 4))
+        got.append([ctx.render(w["cam"], 96, 80, accel=a) for a in ("lbvh", "grid", "kd")])
+    torch.cuda.synchronize()
+    for i, tf in enumerate(tfs):
+        _, ref = make_ctx()
+        ref.set_volume(vol, 8, max_tf=256)
+        ref.set_tf(tf, build=("grid", "lbvh", "kd"), kd=esk.Kd(1, 32, 4))
+        ref.sync()
+        for j, a in enumerate(("lbvh", "grid", "kd")):
+            img = ref.render(w["cam"], 96, 80, accel=a)
+            torch.cuda.synchronize()
+            assert torch.equal(got[i][j], img), (i, a)
+        ref.close()
+
+
 def test_context_reuse_across_volumes_and_sizes():
     esk, ctx = make_ctx()
     torch = _torch()
