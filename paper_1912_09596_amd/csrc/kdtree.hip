@@ -17,12 +17,19 @@
 namespace esk {
 namespace {
 
+// The k-d build runs beside the renders of the other structures, whose
+// waves fill every SIMD; its latency-bound waves raise their issue priority
+// so that each level's chain of dependent steps is not slowed to a share of
+// its SIMD (the renders lose little: they wait on memory most cycles).
+__device__ inline void kd_priority() { __builtin_amdgcn_s_setprio(3); }
+
 // ---------------------------------------------------------------------------
 // 3-D inclusive prefix count S over the flags (one pass per axis)
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(256) void k_prefix_axis(KdArgs k, int axis)
 {
+    kd_priority();
     const int64_t nbx = k.nb[0], nby = k.nb[1], nbz = k.nb[2];
     const int64_t line = (int64_t)blockIdx.x * 256 + threadIdx.x;
     int64_t base, stride, len;
@@ -103,6 +110,7 @@ __device__ inline int64_t box_volume(const KdArgs &k, const int lo[3], const int
 // root: tight box of all flagged bricks (6 lanes of one wave)
 __global__ __launch_bounds__(64) void k_kd_root(KdArgs k)
 {
+    kd_priority();
     __shared__ int face[6];
     const int lane = threadIdx.x;
     const int lo[3] = {0, 0, 0}, hi[3] = {k.nb[0], k.nb[1], k.nb[2]};
@@ -432,6 +440,7 @@ constexpr int kKdSmallBricks = 32768;
 
 __global__ __launch_bounds__(1024) void k_kd_prefix_root_small(KdArgs k)
 {
+    kd_priority();
     extern __shared__ int32_t S[];
     const int nbx = k.nb[0], nby = k.nb[1], nbz = k.nb[2];
     const int nb = nbx * nby * nbz;
@@ -590,6 +599,7 @@ __device__ inline bool last_of_level(const KdArgs &k, uint32_t *last)
 // level copies it again).
 __global__ __launch_bounds__(256) void k_kd_level(KdArgs k)
 {
+    kd_priority();
     __shared__ int16_t tb[4][kMaxCand + 1][2][6];
     __shared__ Proj proj[4];
     __shared__ uint32_t scratch[5];
@@ -641,6 +651,7 @@ __device__ inline void slab_union(const int32_t *slab, int s0, int s1, int l[3],
 
 __global__ __launch_bounds__(256) void k_kd_level_tight(KdArgs k)
 {
+    kd_priority();
     extern __shared__ int32_t slab[];   // [nbx + nby + nbz][6]
     __shared__ int32_t box[6];
     __shared__ int64_t cost[kMaxCand];
@@ -790,6 +801,7 @@ __device__ inline void kd_half_box(const KdArgs &k, int64_t m, int lo[3], int hi
 // runs after it and takes the leaves' boxes from k.box.
 __global__ __launch_bounds__(256) void k_kd_tight(KdArgs k)
 {
+    kd_priority();
     __shared__ int red[6];
     const uint32_t count = k.hdr->kd_count;
     if (k.hdr->kd_begin != k.hdr->kd_end || (int64_t)count > k.cap) return;
@@ -850,6 +862,7 @@ __global__ __launch_bounds__(256) void k_kd_tight(KdArgs k)
 // With voxel-tight leaves, the leaves' boxes come from k_kd_tight.
 __global__ __launch_bounds__(256) void k_kd_pack(KdArgs k)
 {
+    kd_priority();
     const uint32_t count = k.hdr->kd_count;
     if (k.hdr->kd_begin != k.hdr->kd_end || (int64_t)count > k.cap) return;
     const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
