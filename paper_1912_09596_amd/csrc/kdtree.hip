@@ -6,8 +6,10 @@
 // query into a 3-D inclusive prefix count over the brick flags (the summed-
 // volume-table idea of Sec. 3.2, applied at brick granularity), so a tight
 // box is 6 binary searches and one wave evaluates every candidate plane of a
-// node at once: lanes take (candidate, side, face) tasks.  One launch
-// evaluates a whole level; a single-workgroup launch numbers the children in
+// node at once: lanes take (candidate, side, face) tasks.  Nodes at most 32
+// bricks wide read the grid bitmask into occupancy projections instead, from
+// which every child box is a few mask operations.  One launch evaluates a
+// whole level; its last workgroup to finish numbers the children in
 // breadth-first order (left child first) with a block scan.
 #include <algorithm>
 
@@ -165,69 +167,144 @@ __device__ inline int candidate(const int lo[3], const int hi[3], int bins, int 
 
 constexpr int kMaxCand = 45;   // 3 axes x (16 bins - 1)
 
+// Boxes up to this many bricks along every axis read their projections entry
+// by entry (a few entries: cheaper than building the tables below).
+constexpr int kProjLoopMax = 8;
+
 // Occupancy projections of a node whose brick box is at most 32 bricks along
 // every axis, relative to the box: X[y] = the x-bitmask of the flagged bricks
 // of row y (any z), XZ[z] = the x-bitmask of slab z (any y), YZ[z] = the
-// y-bitmask of slab z (bit y set where row (y, z) holds a flagged brick).
-// With them the tight box of either side of any plane is a few bitmask
-// reductions, instead of six binary searches over the prefix count (each step
-// a dependent round of eight loads).
+// y-bitmask of slab z (bit y set where row (y, z) holds a flagged brick),
+// and their transposes Tyx[x] (the rows holding column x), Tzx[x] (the
+// slabs holding column x) and Tzy[y] (the slabs holding row y).  Every
+// child box of a candidate plane is then a union over a prefix or a suffix
+// of one of these arrays (below), so the wave keeps, per array, the unions
+// of every prefix and every suffix: each (candidate, side) task is three
+// table reads instead of six binary searches over the prefix count (each
+// step a dependent round of eight loads) or a loop over the 32 entries.
 struct __align__(16) Proj {
     uint32_t X[32], XZ[32], YZ[32];
-    uint32_t T[32][33];            // T[z][y]: the x-bitmask of row (y, z) (padded: conflict-free columns)
+    union {
+        uint32_t T[32][33];   // T[z][y]: the x-bitmask of row (y, z) (padded: conflict-free columns)
+        uint32_t tab[64][8];  // afterwards: per lane, the prefix / suffix unions (see build_proj)
+    };
     int16_t ca[kMaxCand], cp[kMaxCand];   // the node's candidate planes: axis, plane
 };
 
 __device__ inline uint32_t low_bits(int n) { return n >= 32 ? 0xffffffffu : ((1u << n) - 1u); }
 
-// one wave: lane (y, h) reads the rows (y, z) with z of parity h from the
-// grid bitmask, eight slabs' loads in flight per round; X accumulates in
-// registers, YZ is a ballot per slab, XZ an OR over the rows of the slab
+// Transpose of the bit matrix held by each half of the wave (lane r of the
+// half holds row r, bit c its column c), nonzero only in its first `span`
+// rows and columns (a power of two): afterwards lane c holds column c.
+// Rounds of swapping the off-diagonal blocks of halving size; the blocks of
+// the rounds skipped (size >= span) are zero.
+__device__ inline uint32_t transpose32(uint32_t v, int span)
+{
+    const int lane = threadIdx.x & 63;
+    constexpr uint32_t keep[5] = {0x0000ffffu, 0x00ff00ffu, 0x0f0f0f0fu, 0x33333333u, 0x55555555u};
+#pragma unroll
+    for (int s = 0; s < 5; ++s) {
+        const int j = 16 >> s;
+        if (j >= span) continue;   // wave-uniform
+        const uint32_t m = keep[s];
+        const uint32_t o = (uint32_t)__shfl_xor((int)v, j, 64);
+        v = (lane & j) ? ((v & ~m) | ((o & ~m) >> j)) : ((v & m) | ((o & m) << j));
+    }
+    return v;
+}
+
+// unions over the lanes before (exclusive) and from (inclusive) each lane of
+// its 32-lane half, for the lanes below `span` (entries from span on are zero)
+__device__ inline void or_scans(uint32_t v, int span, uint32_t &pre, uint32_t &suf)
+{
+    uint32_t a = v, b = v;
+    for (int d = 1; d < span; d <<= 1) {
+        a |= (uint32_t)__shfl_up((int)a, d, 32);
+        b |= (uint32_t)__shfl_down((int)b, d, 32);
+    }
+    // every lane takes part in the shuffle (a lane outside EXEC supplies zero), then selects
+    const uint32_t prev = (uint32_t)__shfl_up((int)a, 1, 32);
+    pre = (threadIdx.x & 31) == 0 ? 0u : prev;
+    suf = b;
+}
+
+// One wave.  Lane (y, h) reads the rows (y, z) with z of parity h from the
+// grid bitmask, 16 slabs' words in flight per round; X accumulates in
+// registers, YZ is a ballot per slab, XZ an OR over the rows of the slab.
+// Then per half of the wave r1 = X (lanes 0-31) | XZ (lanes 32-63), r2 = YZ
+// (lanes 0-31), their transposes t1 = Tyx | Tzx and t2 = Tzy, and tab[lane]
+// = {pre r1, suf r1, pre r2, suf r2, pre t1, suf t1, pre t2, suf t2}.
+// Entries past the box's extents are zero.
 __device__ inline void build_proj(const KdArgs &k, const int lo[3], const int hi[3], Proj *P)
 {
     const int lane = threadIdx.x & 63;
     const int y = lane & 31, h = lane >> 5;
     const int ex = hi[0] - lo[0], ey = hi[1] - lo[1], ez = hi[2] - lo[2];
     const uint32_t full = low_bits(ex);
+    const uint64_t nb0 = (uint64_t)k.nb[0], nb1 = (uint64_t)k.nb[1];
     uint32_t xacc = 0u;
-    for (int z0 = 0; z0 < ez; z0 += 8) {
-        uint32_t m[4];
+    // rounds of 16 slabs, each row's words in flight before the first is used
+    for (int z0 = 0; z0 < ez; z0 += 16) {
+        uint32_t lw[8], hw[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
+            lw[u] = 0u;
+            hw[u] = 0u;
+            if (z0 + 2 * u >= ez) continue;   // wave-uniform
             const int z = z0 + 2 * u + h;
-            m[u] = 0u;
             if (y < ey && z < ez) {
                 // bits [base, base + ex) of the bitmask: the row's bricks lo_x .. hi_x - 1
                 const uint64_t base =
-                    (uint64_t)k.nb[0] * ((uint64_t)(lo[1] + y) + (uint64_t)k.nb[1] * (uint64_t)(lo[2] + z)) +
-                    (uint64_t)lo[0];
+                    nb0 * ((uint64_t)(lo[1] + y) + nb1 * (uint64_t)(lo[2] + z)) + (uint64_t)lo[0];
                 const uint64_t wi = base >> 5;
-                const int sh = (int)(base & 31u);
-                uint64_t w = k.grid[wi];
-                if (sh + ex > 32) w |= (uint64_t)k.grid[wi + 1] << 32;   // the row's last brick lies there
-                m[u] = (uint32_t)(w >> sh) & full;
+                lw[u] = k.grid[wi];
+                if ((int)(base & 31u) + ex > 32) hw[u] = k.grid[wi + 1];   // the row's last brick lies there
             }
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
+            if (z0 + 2 * u >= ez) continue;   // wave-uniform
             const int z = z0 + 2 * u + h;
-            xacc |= m[u];
-            const uint64_t bal = __ballot(m[u] != 0u);
+            const bool in = y < ey && z < ez;
+            const uint64_t base = nb0 * ((uint64_t)(lo[1] + y) + nb1 * (uint64_t)(lo[2] + z)) + (uint64_t)lo[0];
+            const uint64_t w = (uint64_t)lw[u] | ((uint64_t)hw[u] << 32);
+            const uint32_t m = in ? (uint32_t)(w >> (int)(base & 31u)) & full : 0u;
+            xacc |= m;
+            const uint64_t bal = __ballot(m != 0u);
             if (z < ez) {
-                P->T[z][y] = m[u];
+                P->T[z][y] = m;
                 if (y == 0) P->YZ[z] = (uint32_t)(bal >> (32 * h));
             }
         }
     }
     wave_lds_sync();
-    const uint32_t xo = xacc | __shfl_xor(xacc, 32, 64);   // even and odd slabs
-    if (lane < 32) P->X[lane] = xo;
-    if (lane < ez) {
-        uint32_t o = 0u;
+    const uint32_t xo = xacc | (uint32_t)__shfl_xor((int)xacc, 32, 64);   // even and odd slabs
+    uint32_t xz = 0u;
+    if (h == 1 && y < ez) {
 #pragma unroll 8
-        for (int yy = 0; yy < ey; ++yy) o |= P->T[lane][yy];
-        P->XZ[lane] = o;
+        for (int yy = 0; yy < ey; ++yy) xz |= P->T[y][yy];
     }
+    const int n = max(ex, max(ey, ez));
+    if (n <= kProjLoopMax) {
+        // the entries themselves (zero past the extents, but YZ)
+        if (h == 0) P->X[y] = xo; else P->XZ[y] = xz;
+        wave_lds_sync();
+        return;
+    }
+    const uint32_t r1 = h == 0 ? xo : xz;
+    const uint32_t r2 = h == 0 && y < ez ? P->YZ[y] : 0u;
+    wave_lds_sync();   // T is overwritten by the tables
+    // the smallest power of two covering every extent: the arrays are zero from there on
+    const int span = n <= 1 ? 1 : 1 << (32 - __builtin_clz((uint32_t)(n - 1)));
+    const uint32_t t1 = transpose32(r1, span), t2 = transpose32(r2, span);
+    uint4 lo4, hi4;
+    or_scans(r1, span, lo4.x, lo4.y);
+    or_scans(r2, span, lo4.z, lo4.w);
+    or_scans(t1, span, hi4.x, hi4.y);
+    or_scans(t2, span, hi4.z, hi4.w);
+    uint4 *row = reinterpret_cast<uint4 *>(P->tab[lane]);
+    row[0] = lo4;
+    row[1] = hi4;
     wave_lds_sync();
 }
 
@@ -259,19 +336,18 @@ __device__ inline int candidates_lds(const int lo[3], const int hi[3], int bins,
     return __popcll(bal);
 }
 
-// faces (absolute brick coordinates: lower bounds, then exclusive upper
-// bounds) of the tight box of the node's bricks below (side 0) or at and
-// above (side 1) plane p on axis a; both sides of a plane strictly inside a
-// tight box hold a flagged brick.  One loop over the projection entries for
-// every axis, with selects (lanes of a wave take different axes), the
-// entries read four at a time.
-__device__ inline void proj_child(const Proj *P, const int lo[3], const int hi[3], int a, int p, int side, int f[6])
+// The x-, y- and z-bitmasks (relative to the box) of the node's bricks below
+// (side 0) or at and above (side 1) plane p on axis a, from the entries: one
+// loop over them for every axis, with selects (lanes of a wave take
+// different axes), the entries read four at a time.
+__device__ inline void proj_masks_loop(const Proj *P, const int lo[3], const int hi[3], int a, int p, int side,
+                                       uint32_t m[3])
 {
     const int ey = hi[1] - lo[1], ez = hi[2] - lo[2];
     const int ea = hi[a] - lo[a];
     const uint32_t below = low_bits(p - lo[a]);
     const uint32_t am = side == 0 ? below : (low_bits(ea) & ~below);
-    const bool ax = a == 0, ay = a == 1, az = a == 2;
+    const bool ax = a == 0, ay = a == 1;
     const int n = max(ey, ez);
     uint32_t mx = 0u, my = 0u, mz = 0u;
     const uint4 *X4 = reinterpret_cast<const uint4 *>(P->X);
@@ -286,7 +362,7 @@ __device__ inline void proj_child(const Proj *P, const int lo[3], const int hi[3
         for (int u = 0; u < 4; ++u) {
             const int i = i0 + u;
             const uint32_t bit = 1u << (i & 31);
-            // entries past the box's extent hold an earlier node's values
+            // YZ entries past the box's extent hold an earlier node's values
             const uint32_t X = i < ey ? xv[u] : 0u;
             const uint32_t XZ = i < ez ? xzv[u] : 0u;
             const uint32_t YZ = i < ez ? yzv[u] : 0u;
@@ -300,10 +376,50 @@ __device__ inline void proj_child(const Proj *P, const int lo[3], const int hi[3
             mz |= ax ? ((XZ & am) ? bit : 0u) : (ay ? (qy ? bit : 0u) : ((in && YZ) ? bit : 0u));
         }
     }
-    const uint32_t m[3] = {mx, my, mz};
-    for (int q = 0; q < 3; ++q) {
-        f[q] = lo[q] + (int)__builtin_ctz(m[q]);
-        f[3 + q] = lo[q] + 32 - (int)__builtin_clz(m[q]);
+    m[0] = mx;
+    m[1] = my;
+    m[2] = mz;
+}
+
+// The same bitmasks from the tables.  With q = p - lo[a] and side 0 taking
+// entries [0, q), side 1 entries [q, extent):
+//   a = x: x-bits = X(all) & side, y-bits = union of Tyx, z-bits = union of Tzx
+//   a = y: x-bits = union of X,  y-bits = Y(all) & side, z-bits = union of Tzy
+//   a = z: x-bits = union of XZ, y-bits = union of YZ, z-bits = Z(all) & side
+// where the unions run over the side's entries (a prefix or a suffix).
+__device__ inline void proj_masks_tab(const Proj *P, const int lo[3], const int hi[3], int a, int p, int side,
+                                      uint32_t m[3])
+{
+    const int q = p - lo[a];
+    const uint32_t below = low_bits(q);
+    const uint32_t am = side == 0 ? below : (low_bits(hi[a] - lo[a]) & ~below);
+    const uint32_t *t = &P->tab[0][0];
+    // tab[lane][2 * array + side], arrays r1, r2, t1, t2 (build_proj)
+    const uint32_t vx = t[(a == 2 ? 32 + q : q) * 8 + side];
+    const uint32_t vy = t[q * 8 + (a == 0 ? 4 : 2) + side];
+    const uint32_t vz = t[(a == 0 ? 32 + q : q) * 8 + (a == 0 ? 4 : 6) + side];
+    // the unions of whole arrays: X over all rows, Y = rows holding a brick (YZ over all
+    // slabs), Z = slabs holding a brick (Tzx over all columns)
+    m[0] = a == 0 ? (t[0 * 8 + 1] & am) : vx;
+    m[1] = a == 1 ? (t[0 * 8 + 3] & am) : vy;
+    m[2] = a == 2 ? (t[32 * 8 + 5] & am) : vz;
+}
+
+// faces (absolute brick coordinates: lower bounds, then exclusive upper
+// bounds) of the tight box of the node's bricks below (side 0) or at and
+// above (side 1) plane p on axis a; both sides of a plane strictly inside a
+// tight box hold a flagged brick.
+__device__ inline void proj_child(const Proj *P, const int lo[3], const int hi[3], int a, int p, int side, int f[6])
+{
+    const int n = max(hi[0] - lo[0], max(hi[1] - lo[1], hi[2] - lo[2]));
+    uint32_t m[3];
+    if (n <= kProjLoopMax)   // wave-uniform: the node's box
+        proj_masks_loop(P, lo, hi, a, p, side, m);
+    else
+        proj_masks_tab(P, lo, hi, a, p, side, m);
+    for (int i = 0; i < 3; ++i) {
+        f[i] = lo[i] + (int)__builtin_ctz(m[i]);
+        f[3 + i] = lo[i] + 32 - (int)__builtin_clz(m[i]);
     }
 }
 
