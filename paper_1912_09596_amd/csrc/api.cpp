@@ -271,7 +271,7 @@ static esk_status kd_finish(esk_ctx *c)
     while (c->pinned->kd_end > c->pinned->kd_begin) {
         if (c->kd_levels_enqueued > 4 * (c->vol.nb[0] + c->vol.nb[1] + c->vol.nb[2]) + 64)
             return fail(c, ESK_EINTERNAL, "k-d build did not terminate");
-        hipError_t e = launch_kd_levels(k, 8, c->stream);
+        hipError_t e = launch_kd_levels(k, 8, (uint32_t)c->kd_levels_enqueued, c->stream);
         if (e == hipSuccess) e = launch_kd_pack(k, 2 * c->L.nb, c->stream);
         if (e != hipSuccess) return hip_check(c, e, "k-d level launch");
         c->kd_levels_enqueued += 8;
@@ -625,7 +625,7 @@ esk_status esk_set_transfer_function(esk_ctx *c, const float *d_rgba, int n_entr
         }
         // levels are enqueued speculatively (a launch past the last level
         // exits at once); completion is checked when the tree is first used
-        if (e == hipSuccess) e = launch_kd_levels(k, c->kd_level_hint, c->aux);
+        if (e == hipSuccess) e = launch_kd_levels(k, c->kd_level_hint, 0, c->aux);
         if (e == hipSuccess) e = launch_kd_pack(k, 2 * L.nb, c->aux);
         if (e == hipSuccess)
             e = hipMemcpyAsync(c->pinned_kd, at<DevHeader>(c, L.header), sizeof(DevHeader), hipMemcpyDeviceToHost,

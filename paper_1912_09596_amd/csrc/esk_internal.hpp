@@ -48,9 +48,14 @@ struct DevHeader {
     uint32_t kd_ticket;    // blocks of the current k-d level launch that finished
     uint32_t kd_vroot_lo;  // voxel-tight split cost: the root's union volume
     uint32_t kd_vroot_hi;  //   (half-voxel units, 64 bits)
-    uint32_t pad[55];
+    // what k-d level launch i finds in slot i % 2 (the launch before it wrote it):
+    // {kKdNumbered, begin, end}: evaluate the level [begin, end), its parents listed in plist;
+    // {kKdToNumber, begin, end}: the level [begin, end) was evaluated, its children are not numbered yet
+    uint32_t kd_next[2][3];
+    uint32_t pad[49];
 };
 static_assert(sizeof(DevHeader) == 256, "header is one 256-byte slot");
+constexpr uint32_t kKdNumbered = 1, kKdToNumber = 2;
 
 // Byte offsets of every array inside the caller's workspace.
 struct Layout {
@@ -175,7 +180,7 @@ bool kd_small(const KdArgs &k);
 hipError_t launch_kd_prefix_root_small(const KdArgs &k, hipStream_t s);
 hipError_t launch_kd_prefix(const KdArgs &k, hipStream_t s);
 hipError_t launch_kd_root(const KdArgs &k, hipStream_t s);
-hipError_t launch_kd_levels(const KdArgs &k, int count, hipStream_t s);
+hipError_t launch_kd_levels(const KdArgs &k, int count, uint32_t first_launch, hipStream_t s);
 hipError_t launch_kd_pack(const KdArgs &k, int64_t max_nodes, hipStream_t s);
 
 struct RenderArgs {

@@ -125,6 +125,9 @@ __global__ __launch_bounds__(64) void k_kd_root(KdArgs k)
             k.hdr->kd_end = 0;
             k.hdr->kd_ticket = 0;
             k.hdr->pad[0] = 0;
+            k.hdr->kd_next[0][0] = kKdNumbered;
+            k.hdr->kd_next[0][1] = 0;
+            k.hdr->kd_next[0][2] = 0;
         }
         return;
     }
@@ -141,6 +144,9 @@ __global__ __launch_bounds__(64) void k_kd_root(KdArgs k)
         k.hdr->kd_end = 1;
         k.hdr->kd_ticket = 0;
         k.hdr->pad[0] = 0;
+        k.hdr->kd_next[0][0] = kKdNumbered;
+        k.hdr->kd_next[0][1] = 0;
+        k.hdr->kd_next[0][2] = 1;
     }
 }
 
@@ -427,10 +433,12 @@ __device__ inline void proj_child(const Proj *P, const int lo[3], const int hi[3
 // from the node's occupancy projections where the node spans at most 32
 // bricks per axis, else every (candidate plane, side, face) binary search
 // over the prefix count runs on its own lane; lane 0 writes axis, plane,
-// split flag and the two children's tight boxes.  tb, P: this wave's scratch.
+// split flag and the two children's tight boxes.  plist: the level's
+// splitting parents in order (the parent of node begin + r is plist[r / 2]);
+// tb, P: this wave's scratch.
 template <typename SP>
-__device__ void eval_node(const KdArgs &k, SP S, int64_t node, int64_t begin, int64_t vroot, int16_t (*tb)[2][6],
-                          Proj *P)
+__device__ void eval_node(const KdArgs &k, SP S, const int32_t *plist, int64_t node, int64_t begin, int64_t vroot,
+                          int16_t (*tb)[2][6], Proj *P)
 {
     const int lane = threadIdx.x & 63;
     int lo[3], hi[3];
@@ -443,7 +451,7 @@ __device__ void eval_node(const KdArgs &k, SP S, int64_t node, int64_t begin, in
         // child `side` of the (r/2)-th splitting node of the level above: its
         // box from the parent's child boxes, recorded for later readers
         const int64_t r = node - begin;
-        const int64_t p = k.plist[r >> 1];
+        const int64_t p = plist[r >> 1];
         const int32_t *cb = &k.clo[12 * p + 6 * (r & 1)];
         for (int q = 0; q < 3; ++q) {
             lo[q] = cb[q];
@@ -602,14 +610,19 @@ __global__ __launch_bounds__(1024) void k_kd_prefix_root_small(KdArgs k)
         k.hdr->kd_end = any ? 1u : 0u;
         k.hdr->kd_ticket = 0;
         k.hdr->pad[0] = 0;
+        k.hdr->kd_next[0][0] = kKdNumbered;
+        k.hdr->kd_next[0][1] = 0;
+        k.hdr->kd_next[0][2] = any ? 1u : 0u;
     }
 }
 
 // One level per launch, no host round trip: the level bounds come from the
 // device header (a level past the last one finds begin == end and exits).
-// Waves of a fixed grid evaluate the level's nodes; the last block to finish
-// (ticket counter, agent-scope release/acquire) numbers the children in
-// breadth-first order and publishes the next level.
+// Waves of a fixed grid evaluate the level's nodes.  The children of a level
+// of at most kKdNumberLds nodes are numbered by every block of the next
+// launch from the split flags; those of a wider level by the last block of
+// its own launch to finish (ticket counter, agent-scope release/acquire),
+// which publishes the next level.  Either way in breadth-first order.
 // Workgroups per level launch, from the brick count (nb / 1024, clamped to
 // [32, 1024]): small grids have narrow levels, and the build runs beside the
 // first renders, so it should hold few CUs; wide levels of large grids need
@@ -625,7 +638,7 @@ inline int kd_level_blocks(const KdArgs &k)
 // split flag of the level is visible to it): children in parent order, the
 // first child of each splitting parent, the ordered list of splitting
 // parents, and the next level's bounds in the header.
-__device__ void number_children(const KdArgs &k, uint32_t begin, uint32_t end, uint32_t *scratch)
+__device__ void number_children(const KdArgs &k, uint32_t begin, uint32_t end, uint32_t *scratch, uint32_t *slot)
 {
     const int64_t width = (int64_t)end - begin;
     const int64_t per = (width + 255) / 256;
@@ -684,8 +697,63 @@ __device__ void number_children(const KdArgs &k, uint32_t begin, uint32_t end, u
         k.hdr->kd_count = next;
         if (fits && total > 0) k.hdr->kd_height += 1;
         k.hdr->kd_ticket = 0;
+        if (slot) {
+            slot[0] = kKdNumbered;
+            slot[1] = end;
+            slot[2] = next;
+        }
         __threadfence();
     }
+}
+
+// Widest level whose children the next level launch numbers itself: every
+// block of that launch scans the level's split flags (at most 8 per thread)
+// and lists the splitting parents in LDS, so no block of the level's own
+// launch waits for the others (no ticket, no last-block numbering).
+constexpr int kKdNumberLds = 2048;
+
+// Numbering of the children of the level [pb, pe) (pe - pb <= kKdNumberLds),
+// done by every block of the launch that evaluates them: the splitting
+// parents in order into parents[], the children's level into [*begin, *end).
+// Block 0 also records each splitting parent's first child and the level in
+// the header, as number_children does.
+__device__ void number_in_block(const KdArgs &k, uint32_t pb, uint32_t pe, int32_t *parents, uint32_t *scratch,
+                                uint32_t *begin, uint32_t *end)
+{
+    constexpr int U = kKdNumberLds / 256;
+    const int64_t width = (int64_t)pe - pb;
+    const int64_t per = (width + 255) / 256;   // <= U
+    const int64_t i0 = pb + threadIdx.x * per;
+    const int64_t i1 = min((int64_t)pe, i0 + per);
+    int32_t f[U];
+    uint32_t c = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        f[u] = i0 + u < i1 ? k.split[i0 + u] : 0;
+        c += f[u] != 0 ? 1u : 0u;
+    }
+    uint32_t total;
+    uint32_t run = block_exclusive_scan<256>(c, scratch, &total);
+    const bool fits = (int64_t)pe + 2 * (int64_t)total <= k.cap;
+    const bool first = blockIdx.x == 0 && fits;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (f[u]) {
+            parents[run] = (int32_t)(i0 + u);
+            if (first) k.first[i0 + u] = (int32_t)((int64_t)pe + 2 * (int64_t)run);
+            ++run;
+        }
+    __syncthreads();
+    const uint32_t next = fits ? pe + 2 * total : pe;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (!fits) k.hdr->pad[0] = 1u;  // cannot happen for a correct build: stop growing
+        k.hdr->kd_begin = pe;
+        k.hdr->kd_end = next;
+        k.hdr->kd_count = next;
+        if (fits && total > 0) k.hdr->kd_height += 1;
+    }
+    *begin = pe;
+    *end = next;
 }
 
 // The last workgroup of a level launch to arrive (ticket counter) numbers
@@ -712,23 +780,43 @@ __device__ inline bool last_of_level(const KdArgs &k, uint32_t *last)
 
 // The binary searches read the prefix count through L2 (staging the whole
 // table in LDS per workgroup was measured slower: every busy workgroup of a
-// level copies it again).
-__global__ __launch_bounds__(256) void k_kd_level(KdArgs k)
+// level copies it again).  li: the launch's index in the build (its slot of
+// kd_next is li % 2; it writes the other one for the next launch).
+__global__ __launch_bounds__(256) void k_kd_level(KdArgs k, uint32_t li)
 {
     kd_priority();
     __shared__ int16_t tb[4][kMaxCand + 1][2][6];
     __shared__ Proj proj[4];
     __shared__ uint32_t scratch[5];
     __shared__ uint32_t last;
-    const uint32_t begin = k.hdr->kd_begin, end = k.hdr->kd_end;
-    if (begin == end) return;
+    __shared__ int32_t parents[kKdNumberLds];
+    const uint32_t *in = k.hdr->kd_next[li & 1u];
+    uint32_t *out = k.hdr->kd_next[(li + 1u) & 1u];
+    const uint32_t mode = in[0];
+    uint32_t begin = in[1], end = in[2];
+    const int32_t *plist = k.plist;
+    if (mode == kKdToNumber) {
+        // the launch before evaluated [begin, end) and left its children to this one
+        number_in_block(k, begin, end, parents, scratch, &begin, &end);
+        plist = parents;
+    }
+    const uint32_t width = end - begin;
+    const bool narrow = width <= (uint32_t)kKdNumberLds;
+    if (narrow && blockIdx.x == 0 && threadIdx.x == 0) {
+        // the next launch numbers this level's children (or finds the build finished)
+        out[0] = width == 0 ? kKdNumbered : kKdToNumber;
+        out[1] = begin;
+        out[2] = end;
+    }
+    if (width == 0) return;
     const int wave = threadIdx.x >> 6;
     const int64_t vroot = root_volume(k);
     for (int64_t node = (int64_t)begin + (int64_t)blockIdx.x * 4 + wave; node < end;
          node += (int64_t)gridDim.x * 4) {
-        eval_node(k, (const int32_t *)k.S, node, (int64_t)begin, vroot, tb[wave], &proj[wave]);
+        eval_node(k, (const int32_t *)k.S, plist, node, (int64_t)begin, vroot, tb[wave], &proj[wave]);
     }
-    if (last_of_level(k, &last)) number_children(k, begin, end, scratch);
+    // a wide level: the last block to finish numbers the children and fills the next slot
+    if (!narrow && last_of_level(k, &last)) number_children(k, begin, end, scratch, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -898,7 +986,7 @@ __global__ __launch_bounds__(256) void k_kd_level_tight(KdArgs k)
         }
         __syncthreads();   // box, slabs and shared results are reused by the next node
     }
-    if (last_of_level(k, &last)) number_children(k, begin, end, scratch);
+    if (last_of_level(k, &last)) number_children(k, begin, end, scratch, nullptr);
 }
 
 // render box of node m from its brick box: voxels clipped to the volume, in
@@ -1039,7 +1127,7 @@ hipError_t launch_kd_prefix_root_small(const KdArgs &k, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_kd_levels(const KdArgs &k, int count, hipStream_t s)
+hipError_t launch_kd_levels(const KdArgs &k, int count, uint32_t first_launch, hipStream_t s)
 {
     const int blocks = kd_level_blocks(k);
     if (k.tight_cost) {
@@ -1054,7 +1142,8 @@ hipError_t launch_kd_levels(const KdArgs &k, int count, hipStream_t s)
             hipLaunchKernelGGL(k_kd_level_tight, dim3(blocks), dim3(256), lds, s, k);
         return hipGetLastError();
     }
-    for (int i = 0; i < count; ++i) hipLaunchKernelGGL(k_kd_level, dim3(blocks), dim3(256), 0, s, k);
+    for (int i = 0; i < count; ++i)
+        hipLaunchKernelGGL(k_kd_level, dim3(blocks), dim3(256), 0, s, k, first_launch + (uint32_t)i);
     return hipGetLastError();
 }
 
