@@ -616,7 +616,9 @@ esk_status esk_set_transfer_function(esk_ctx *c, const float *d_rgba, int n_entr
         e = hipEventRecord(c->ev_fork, c->stream);
         if (e == hipSuccess) e = hipStreamWaitEvent(c->aux, c->ev_fork, 0);
         if (e == hipSuccess) {
-            if (kd_small(k)) {
+            if (kd_projected(k)) {
+                e = launch_kd_root_bits(k, c->aux);
+            } else if (kd_small(k)) {
                 e = launch_kd_prefix_root_small(k, c->aux);
             } else {
                 e = launch_kd_prefix(k, c->aux);

@@ -176,6 +176,8 @@ struct KdArgs {
     int tight_cost;        // 1: split cost and compared volumes from the unions of the voxel-tight boxes
 };
 
+bool kd_projected(const KdArgs &k);
+hipError_t launch_kd_root_bits(const KdArgs &k, hipStream_t s);
 bool kd_small(const KdArgs &k);
 hipError_t launch_kd_prefix_root_small(const KdArgs &k, hipStream_t s);
 hipError_t launch_kd_prefix(const KdArgs &k, hipStream_t s);
