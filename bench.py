@@ -729,6 +729,35 @@ def trace_markdown(db, command):
     return "\n".join(out)
 
 
+def ranges_markdown(db, command):
+    """Host time of the library's entry points from a rocprofv3 --marker-trace
+    database (the named ranges each entry point opens): calls, median, 90th
+    percentile and maximum in microseconds."""
+    import collections
+    import json as _json
+    import sqlite3
+    c = sqlite3.connect(db)
+    per = collections.defaultdict(list)
+    for ext, dur in c.execute("select extdata, duration from regions where category like 'MARKER%'"):
+        try:
+            name = _json.loads(ext or "{}").get("message", "")
+        except ValueError:
+            name = ""
+        if name.startswith("esk_"):
+            per[name].append(dur / 1e3)
+    out = ["# Host time per entry point: 512^3 f32 noise volume, 1920x1080, grid + LBVH + k-d per TF", "",
+           "Command (from the repository root on the MI355X box):", "", "```", command, "```", "",
+           "Each entry point opens a named host range (roctx) for its duration: argument checks, "
+           "enqueueing its kernels and copies, and any wait it makes (esk_sync waits for the device).  "
+           "The first calls include allocations and module loading.", "",
+           "| entry point | calls | median us | p90 us | max us |", "|---|---:|---:|---:|---:|"]
+    for name in sorted(per, key=lambda n: -sum(per[n])):
+        v = sorted(per[name])
+        p90 = v[min(len(v) - 1, int(0.9 * len(v)))]
+        out.append(f"| `{name}` | {len(v)} | {statistics.median(v):.1f} | {p90:.1f} | {v[-1]:.1f} |")
+    return "\n".join(out)
+
+
 def counters_markdown(fetch_db, write_db, command):
     """HBM traffic per launch from FETCH_SIZE and WRITE_SIZE runs (KiB per
     dispatch), each scaled by what the counter reads for the 512 MiB device
@@ -874,6 +903,8 @@ def main():
                     help="print the kernel-trace summary of a rocprofv3 database and exit")
     ap.add_argument("--counters-md", nargs=3, metavar=("FETCH_DB", "WRITE_DB", "COMMAND"),
                     help="print the HBM traffic summary of two rocprofv3 --pmc databases and exit")
+    ap.add_argument("--ranges-md", nargs=2, metavar=("DB", "COMMAND"),
+                    help="print the host time per entry point from a rocprofv3 --marker-trace database and exit")
     ap.add_argument("--profile-frames", action="store_true",
                     help="render the profiled frame with every structure (for rocprofv3 --pmc runs) and exit")
     ap.add_argument("--issue-md", nargs=4, metavar=("DB_A", "DB_B", "FRAMES_JSON", "COMMAND"),
@@ -883,6 +914,9 @@ def main():
     args = ap.parse_args()
     if args.trace_md:
         print(trace_markdown(*args.trace_md))
+        return
+    if args.ranges_md:
+        print(ranges_markdown(*args.ranges_md))
         return
     if args.counters_md:
         print(counters_markdown(*args.counters_md))

@@ -29,7 +29,9 @@ def sources():
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp"
-    cmd = [hipcc, *FLAGS, "-I", os.path.join(ROOT, "include"), *sources(), "-o", tmp]
+    # host ranges (roctx) around the entry points
+    libs = ["-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
+    cmd = [hipcc, *FLAGS, "-I", os.path.join(ROOT, "include"), *sources(), *libs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

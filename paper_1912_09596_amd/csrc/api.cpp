@@ -14,6 +14,8 @@
 
 #include "esk_internal.hpp"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 namespace esk {
 
 int elem_size(int dtype)
@@ -253,6 +255,16 @@ esk_status join_builds(esk_ctx *c)
 
 }  // namespace
 
+// A named host range around each entry point that enqueues work (shown by
+// timeline tools that record markers, e.g. rocprofv3 --marker-trace); costs
+// a call into the marker library when no tool listens.
+struct HostRange {
+    explicit HostRange(const char *name) { roctxRangePushA(name); }
+    ~HostRange() { roctxRangePop(); }
+    HostRange(const HostRange &) = delete;
+    HostRange &operator=(const HostRange &) = delete;
+};
+
 static KdArgs kd_args(esk_ctx *c, const esk_kd_params *p);
 
 // Makes sure the enqueued k-d build has reached its last level (enqueuing
@@ -379,6 +391,7 @@ esk_status esk_workspace_bytes(int nx, int ny, int nz, int dtype, int brick, int
 esk_status esk_set_volume(esk_ctx *c, const void *d_vox, int dtype, int nx, int ny, int nz, float value_lo,
                           float value_hi, int brick, int max_tf_entries, void *d_ws, size_t ws_bytes)
 {
+    HostRange range("esk_set_volume");
     if (!c) return ESK_EINVAL;
     esk_status s = check_shape(c, nx, ny, nz, dtype, brick, max_tf_entries);
     if (s != ESK_OK) return s;
@@ -531,6 +544,7 @@ static KdArgs kd_args(esk_ctx *c, const esk_kd_params *p)
 esk_status esk_set_transfer_function(esk_ctx *c, const float *d_rgba, int n_entries, int build_mask,
                                      const esk_kd_params *kd)
 {
+    HostRange range("esk_set_transfer_function");
     if (!c) return ESK_EINVAL;
     if (!d_rgba) return fail(c, ESK_EINVAL, "TF pointer is null");
     if ((reinterpret_cast<uintptr_t>(d_rgba) & 15) != 0) return fail(c, ESK_EINVAL, "TF must be 16-byte aligned");
@@ -661,6 +675,7 @@ esk_status esk_rebuild_batch_bytes(int n, size_t *out)
 esk_status esk_rebuild_batch(esk_ctx *const *ctxs, int n, const float *const *d_tfs, const int *n_entries,
                              int build_mask, void *d_args, size_t args_bytes)
 {
+    HostRange range("esk_rebuild_batch");
     if (!ctxs || n < 1 || n > 65535 || !ctxs[0]) return ESK_EINVAL;
     esk_ctx *c0 = ctxs[0];
     if (!d_tfs || !n_entries) return fail(c0, ESK_EINVAL, "null request array");
@@ -906,6 +921,7 @@ extern "C" {
 esk_status esk_render(esk_ctx *c, int accel, const esk_camera *cam, int width, int height, float step,
                       float opacity_ref_step, float *d_rgba_out, int32_t *d_count_out)
 {
+    HostRange range("esk_render");
     RenderArgs r;
     esk_status st =
         prepare_render(c, accel, cam, width, height, step, opacity_ref_step, d_rgba_out, d_count_out, r, c->stream);
@@ -985,6 +1001,7 @@ esk_status esk_render_batch(esk_ctx *const *ctxs, int n, int accel, const esk_ca
                             const int *heights, float step, float opacity_ref_step, float *const *d_outs,
                             void *d_args, size_t args_bytes)
 {
+    HostRange range("esk_render_batch");
     if (!ctxs || n < 1 || n > 65535 || !ctxs[0]) return ESK_EINVAL;
     esk_ctx *c0 = ctxs[0];
     if (!d_args || (reinterpret_cast<uintptr_t>(d_args) & 15) != 0)
@@ -1019,6 +1036,7 @@ esk_status esk_render_batch_noalloc(esk_ctx *const *ctxs, int n, int accel, cons
                                     const int *widths, const int *heights, float step, float opacity_ref_step,
                                     float *const *d_outs)
 {
+    HostRange range("esk_render_batch_noalloc");
     if (!ctxs || n < 1 || !ctxs[0]) return ESK_EINVAL;
     esk_ctx *c0 = ctxs[0];
     if (n > kNoAllocBatchMax)
@@ -1039,6 +1057,7 @@ esk_status esk_render_batch_noalloc(esk_ctx *const *ctxs, int n, int accel, cons
 
 esk_status esk_sync(esk_ctx *c)
 {
+    HostRange range("esk_sync");
     if (!c) return ESK_EINVAL;
     if (c->device < 0) return fail(c, ESK_ESTATE, "validation-only context");
     hipError_t e = hipSetDevice(c->device);
