@@ -267,6 +267,46 @@ def test_multiblock_sort_path():
     assert ctx.stats()["n_bricks"] > 32768 and flags.sum() > 32768
 
 
+def test_kd_levels_wider_than_block_numbering():
+    """Thin tubes in 320^3 voxels, 4^3 bricks (512,000 bricks): the k-d trees
+    hold levels of more than 2048 nodes, whose children are numbered by the
+    last workgroup of their own level launch instead of by every workgroup of
+    the next one, so the build switches between both ways and back; every
+    node, the first-child links and the height bit-exact against the oracle,
+    and the k-d render equal to the full march."""
+    torch = _torch()
+    dims = (320, 320, 320)
+    log(f"case: k-d wide levels {dims} B=4")
+    vol = synth.tubes(dims, n_tubes=300, seed=3, radius=(1.0, 2.0))
+    tf = synth.tf_ramp(256, start=0.05)
+    B = 4
+    esk, ctx = make_ctx()
+    ctx.set_volume(to_dev(vol), B, (0.0, 1.0), max_tf=256)
+    dtf = to_dev(tf)
+    mn, mx = oracle.brick_minmax(vol, B)
+    flags = oracle.classify(mn, mx, vol.dtype, tf)
+    cam = synth.perspective(dims, 96, 64, synth.view_direction(5))
+    for kd in ((1, 0), (1, 32)):
+        log(f"case: k-d wide levels kd={kd}")
+        k = oracle.kd(flags, B, dims, kd[0], kd[1], 4)
+        # the premise: some level of the oracle's tree is wider than 2048 nodes
+        axis, begin, end, widest = k["axis"], 0, 1, 0
+        while begin < end:
+            widest = max(widest, end - begin)
+            begin, end = end, end + 2 * int((axis[begin:end] >= 0).sum())
+        assert widest > 2048, widest
+        ctx.set_tf(dtf, build=("kd",), kd=esk.Kd(kd[0], kd[1], 4))
+        torch.cuda.synchronize()
+        for name in ("lo", "hi", "axis", "plane"):
+            assert np.array_equal(ctx.export("kd_" + name), k[name]), (kd, name)
+        assert np.array_equal(ctx.export("kd_first"), k["first_child"]), kd
+        st = ctx.stats()
+        assert st["kd_nodes"] == len(k["axis"]) and st["kd_height"] == k["height"], kd
+        full = ctx.render(cam, 96, 64, accel="none").cpu().numpy()
+        img = ctx.render(cam, 96, 64, accel="kd").cpu().numpy()
+        assert np.array_equal(img, full), kd
+
+
 def test_rebuild_is_deterministic():
     w = synth.c1_workload()
     esk, ctx = make_ctx()
