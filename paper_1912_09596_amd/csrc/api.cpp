@@ -267,33 +267,40 @@ struct HostRange {
 
 static KdArgs kd_args(esk_ctx *c, const esk_kd_params *p);
 
-// Makes sure the enqueued k-d build has reached its last level (enqueuing
-// more levels if the speculative batch was short), then reads the node count
-// and height back.  Synchronises.
+// Makes sure the enqueued k-d build has reached its last level, then reads
+// the node count and height back.  Waits for the k-d stream only (work queued
+// on the main stream keeps running).  When the speculative batch of level
+// launches was short (the tree grew by more than the margin), more levels go
+// on the k-d stream too, beside the main stream's work, with a fresh header
+// copy and completion event, until the build has finished.
 static esk_status kd_finish(esk_ctx *c)
 {
     if (!c->kd_on_device) return ESK_OK;
-    // wait for the k-d stream only: work queued on the main stream keeps running
-    hipError_t e0 = hipEventSynchronize(c->ev_kd);
-    if (e0 != hipSuccess) return hip_check(c, e0, "waiting for the k-d build");
-    std::memcpy(c->pinned, c->pinned_kd, sizeof(DevHeader));
-    esk_status st = join_kd(c);
-    if (st != ESK_OK) return st;
     KdArgs k = kd_args(c, &c->kd_params);
-    while (c->pinned->kd_end > c->pinned->kd_begin) {
+    while (true) {
+        hipError_t e = hipEventSynchronize(c->ev_kd);
+        if (e != hipSuccess) return hip_check(c, e, "waiting for the k-d build");
+        std::memcpy(c->pinned, c->pinned_kd, sizeof(DevHeader));
+        if (c->pinned->kd_end <= c->pinned->kd_begin) break;
         if (c->kd_levels_enqueued > 4 * (c->vol.nb[0] + c->vol.nb[1] + c->vol.nb[2]) + 64)
             return fail(c, ESK_EINTERNAL, "k-d build did not terminate");
-        hipError_t e = launch_kd_levels(k, 8, (uint32_t)c->kd_levels_enqueued, c->stream);
-        if (e == hipSuccess) e = launch_kd_pack(k, 2 * c->L.nb, c->stream);
+        e = launch_kd_levels(k, 8, (uint32_t)c->kd_levels_enqueued, c->aux);
+        if (e == hipSuccess) e = launch_kd_pack(k, 2 * c->L.nb, c->aux);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->pinned_kd, at<DevHeader>(c, c->L.header), sizeof(DevHeader), hipMemcpyDeviceToHost,
+                               c->aux);
+        if (e == hipSuccess) e = hipEventRecord(c->ev_kd, c->aux);
         if (e != hipSuccess) return hip_check(c, e, "k-d level launch");
         c->kd_levels_enqueued += 8;
-        st = read_header(c);
-        if (st != ESK_OK) return st;
+        c->kd_joined = false;
     }
+    esk_status st = join_kd(c);
+    if (st != ESK_OK) return st;
     if (c->pinned->pad[0] != 0) return fail(c, ESK_EINTERNAL, "k-d node capacity exceeded");
     c->kd_count = c->pinned->kd_count;
     c->kd_height = c->pinned->kd_height;
-    c->kd_level_hint = std::max(16, (int)c->kd_height + 3);
+    // a tree of height h takes h + 1 launches (the last one finds no children)
+    c->kd_level_hint = std::max(16, (int)c->kd_height + 4);
     c->kd_on_device = false;
     return ESK_OK;
 }
