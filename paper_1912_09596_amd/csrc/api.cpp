@@ -267,6 +267,22 @@ struct HostRange {
 
 static KdArgs kd_args(esk_ctx *c, const esk_kd_params *p);
 
+// Sizes the next speculative batch of level launches from the last k-d build
+// if it has finished (a rebuild that follows it without a render in between,
+// so without kd_finish, learns its height too); never waits.
+static void kd_learn_hint(esk_ctx *c)
+{
+    if (!c->kd_on_device) return;
+    if (hipEventQuery(c->ev_kd) != hipSuccess) {
+        (void)hipGetLastError();   // "not ready" is no failure of the next call
+        return;
+    }
+    const DevHeader *h = c->pinned_kd;
+    if (h->kd_end > h->kd_begin || h->pad[0] != 0) return;   // short batch or failed build: kd_finish handles it
+    const int top = c->kd_tight_cost ? 0 : (int)h->kd_top_levels;
+    c->kd_level_hint = std::max(4, (int)h->kd_height + 4 - top);
+}
+
 // Makes sure the enqueued k-d build has reached its last level, then reads
 // the node count and height back.  Waits for the k-d stream only (work queued
 // on the main stream keeps running).  When the speculative batch of level
@@ -299,8 +315,10 @@ static esk_status kd_finish(esk_ctx *c)
     if (c->pinned->pad[0] != 0) return fail(c, ESK_EINTERNAL, "k-d node capacity exceeded");
     c->kd_count = c->pinned->kd_count;
     c->kd_height = c->pinned->kd_height;
-    // a tree of height h takes h + 1 launches (the last one finds no children)
-    c->kd_level_hint = std::max(16, (int)c->kd_height + 4);
+    // a tree of height h takes h + 1 level launches (the last one finds no
+    // children), less the levels the single-workgroup launch took; three spare
+    const int top = k.tight_cost ? 0 : (int)c->pinned->kd_top_levels;
+    c->kd_level_hint = std::max(4, (int)c->kd_height + 4 - top);
     c->kd_on_device = false;
     return ESK_OK;
 }
@@ -629,6 +647,7 @@ esk_status esk_set_transfer_function(esk_ctx *c, const float *d_rgba, int n_entr
         if (fork) c->lbvh_joined = false;
     }
     if (build_mask & ESK_ACCEL_KD) {
+        kd_learn_hint(c);
         c->kd_tight_cost = (build_mask & ESK_KD_TIGHT_COST) != 0;
         KdArgs k = kd_args(c, kd);
         c->kd_params = *kd;
@@ -646,8 +665,10 @@ esk_status esk_set_transfer_function(esk_ctx *c, const float *d_rgba, int n_entr
                 if (e == hipSuccess) e = launch_kd_root(k, c->aux);
             }
         }
-        // levels are enqueued speculatively (a launch past the last level
-        // exits at once); completion is checked when the tree is first used
+        // the first narrow levels in one workgroup, then the level launches,
+        // enqueued speculatively (a launch past the last level exits at
+        // once); completion is checked when the tree is first used
+        if (e == hipSuccess && !k.tight_cost) e = launch_kd_top(k, c->aux);
         if (e == hipSuccess) e = launch_kd_levels(k, c->kd_level_hint, 0, c->aux);
         if (e == hipSuccess) e = launch_kd_pack(k, 2 * L.nb, c->aux);
         if (e == hipSuccess)

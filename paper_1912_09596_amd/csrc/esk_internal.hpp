@@ -52,7 +52,8 @@ struct DevHeader {
     // {kKdNumbered, begin, end}: evaluate the level [begin, end), its parents listed in plist;
     // {kKdToNumber, begin, end}: the level [begin, end) was evaluated, its children are not numbered yet
     uint32_t kd_next[2][3];
-    uint32_t pad[49];
+    uint32_t kd_top_levels;  // levels the first (single-workgroup) k-d launch evaluated
+    uint32_t pad[48];
 };
 static_assert(sizeof(DevHeader) == 256, "header is one 256-byte slot");
 constexpr uint32_t kKdNumbered = 1, kKdToNumber = 2;
@@ -178,6 +179,7 @@ struct KdArgs {
 
 bool kd_projected(const KdArgs &k);
 hipError_t launch_kd_root_bits(const KdArgs &k, hipStream_t s);
+hipError_t launch_kd_top(const KdArgs &k, hipStream_t s);
 bool kd_small(const KdArgs &k);
 hipError_t launch_kd_prefix_root_small(const KdArgs &k, hipStream_t s);
 hipError_t launch_kd_prefix(const KdArgs &k, hipStream_t s);

@@ -445,11 +445,12 @@ __device__ inline void proj_child(const Proj *P, const int lo[3], const int hi[3
 // from the node's occupancy projections where the node spans at most 32
 // bricks per axis, else every (candidate plane, side, face) binary search
 // over the prefix count runs on its own lane; lane 0 writes axis, plane,
-// split flag and the two children's tight boxes.  plist: the level's
+// split flag and the two children's tight boxes, and every lane returns the
+// split flag.  plist: the level's
 // splitting parents in order (the parent of node begin + r is plist[r / 2]);
 // tb, P: this wave's scratch.
 template <typename SP>
-__device__ void eval_node(const KdArgs &k, SP S, const int32_t *plist, int64_t node, int64_t begin, int64_t vroot,
+__device__ bool eval_node(const KdArgs &k, SP S, const int32_t *plist, int64_t node, int64_t begin, int64_t vroot,
                           int16_t (*tb)[2][6], Proj *P)
 {
     const int lane = threadIdx.x & 63;
@@ -561,6 +562,7 @@ __device__ void eval_node(const KdArgs &k, SP S, const int32_t *plist, int64_t n
         if (axis < 0) k.first[node] = -1;
     }
     wave_lds_sync();
+    return axis >= 0;   // wave-uniform
 }
 
 __device__ inline int64_t root_volume(const KdArgs &k)
@@ -665,6 +667,74 @@ __global__ __launch_bounds__(1024) void k_kd_prefix_root_small(KdArgs k)
         k.hdr->kd_next[0][0] = kKdNumbered;
         k.hdr->kd_next[0][1] = 0;
         k.hdr->kd_next[0][2] = any ? 1u : 0u;
+    }
+}
+
+// The first levels of a tree, while they hold at most kKdTopWaves nodes,
+// in one workgroup: a wave per node, the children numbered in LDS by one
+// thread between levels (workgroup barriers instead of launches).  It hands
+// the first wider level over to the level launches as a numbered level (its
+// parents in the global list, slot 0) and records how many levels it took.
+constexpr int kKdTopWaves = 8;
+
+__global__ __launch_bounds__(64 * kKdTopWaves) void k_kd_top(KdArgs k)
+{
+    kd_priority();
+    __shared__ int16_t tb[kKdTopWaves][kMaxCand + 1][2][6];
+    __shared__ Proj proj[kKdTopWaves];
+    __shared__ int32_t parents[kKdTopWaves];
+    __shared__ int32_t split[kKdTopWaves];
+    __shared__ uint32_t level[3];   // begin, end, levels taken
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (threadIdx.x == 0) {
+        level[0] = k.hdr->kd_next[0][1];
+        level[1] = k.hdr->kd_next[0][2];
+        level[2] = 0;
+    }
+    __syncthreads();
+    const int64_t vroot = root_volume(k);
+    uint32_t height = k.hdr->kd_height;
+    while (true) {
+        const uint32_t begin = level[0], end = level[1];
+        if (end == begin || end - begin > (uint32_t)kKdTopWaves) break;
+        const int64_t node = (int64_t)begin + wave;
+        bool sp = false;
+        if (node < end)
+            sp = eval_node(k, (const int32_t *)k.S, level[2] == 0 ? k.plist : parents, node, (int64_t)begin, vroot,
+                           tb[wave], &proj[wave]);
+        if (node < end && lane == 0) split[wave] = sp ? 1 : 0;
+        __syncthreads();   // also makes the waves' global stores (child boxes) visible to the block
+        if (threadIdx.x == 0) {
+            uint32_t total = 0;
+            for (uint32_t i = 0; i < end - begin; ++i) total += split[i] ? 1u : 0u;
+            const bool fits = (int64_t)end + 2 * (int64_t)total <= k.cap;
+            uint32_t run = 0;
+            if (fits)
+                for (uint32_t i = 0; i < end - begin; ++i)
+                    if (split[i]) {
+                        parents[run] = (int32_t)(begin + i);
+                        k.plist[run] = (int32_t)(begin + i);
+                        k.first[begin + i] = (int32_t)((int64_t)end + 2 * (int64_t)run);
+                        ++run;
+                    }
+            if (!fits) k.hdr->pad[0] = 1u;  // cannot happen for a correct build: stop growing
+            level[0] = end;
+            level[1] = fits ? end + 2 * total : end;
+            level[2] += 1;
+        }
+        __syncthreads();
+        if (level[1] > level[0]) height += 1;
+    }
+    if (threadIdx.x == 0) {
+        const uint32_t begin = level[0], end = level[1];
+        k.hdr->kd_begin = begin;
+        k.hdr->kd_end = end;
+        k.hdr->kd_count = end;
+        k.hdr->kd_height = height;
+        k.hdr->kd_top_levels = level[2];
+        k.hdr->kd_next[0][0] = kKdNumbered;
+        k.hdr->kd_next[0][1] = begin;
+        k.hdr->kd_next[0][2] = end;
     }
 }
 
@@ -1164,6 +1234,12 @@ hipError_t launch_kd_pack(const KdArgs &k, int64_t max_nodes, hipStream_t s)
     if (k.tight)
         hipLaunchKernelGGL(k_kd_tight, dim3((unsigned)std::min<int64_t>(max_nodes, 2048)), dim3(256), 0, s, k);
     hipLaunchKernelGGL(k_kd_pack, dim3((unsigned)((max_nodes + 255) / 256)), dim3(256), 0, s, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_kd_top(const KdArgs &k, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_kd_top, dim3(1), dim3(64 * kKdTopWaves), 0, s, k);
     return hipGetLastError();
 }
 
