@@ -278,7 +278,12 @@ static void kd_learn_hint(esk_ctx *c)
         return;
     }
     const DevHeader *h = c->pinned_kd;
-    if (h->kd_end > h->kd_begin || h->pad[0] != 0) return;   // short batch or failed build: kd_finish handles it
+    if (h->pad[0] != 0) return;   // a failed build: kd_finish reports it
+    if (h->kd_end > h->kd_begin) {
+        // the tree outgrew its batch (kd_finish completes it if it is used): a longer one next time
+        c->kd_level_hint = c->kd_levels_enqueued + 8;
+        return;
+    }
     const int top = c->kd_tight_cost ? 0 : (int)h->kd_top_levels;
     c->kd_level_hint = std::max(4, (int)h->kd_height + 4 - top);
 }
