@@ -428,9 +428,7 @@ def small_config(esk, torch, reps=20):
 
     res = {"workload": "64^3 u8 blobs (~10% non-zero), 8^3 bricks, ramp TF, 128x128 perspective, step 0.5"}
     res["set_volume_ms"] = wall(lambda: ctx.set_volume(vol, w["brick"], max_tf=256))
-    # (the k-d rebuild with the completion check that esk_get_stats makes)
-    res["rebuild_ms"] = {a: wall(lambda a=a: ctx.set_tf(tf, build=(a,), kd=esk.Kd(1, 32, 4)) or
-                                 (ctx.stats() if a == "kd" else None) or ctx.sync())
+    res["rebuild_ms"] = {a: wall(lambda a=a: ctx.set_tf(tf, build=(a,), kd=esk.Kd(1, 32, 4)) or ctx.sync())
                          for a in ACCELS}
     ctx.set_tf(tf, build=ACCELS, kd=esk.Kd(1, 32, 4))
     out = torch.empty((w["H"], w["W"], 4), dtype=torch.float32, device="cuda")
@@ -501,8 +499,7 @@ def large_volumes(esk, torch, reps=3):
                     torch.cuda.synchronize()
                     t = time.perf_counter()
                     ctx.set_tf(tf, build=(a,), kd=kd)
-                    if a == "kd":
-                        ctx.stats()   # the k-d build complete (see the phase breakdown)
+                    ctx.sync()   # every structure complete (see the phase breakdown)
                     torch.cuda.synchronize()
                     times.append((time.perf_counter() - t) * 1e3)
                 rebuild[a] = round(statistics.median(times), 4)
@@ -551,8 +548,7 @@ def statistics_table(esk, torch, noise_vol, reps=3):
             torch.cuda.synchronize()
             t = time.perf_counter()
             ctx.set_tf(tf, build=build, kd=kd, kd_cost=kd_cost)
-            if "kd" in build:
-                ctx.stats()   # the k-d build complete (see the phase breakdown)
+            ctx.sync()   # every structure complete (see the phase breakdown)
             torch.cuda.synchronize()
             times.append((time.perf_counter() - t) * 1e3)
         return round(statistics.median(times), 4)
@@ -1011,8 +1007,8 @@ def main():
             torch.cuda.synchronize()
             t = time.perf_counter()
             ctx.set_tf(dtfs[i % 100], build=(a,), kd=kd)
-            if a == "kd":
-                ctx.stats()   # the build complete even where its speculative batch of level launches fell short
+            # esk_sync: every structure complete (a k-d batch of level launches that fell short is finished)
+            ctx.sync()
             torch.cuda.synchronize()
             times.append((time.perf_counter() - t) * 1e3)
         rebuild[a] = {"median_ms": statistics.median(times), "p99_ms": percentile(times, 99)}

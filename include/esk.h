@@ -287,7 +287,10 @@ esk_status esk_render_batch_noalloc(esk_ctx *const *ctxs, int n, int accel, cons
                                     const int *widths, const int *heights, float step, float opacity_ref_step,
                                     float *const *d_outs);
 
-/* Waits for the context's stream and its internal build streams; reports
+/* Waits for the context's stream and its internal build streams, and
+ * finishes a k-d build whose speculative batch of level launches fell short
+ * of the tree (more levels are enqueued and waited for), so every structure
+ * built by the last esk_set_transfer_function is complete on return; reports
  * device faults. */
 esk_status esk_sync(esk_ctx *ctx);
 

@@ -1094,7 +1094,12 @@ esk_status esk_sync(esk_ctx *c)
     if (!c) return ESK_EINVAL;
     if (c->device < 0) return fail(c, ESK_ESTATE, "validation-only context");
     hipError_t e = hipSetDevice(c->device);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_check(c, e, "hipSetDevice");
+    if (c->has_tf && (c->built & ESK_ACCEL_KD)) {
+        const esk_status s = kd_finish(c);
+        if (s != ESK_OK) return s;
+    }
+    e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess && c->aux) e = hipStreamSynchronize(c->aux);
     if (e == hipSuccess && c->aux2) e = hipStreamSynchronize(c->aux2);
     return hip_check(c, e, "stream synchronize");
