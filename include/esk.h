@@ -253,6 +253,30 @@ esk_status esk_rebuild_batch(esk_ctx *const *ctxs, int n, const float *const *d_
 esk_status esk_render(esk_ctx *ctx, int accel, const esk_camera *cam, int width, int height,
                       float step, float opacity_ref_step, float *d_rgba_out, int32_t *d_count_out);
 
+/* Several frames of one context in one call (Sec. 4.1, as esk_render per
+ * frame), typically one view rendered with several structures: frame i is
+ * exactly esk_render(ctx, accels[i], &cams[i], widths[i], heights[i], step,
+ * opacity_ref_step, d_outs[i], d_counts ? d_counts[i] : NULL).  The frames
+ * of the k-d tree (and hybrid), of the LBVH and of the other modes run on
+ * three streams (the context's internal build streams and its own), so the
+ * kernels of different structures overlap; every frame is complete on the
+ * context's stream when the work enqueued after this call runs, as after n
+ * esk_render calls.  Frames must not share an output.  n in [1,
+ * ESK_RENDER_MULTI_MAX].  All frames are checked before any is enqueued; a
+ * frame failing after the checks (a device error, a k-d tree too tall)
+ * leaves the frames before it enqueued and joined. */
+#define ESK_RENDER_MULTI_MAX 8
+
+/* The stream (a hipStream_t) on which esk_render_multi runs the frames of
+ * `accel` outside a graph capture: for timing or ordering against them only
+ * (events recorded there around a call bracket that call's frames of
+ * `accel`).  Work the caller enqueues there runs in order with the
+ * context's builds and frames. */
+esk_status esk_render_stream(esk_ctx *ctx, int accel, void **stream_out);
+esk_status esk_render_multi(esk_ctx *ctx, int n, const int *accels, const esk_camera *cams, const int *widths,
+                            const int *heights, float step, float opacity_ref_step, float *const *d_outs,
+                            int32_t *const *d_counts);
+
 /* Batched rendering: n requests (each a context with its own volume, TF and
  * hierarchy, all of the same volume dtype and on one device) rendered by one
  * kernel launch on ctxs[0]'s stream, request i into d_outs[i] (heights[i] x

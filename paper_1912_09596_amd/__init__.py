@@ -96,6 +96,9 @@ def lib() -> ctypes.CDLL:
     L.esk_set_volume.argtypes = [P, P, i32, i32, i32, i32, f32, f32, i32, i32, P, sz]
     L.esk_set_transfer_function.argtypes = [P, P, i32, i32, ctypes.POINTER(KdParams)]
     L.esk_render.argtypes = [P, i32, ctypes.POINTER(Camera), i32, i32, f32, f32, P, P]
+    L.esk_render_stream.argtypes = [P, i32, ctypes.POINTER(P)]
+    L.esk_render_multi.argtypes = [P, i32, ctypes.POINTER(i32), ctypes.POINTER(Camera), ctypes.POINTER(i32),
+                                   ctypes.POINTER(i32), f32, f32, ctypes.POINTER(P), ctypes.POINTER(P)]
     L.esk_sync.argtypes = [P]
     L.esk_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
     L.esk_export.argtypes = [P, i32, P, sz, ctypes.POINTER(sz)]
@@ -111,8 +114,8 @@ def lib() -> ctypes.CDLL:
     L.esk_rebuild_batch_bytes.argtypes = [i32, ctypes.POINTER(sz)]
     L.esk_rebuild_batch.argtypes = [ctypes.POINTER(P), i32, ctypes.POINTER(P), ctypes.POINTER(i32), i32, P, sz]
     for name in ("esk_create", "esk_destroy", "esk_workspace_bytes", "esk_set_volume",
-                 "esk_set_transfer_function", "esk_render", "esk_sync", "esk_get_stats", "esk_export",
-                 "esk_render_batch_bytes", "esk_render_batch", "esk_render_batch_noalloc",
+                 "esk_set_transfer_function", "esk_render", "esk_render_multi", "esk_render_stream", "esk_sync",
+                 "esk_get_stats", "esk_export", "esk_render_batch_bytes", "esk_render_batch", "esk_render_batch_noalloc",
                  "esk_rebuild_batch_bytes", "esk_rebuild_batch"):
         getattr(L, name).restype = i32
     _lib = L
@@ -279,6 +282,48 @@ class Context:
                                          ctypes.c_void_p(out.data_ptr()),
                                          ctypes.c_void_p(counts.data_ptr()) if counts is not None else None))
         return out
+
+    def render_multi(self, frames, step=0.5, ref=1.0):
+        """Several frames in one call (esk_render_multi): frames is a list of
+        dicts with keys cam, W, H, accel and optionally out and counts (as in
+        render); the frames of different structures render concurrently.
+        Returns the list of output tensors."""
+        import torch
+        n = len(frames)
+        if n < 1:
+            raise ValueError("no frames")
+        outs, cnts = [], []
+        for f in frames:
+            W, H = int(f["W"]), int(f["H"])
+            out = f.get("out")
+            if out is None:
+                out = torch.empty((H, W, 4), dtype=torch.float32, device=self._keep["vol"].device)
+                self._on_stream(out)
+            _require(out, "out", self.device, torch.float32, (H, W, 4))
+            cnt = f.get("counts")
+            if cnt is not None:
+                _require(cnt, "counts", self.device, torch.int32, (H, W))
+            outs.append(out)
+            cnts.append(cnt)
+        accels = (ctypes.c_int * n)(*[ACCEL[f["accel"]] if isinstance(f["accel"], str) else int(f["accel"])
+                                      for f in frames])
+        cams = (Camera * n)(*[camera_struct(f["cam"]) for f in frames])
+        widths = (ctypes.c_int * n)(*[int(f["W"]) for f in frames])
+        heights = (ctypes.c_int * n)(*[int(f["H"]) for f in frames])
+        out_ptrs = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+        cnt_ptrs = (ctypes.c_void_p * n)(*[c.data_ptr() if c is not None else None for c in cnts])
+        has_cnt = any(c is not None for c in cnts)
+        self._check(self._lib.esk_render_multi(self._ctx, n, accels, cams, widths, heights, float(step), float(ref),
+                                               out_ptrs, cnt_ptrs if has_cnt else None))
+        return outs
+
+    def render_stream(self, accel) -> int:
+        """The HIP stream handle on which render_multi runs the frames of
+        `accel` (for events that time them)."""
+        h = ctypes.c_void_p()
+        self._check(self._lib.esk_render_stream(self._ctx, ACCEL[accel] if isinstance(accel, str) else int(accel),
+                                                ctypes.byref(h)))
+        return h.value or 0
 
     def sync(self):
         self._check(self._lib.esk_sync(self._ctx))

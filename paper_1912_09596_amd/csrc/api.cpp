@@ -142,6 +142,7 @@ struct esk_ctx {
     // point, so the grid render starts right after classification
     hipStream_t aux2 = nullptr;
     hipEvent_t ev_lbvh = nullptr;
+    hipEvent_t ev_join[2] = {nullptr, nullptr};  // esk_render_multi: the frames on aux2 / aux done
     bool lbvh_joined = true;          // main stream already ordered after the last LBVH build
     bool rebuild_compacts = false;    // the last rebuild (and any replay of it) writes ids/keys
 };
@@ -370,6 +371,7 @@ esk_status esk_create(int device, void *hip_stream, esk_ctx **out)
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_kd, hipEventDisableTiming);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->aux2, hipStreamNonBlocking);  // default priority
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_lbvh, hipEventDisableTiming);
+        for (int j = 0; j < 2 && e == hipSuccess; ++j) e = hipEventCreateWithFlags(&c->ev_join[j], hipEventDisableTiming);
         // once per device: the address of the allocation-free batch's argument array
         if (e == hipSuccess) e = noalloc_init(device);
         if (e != hipSuccess) {
@@ -403,6 +405,8 @@ esk_status esk_destroy(esk_ctx *c)
         if (c->aux2) (void)hipStreamSynchronize(c->aux2);
         if (c->aux2) (void)hipStreamDestroy(c->aux2);
         if (c->ev_lbvh) (void)hipEventDestroy(c->ev_lbvh);
+        for (int j = 0; j < 2; ++j)
+            if (c->ev_join[j]) (void)hipEventDestroy(c->ev_join[j]);
         if (c->pinned_kd) (void)hipHostFree(c->pinned_kd);
     }
     delete c;
@@ -876,9 +880,9 @@ static void centre_tile(const VolumeDesc &v, const esk_camera &cam, int W, int H
 
 // validates one render request and fills its kernel arguments (may
 // synchronise once to finish a pending k-d build)
-static esk_status prepare_render(esk_ctx *c, int accel, const esk_camera *cam, int width, int height, float step,
-                                 float opacity_ref_step, float *d_rgba_out, int32_t *d_count_out, RenderArgs &r,
-                                 hipStream_t launch_stream)
+// The host checks of one frame (no device work, no state change).
+static esk_status check_render(esk_ctx *c, int accel, const esk_camera *cam, int width, int height, float step,
+                               float opacity_ref_step, float *d_rgba_out, int32_t *d_count_out)
 {
     if (!c) return ESK_EINVAL;
     if (!cam) return fail(c, ESK_EINVAL, "camera is null");
@@ -902,6 +906,15 @@ static esk_status prepare_render(esk_ctx *c, int accel, const esk_camera *cam, i
     const int needs = accel == ESK_ACCEL_HYBRID ? (int)ESK_ACCEL_KD : accel;
     if (accel != ESK_ACCEL_NONE && !(c->built & needs))
         return fail(c, ESK_ESTATE, "accel %d was not built by the last rebuild", accel);
+    return ESK_OK;
+}
+
+static esk_status prepare_render(esk_ctx *c, int accel, const esk_camera *cam, int width, int height, float step,
+                                 float opacity_ref_step, float *d_rgba_out, int32_t *d_count_out, RenderArgs &r,
+                                 hipStream_t launch_stream)
+{
+    esk_status cs = check_render(c, accel, cam, width, height, step, opacity_ref_step, d_rgba_out, d_count_out);
+    if (cs != ESK_OK) return cs;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_check(c, e, "hipSetDevice");
     const Layout &L = c->L;
@@ -960,6 +973,78 @@ esk_status esk_render(esk_ctx *c, int accel, const esk_camera *cam, int width, i
         prepare_render(c, accel, cam, width, height, step, opacity_ref_step, d_rgba_out, d_count_out, r, c->stream);
     if (st != ESK_OK) return st;
     return hip_check(c, launch_render(accel, r, c->stream), "render launch");
+}
+
+esk_status esk_render_multi(esk_ctx *c, int n, const int *accels, const esk_camera *cams, const int *widths,
+                            const int *heights, float step, float opacity_ref_step, float *const *d_outs,
+                            int32_t *const *d_counts)
+{
+    HostRange range("esk_render_multi");
+    if (!c) return ESK_EINVAL;
+    if (n < 1 || n > ESK_RENDER_MULTI_MAX)
+        return fail(c, ESK_EINVAL, "%d frames (1 to %d in one call)", n, ESK_RENDER_MULTI_MAX);
+    if (!accels || !cams || !widths || !heights || !d_outs) return fail(c, ESK_EINVAL, "null frame array");
+    for (int i = 0; i < n; ++i) {
+        esk_status st = check_render(c, accels[i], &cams[i], widths[i], heights[i], step, opacity_ref_step,
+                                     d_outs[i], d_counts ? d_counts[i] : nullptr);
+        if (st != ESK_OK) return st;
+    }
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_check(c, e, "hipSetDevice");
+    // each frame on the stream of the build it reads (k-d and hybrid: the k-d
+    // build's, LBVH: the LBVH build's, others: the context's), so frames of
+    // different structures run concurrently and fill each other's tails; a
+    // stream being captured keeps every frame (a capture joins no fork here)
+    const bool cap = capturing(c->stream);
+    hipStream_t sx[3] = {c->stream, c->aux2, c->aux};
+    auto lane_of = [&](int accel) {
+        if (cap) return 0;
+        return accel == ESK_ACCEL_LBVH ? 1 : (accel == ESK_ACCEL_KD || accel == ESK_ACCEL_HYBRID) ? 2 : 0;
+    };
+    bool used[3] = {false, false, false};
+    for (int i = 0; i < n; ++i) used[lane_of(accels[i])] = true;
+    // the forked frames start after everything enqueued on the context's stream
+    if (used[1] || used[2]) {
+        e = hipEventRecord(c->ev_fork, c->stream);
+        for (int j = 1; j < 3 && e == hipSuccess; ++j)
+            if (used[j]) e = hipStreamWaitEvent(sx[j], c->ev_fork, 0);
+        if (e != hipSuccess) return hip_check(c, e, "render fork");
+    }
+    // frames without the k-d tree first: a k-d frame waits on the host for
+    // the tree's height
+    esk_status st = ESK_OK;
+    for (int pass = 0; pass < 2 && st == ESK_OK; ++pass)
+        for (int i = 0; i < n && st == ESK_OK; ++i) {
+            const bool kdf = accels[i] == ESK_ACCEL_KD || accels[i] == ESK_ACCEL_HYBRID;
+            if (kdf != (pass == 1)) continue;
+            hipStream_t s = sx[lane_of(accels[i])];
+            RenderArgs r;
+            st = prepare_render(c, accels[i], &cams[i], widths[i], heights[i], step, opacity_ref_step, d_outs[i],
+                                d_counts ? d_counts[i] : nullptr, r, s);
+            if (st == ESK_OK) st = hip_check(c, launch_render(accels[i], r, s), "render launch");
+        }
+    // join, also after a failed frame: the context's stream waits for every frame
+    for (int j = 1; j < 3; ++j) {
+        if (!used[j]) continue;
+        e = hipEventRecord(c->ev_join[j - 1], sx[j]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->ev_join[j - 1], 0);
+        if (e != hipSuccess && st == ESK_OK) st = hip_check(c, e, "render join");
+    }
+    return st;
+}
+
+esk_status esk_render_stream(esk_ctx *c, int accel, void **out)
+{
+    if (!c || !out) return ESK_EINVAL;
+    if (accel != ESK_ACCEL_NONE && accel != ESK_ACCEL_GRID && accel != ESK_ACCEL_LBVH && accel != ESK_ACCEL_KD &&
+        accel != ESK_ACCEL_HYBRID)
+        return fail(c, ESK_EINVAL, "unknown accel %d", accel);
+    if (c->device < 0) return fail(c, ESK_ESTATE, "validation-only context");
+    hipStream_t s = accel == ESK_ACCEL_LBVH ? c->aux2
+                    : (accel == ESK_ACCEL_KD || accel == ESK_ACCEL_HYBRID) ? c->aux
+                                                                           : c->stream;
+    *out = static_cast<void *>(s);
+    return ESK_OK;
 }
 
 esk_status esk_render_batch_bytes(int n, size_t *out)

@@ -123,6 +123,19 @@ def test_tf_and_render_validation():
     assert r(v.c, esk.LBVH, ctypes.byref(cam), 64, 64, 0.5, 1.0, FAKE, None) == esk.ESTATE
     assert r(v.c, esk.HYBRID, ctypes.byref(cam), 64, 64, 0.5, 1.0, FAKE, None) == esk.ESTATE
     assert r(v.c, 16, ctypes.byref(cam), 64, 64, 0.5, 1.0, FAKE, None) == esk.EINVAL
+    # several frames: counts, null arrays, then every frame's own checks
+    m = L.esk_render_multi
+    acc = (ctypes.c_int * 2)(esk.LBVH, esk.KD)
+    cams = (esk.Camera * 2)(cam, cam)
+    ws, hs = (ctypes.c_int * 2)(64, 64), (ctypes.c_int * 2)(64, 64)
+    outs = (ctypes.c_void_p * 2)(FAKE.value, FAKE.value + 65536)
+    assert m(v.c, 0, acc, cams, ws, hs, 0.5, 1.0, outs, None) == esk.EINVAL
+    assert m(v.c, 9, acc, cams, ws, hs, 0.5, 1.0, outs, None) == esk.EINVAL
+    assert m(v.c, 2, None, cams, ws, hs, 0.5, 1.0, outs, None) == esk.EINVAL
+    assert m(v.c, 2, acc, cams, ws, hs, 0.5, 1.0, None, None) == esk.EINVAL
+    assert m(v.c, 2, acc, cams, (ctypes.c_int * 2)(0, 64), hs, 0.5, 1.0, outs, None) == esk.EINVAL
+    assert m(v.c, 2, (ctypes.c_int * 2)(3, esk.LBVH), cams, ws, hs, 0.5, 1.0, outs, None) == esk.EINVAL
+    assert m(v.c, 2, acc, cams, ws, hs, 0.5, 1.0, outs, None) == esk.ESTATE
     assert L.esk_sync(v.c) == esk.ESTATE
     s = esk.Stats()
     assert L.esk_get_stats(v.c, ctypes.byref(s)) == esk.ESTATE

@@ -307,6 +307,38 @@ def test_kd_levels_wider_than_block_numbering():
         assert np.array_equal(img, full), kd
 
 
+def test_render_multi_equals_single_renders():
+    """esk_render_multi: each frame bit-identical to esk_render of the same
+    request (grid, LBVH, k-d, hybrid and the full march, counts included),
+    the frames of different structures running on different streams; read
+    back on the context's stream with no synchronisation of our own (the call
+    joins its frames), twice, with a rebuild between."""
+    torch = _torch()
+    dims = (96, 80, 72)
+    log(f"case: render_multi {dims} B=8")
+    vol = synth.blobs_u8(dims, seed=3, n_blobs=10, sigma=(4.0, 9.0), cut=40, centre_range=(0.1, 0.9))
+    esk, ctx = make_ctx()
+    ctx.set_volume(to_dev(vol), 8, (0.0, 1.0), max_tf=256)
+    W, H = 120, 90
+    for rnd, tf in enumerate((synth.tf_ramp(256, start=0.05), synth.tf_random(7, 256))):
+        ctx.set_tf(to_dev(tf), build=("grid", "lbvh", "kd"), kd=esk.Kd(1, 32, 4))
+        cam = synth.perspective(dims, W, H, synth.view_direction(rnd + 2))
+        accels = ("grid", "lbvh", "kd", "hybrid", "none")
+        frames = [dict(cam=cam, W=W, H=H, accel=a) for a in accels]
+        frames[1]["counts"] = torch.zeros((H, W), dtype=torch.int32, device="cuda")
+        frames[2]["counts"] = torch.zeros((H, W), dtype=torch.int32, device="cuda")
+        outs = ctx.render_multi(frames)
+        got = [o.cpu().numpy() for o in outs]
+        got_cnt = {i: frames[i]["counts"].cpu().numpy() for i in (1, 2)}
+        for i, a in enumerate(accels):
+            cnt = torch.zeros((H, W), dtype=torch.int32, device="cuda")
+            ref = ctx.render(cam, W, H, accel=a, counts=cnt).cpu().numpy()
+            assert np.array_equal(got[i], ref), (rnd, a)
+            if i in got_cnt:
+                assert np.array_equal(got_cnt[i], cnt.cpu().numpy()), (rnd, a)
+        assert np.array_equal(got[0], got[4]) and np.array_equal(got[1], got[4]), rnd
+
+
 def test_rebuild_is_deterministic():
     w = synth.c1_workload()
     esk, ctx = make_ctx()
