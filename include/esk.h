@@ -261,7 +261,10 @@ esk_status esk_render(esk_ctx *ctx, int accel, const esk_camera *cam, int width,
  * three streams (the context's internal build streams and its own), so the
  * kernels of different structures overlap; every frame is complete on the
  * context's stream when the work enqueued after this call runs, as after n
- * esk_render calls.  Frames must not share an output.  n in [1,
+ * esk_render calls.  The frames that need no k-d tree are enqueued first;
+ * a k-d or hybrid frame follows once the host has seen the k-d build finish
+ * (its height sizes the traversal stack, as in esk_render), while the others
+ * already run.  Frames must not share an output.  n in [1,
  * ESK_RENDER_MULTI_MAX].  All frames are checked before any is enqueued; a
  * frame failing after the checks (a device error, a k-d tree too tall)
  * leaves the frames before it enqueued and joined. */
