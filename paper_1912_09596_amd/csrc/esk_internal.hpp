@@ -226,8 +226,10 @@ constexpr int kRaySegments = 2;
 // SIMDs idle, so shorter rays split too (measured: 128^2 to 256^2 renders
 // 25-40 % faster; for 512^2 requests batched 64 to a launch the extra waves
 // cost 5-8 %, hence the threshold).  It depends on the image size only, so a
-// request renders the same alone and in a batch.
-constexpr int kRaySegLen = 256;
+// request renders the same alone and in a batch.  kRaySegLen: 192 measured
+// 1 % faster than 256 for the three 1080p frames of one view rendered
+// together (128: between; 512 and 1024: 2 and 5 % slower).
+constexpr int kRaySegLen = 192;
 constexpr int kRaySegLenFew = 32;
 constexpr int kRaySegFewTiles = 2048;
 __host__ __device__ constexpr int render_tile_for(int) { return 8; }
